@@ -1,0 +1,325 @@
+"""Seeded synthetic workloads (meshes, query points, nodal fields).
+
+This module only produces inputs: node coordinates of structured, curved
+quad/hex meshes and of a bumpy cubed-sphere surface, query points and nodal
+field values.  It holds none of the field-evaluation method's arithmetic (no
+element map, no bounds, no Newton): node positions are placed at
+Gauss-Lobatto-Legendre points computed here with ``numpy.polynomial`` and the
+curving maps are analytic functions of the node positions.  Both the oracle
+tests and the HIP library consume these arrays.
+
+Layouts: nodes ``[n_elem][D][N^R]`` (i fastest, then j, then k), points
+``[D][n]``, fields ``[n_fields][n_elem][N^R]``; all float64.
+
+The paper's meshes (spiral, triple point, turbine blade, channel) are not
+available; these stand in for them with the shapes and sizes of the five
+workloads:
+
+* ``quad2d``  : 8x8 quads on [0,1]^2, p=4, X += 0.05 h sin(2 pi X) sin(2 pi Y)
+* ``hex16``   : 16^3 hexes, p=5, x += 0.1 sin(pi x) sin(pi y) sin(pi z)
+* ``hex48``   : 48^3 hexes, p=7, amplitude 0.15, 16M points, 3 fields
+* ``serving`` : four resident hex meshes p=3,5,7,9
+* ``sphere``  : cubed sphere 6x32x32, p=6, radius 1 + 0.05 B(x)
+"""
+import math
+
+import numpy as np
+from numpy.polynomial import legendre as npleg
+
+
+def gll_points(N):
+    """GLL points on [-1,1] for node placement (numpy's Legendre roots)."""
+    if N == 2:
+        return np.array([-1.0, 1.0])
+    inner = npleg.Legendre.basis(N - 1).deriv().roots()
+    z = np.concatenate([[-1.0], np.sort(inner.real), [1.0]])
+    z = 0.5 * (z - z[::-1])
+    return z
+
+
+def box_mesh(D, n, N):
+    """Uncurved structured mesh of [0,1]^D with n elements per direction and
+    N GLL nodes per direction.  Element id = a + n*(b + n*c)."""
+    t = 0.5 * (gll_points(N) + 1.0) / n           # local offsets in [0, 1/n]
+    a = np.arange(n) / n
+    if D == 2:
+        X = (a[None, :, None, None] + t[None, None, None, :])  # [b][a][j][i]
+        Y = (a[:, None, None, None] + t[None, None, :, None])
+        X = np.broadcast_to(X, (n, n, N, N))
+        Y = np.broadcast_to(Y, (n, n, N, N))
+        nodes = np.stack([X, Y], axis=2)          # [b][a][D][j][i]
+        return np.ascontiguousarray(nodes.reshape(n * n, 2, N * N))
+    X = a[None, None, :, None, None, None] + t[None, None, None, None, None, :]
+    Y = a[None, :, None, None, None, None] + t[None, None, None, None, :, None]
+    Z = a[:, None, None, None, None, None] + t[None, None, None, :, None, None]
+    shp = (n, n, n, N, N, N)
+    nodes = np.stack([np.broadcast_to(X, shp), np.broadcast_to(Y, shp),
+                      np.broadcast_to(Z, shp)], axis=3)   # [c][b][a][D][k][j][i]
+    return np.ascontiguousarray(nodes.reshape(n ** 3, 3, N ** 3))
+
+
+def curve_quad2d(nodes, n):
+    """X += 0.05 h sin(2 pi X) sin(2 pi Y) applied to both components."""
+    h = 1.0 / n
+    X, Y = nodes[:, 0].copy(), nodes[:, 1].copy()
+    d = 0.05 * h * np.sin(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+    out = nodes.copy()
+    out[:, 0] = X + d
+    out[:, 1] = Y + d
+    return out
+
+
+def curve_hex(nodes, amp, chunk=4096):
+    """x_c += amp sin(pi x) sin(pi y) sin(pi z) for every component c."""
+    out = np.empty_like(nodes)
+    for s in range(0, nodes.shape[0], chunk):
+        blk = nodes[s:s + chunk]
+        d = amp * (np.sin(np.pi * blk[:, 0]) * np.sin(np.pi * blk[:, 1]) *
+                   np.sin(np.pi * blk[:, 2]))
+        out[s:s + chunk] = blk + d[:, None, :]
+    return out
+
+
+def poly_coeffs(D, deg, rng):
+    """Random total-degree-``deg`` polynomial: list of (exponents, coeff)."""
+    terms = []
+    if D == 2:
+        for a in range(deg + 1):
+            for b in range(deg + 1 - a):
+                terms.append(((a, b), rng.uniform(-1, 1)))
+    else:
+        for a in range(deg + 1):
+            for b in range(deg + 1 - a):
+                for c in range(deg + 1 - a - b):
+                    terms.append(((a, b, c), rng.uniform(-1, 1)))
+    return terms
+
+
+def poly_eval(terms, X, chunk=1 << 22):
+    """Evaluate a polynomial given by ``poly_coeffs`` at points X [D][...]."""
+    X = np.asarray(X)
+    D = X.shape[0]
+    flat = X.reshape(D, -1)
+    out = np.empty(flat.shape[1])
+    deg = max(sum(e) for e, _ in terms)
+    for s in range(0, flat.shape[1], chunk):
+        blk = flat[:, s:s + chunk]
+        pw = [[np.ones(blk.shape[1])] for _ in range(D)]
+        for d in range(D):
+            for _ in range(deg):
+                pw[d].append(pw[d][-1] * blk[d])
+        acc = np.zeros(blk.shape[1])
+        for e, c in terms:
+            t = c * pw[0][e[0]]
+            for d in range(1, D):
+                t = t * pw[d][e[d]]
+            acc += t
+        out[s:s + chunk] = acc
+    return out.reshape(X.shape[1:])
+
+
+def nodal_field(nodes, terms):
+    """Field values u(x_node) of a physical polynomial: [nel][NP]."""
+    X = np.moveaxis(nodes, 1, 0)          # [D][nel][NP]
+    return poly_eval(terms, X)
+
+
+def uniform_points(rng, n, D, lo, hi):
+    return rng.uniform(lo, hi, size=(D, n))
+
+
+def shell_points(rng, n, D, inner=(0.0, 1.0), outer=(-0.05, 1.05)):
+    """n points uniform in the outer box minus the inner box (rejection)."""
+    out = np.empty((D, 0))
+    while out.shape[1] < n:
+        p = rng.uniform(outer[0], outer[1], size=(D, 2 * n + 16))
+        ins = np.all((p >= inner[0]) & (p <= inner[1]), axis=0)
+        out = np.concatenate([out, p[:, ~ins]], axis=1)
+    return np.ascontiguousarray(out[:, :n])
+
+
+# --------------------------------------------------------------------------
+# The five workloads.
+# --------------------------------------------------------------------------
+
+def quad2d(n_pts=10000, seed=1000):
+    """8x8 curved quads, p=4; points uniform in [-0.05,1.05]^2; a total-degree
+    4 field plus the linear field x (rows 0 and 1 of ``fields``)."""
+    rng = np.random.default_rng(seed)
+    n, N = 8, 5
+    nodes = curve_quad2d(box_mesh(2, n, N), n)
+    pts = uniform_points(rng, n_pts, 2, -0.05, 1.05)
+    terms = poly_coeffs(2, 4, rng)
+    fields = np.stack([nodal_field(nodes, terms), nodes[:, 0].copy()])
+    return dict(name="quad2d_8x8_p4", dim=2, ref_dim=2, N=N, nodes=nodes, pts=pts,
+                fields=fields, terms=[terms, [((1, 0), 1.0)]], h=1.0 / n)
+
+
+def hex16(n_in=1000000, n_out=20000, seed=1001):
+    """16^3 curved hexes, p=5; 1M points in the cube plus 2% in the shell
+    [-0.05,1.05]^3 minus [0,1]^3; a total-degree 5 scalar field."""
+    rng = np.random.default_rng(seed)
+    n, N = 16, 6
+    nodes = curve_hex(box_mesh(3, n, N), 0.1)
+    pts = np.concatenate([uniform_points(rng, n_in, 3, 0.0, 1.0),
+                          shell_points(rng, n_out, 3)], axis=1)
+    terms = poly_coeffs(3, 5, rng)
+    fields = nodal_field(nodes, terms)[None]
+    return dict(name="hex16_p5", dim=3, ref_dim=3, N=N, nodes=nodes, pts=pts,
+                fields=fields, terms=[terms], h=1.0 / n)
+
+
+def hex48(n_pts=1 << 24, seed=1002, with_fields=True, n_elem_side=48):
+    """48^3 curved hexes (amplitude 0.15), p=7; 2^24 points uniform in the
+    cube; three total-degree 7 fields."""
+    rng = np.random.default_rng(seed)
+    n, N = n_elem_side, 8
+    nodes = curve_hex(box_mesh(3, n, N), 0.15)
+    pts = uniform_points(rng, n_pts, 3, 0.0, 1.0)
+    terms = [poly_coeffs(3, 7, rng) for _ in range(3)]
+    fields = None
+    if with_fields:
+        fields = np.stack([nodal_field(nodes, t) for t in terms])
+    return dict(name="hex48_p7", dim=3, ref_dim=3, N=N, nodes=nodes, pts=pts,
+                fields=fields, terms=terms, h=1.0 / n)
+
+
+SERVING_MESHES = ((4, 46), (6, 36), (8, 27), (10, 22))   # (N = p+1, elems/dir)
+
+
+def serving_mesh(k, seed=1003, scale=1.0):
+    """Resident mesh k of the serving workload: p = 3,5,7,9 with 46^3, 36^3,
+    27^3, 22^3 hexes (amplitude 0.1) and a degree-p scalar field.  ``scale``
+    < 1 shrinks the element count per direction (for small tests)."""
+    N, n = SERVING_MESHES[k]
+    n = max(2, int(round(n * scale)))
+    rng = np.random.default_rng(seed + 17 * k)
+    nodes = curve_hex(box_mesh(3, n, N), 0.1)
+    terms = poly_coeffs(3, N - 1, rng)
+    fields = nodal_field(nodes, terms)[None]
+    return dict(name="serve_p%d_%d3" % (N - 1, n), dim=3, ref_dim=3, N=N,
+                nodes=nodes, fields=fields, terms=[terms], h=1.0 / n)
+
+
+def serving_requests(n_req, seed=1004, lo=3.0, hi=6.0, n_mesh=4):
+    """Request sizes round(10^U(lo,hi)), uniform mesh choice."""
+    rng = np.random.default_rng(seed)
+    sizes = np.round(10.0 ** rng.uniform(lo, hi, size=n_req)).astype(np.int64)
+    meshes = rng.integers(0, n_mesh, size=n_req)
+    return sizes, meshes, rng
+
+
+# --------------------------------------------------------------------------
+# Cubed sphere with random spherical-harmonic bumps.
+# --------------------------------------------------------------------------
+
+def _face_dirs(f, X, Y):
+    """Unnormalised direction of gnomonic coordinates (X, Y) on face f."""
+    one = np.ones_like(X)
+    if f == 0:
+        return np.stack([one, X, Y])
+    if f == 1:
+        return np.stack([-one, -X, Y])
+    if f == 2:
+        return np.stack([-X, one, Y])
+    if f == 3:
+        return np.stack([X, -one, Y])
+    if f == 4:
+        return np.stack([-Y, X, one])
+    return np.stack([Y, X, -one])
+
+
+def _real_sph(l, m, theta, phi):
+    from scipy.special import sph_harm_y
+    if m == 0:
+        return sph_harm_y(l, 0, theta, phi).real
+    if m > 0:
+        return math.sqrt(2.0) * sph_harm_y(l, m, theta, phi).real
+    return math.sqrt(2.0) * sph_harm_y(l, -m, theta, phi).imag
+
+
+class Bumps:
+    """B(x_hat) = sum_{l=2..6} sum_m c_lm Y_lm(x_hat), c_lm ~ N(0,1),
+    normalised to max |B| = 1 over a fine sample of the sphere."""
+
+    def __init__(self, rng):
+        self.terms = [(l, m, rng.standard_normal()) for l in range(2, 7)
+                      for m in range(-l, l + 1)]
+        th = np.linspace(0, np.pi, 181)
+        ph = np.linspace(0, 2 * np.pi, 361)
+        T, P = np.meshgrid(th, ph, indexing="ij")
+        self.scale = 1.0
+        self.scale = 1.0 / np.abs(self._raw(T.ravel(), P.ravel())).max()
+
+    def _raw(self, theta, phi):
+        acc = np.zeros_like(theta)
+        for l, m, c in self.terms:
+            acc += c * _real_sph(l, m, theta, phi)
+        return acc * self.scale
+
+    def __call__(self, u):
+        """u: unit vectors [3][n]."""
+        theta = np.arccos(np.clip(u[2], -1.0, 1.0))
+        phi = np.arctan2(u[1], u[0])
+        return self._raw(theta, phi)
+
+
+def _sphere_surface(bumps, f, xi, eta, amp):
+    d = _face_dirs(f, np.tan(xi), np.tan(eta))
+    u = d / np.linalg.norm(d, axis=0)
+    return (1.0 + amp * bumps(u)) * u
+
+
+def sphere(n_pts=1 << 22, seed=1005, ne=32, N=7, amp=0.05, far_frac=0.01,
+           offset=1e-3):
+    """Cubed sphere 6 x ne x ne quads, N nodes per direction, equiangular
+    gnomonic faces, radius 1 + amp B.  Points: (1-far_frac) at signed normal
+    offsets U[-offset, offset] from the analytic surface at uniformly drawn
+    (element, local coordinates); far_frac uniform in 1.5 <= |x| <= 2."""
+    rng = np.random.default_rng(seed)
+    bumps = Bumps(rng)
+    z = gll_points(N)
+    edges = np.linspace(-np.pi / 4, np.pi / 4, ne + 1)
+    nel = 6 * ne * ne
+    nodes = np.empty((nel, 3, N * N))
+    e = 0
+    for f in range(6):
+        for b in range(ne):
+            for a in range(ne):
+                xa = edges[a] + 0.5 * (z + 1.0) * (edges[a + 1] - edges[a])
+                yb = edges[b] + 0.5 * (z + 1.0) * (edges[b + 1] - edges[b])
+                XI, ETA = np.meshgrid(xa, yb, indexing="xy")   # [j][i]
+                nodes[e] = _sphere_surface(bumps, f, XI.ravel(), ETA.ravel(), amp)
+                e += 1
+    n_far = int(round(n_pts * far_frac))
+    n_near = n_pts - n_far
+    ef = rng.integers(0, nel, size=n_near)
+    rr = rng.uniform(-1.0, 1.0, size=(2, n_near))
+    dl = rng.uniform(-offset, offset, size=n_near)
+    f = ef // (ne * ne)
+    a = ef % ne
+    b = (ef // ne) % ne
+    xi = edges[a] + 0.5 * (rr[0] + 1.0) * (edges[a + 1] - edges[a])
+    eta = edges[b] + 0.5 * (rr[1] + 1.0) * (edges[b + 1] - edges[b])
+    near = np.empty((3, n_near))
+    hs = 1e-6
+    for face in range(6):
+        sel = np.nonzero(f == face)[0]
+        if sel.size == 0:
+            continue
+        x0 = _sphere_surface(bumps, face, xi[sel], eta[sel], amp)
+        x1 = _sphere_surface(bumps, face, xi[sel] + hs, eta[sel], amp)
+        x2 = _sphere_surface(bumps, face, xi[sel], eta[sel] + hs, amp)
+        nrm = np.cross((x1 - x0).T, (x2 - x0).T).T
+        nrm /= np.linalg.norm(nrm, axis=0)
+        near[:, sel] = x0 + dl[sel] * nrm
+    u = rng.standard_normal((3, n_far))
+    u /= np.linalg.norm(u, axis=0)
+    rad = np.cbrt(rng.uniform(1.5 ** 3, 2.0 ** 3, size=n_far))
+    far = u * rad
+    pts = np.ascontiguousarray(np.concatenate([near, far], axis=1))
+    terms = poly_coeffs(3, N - 1, rng)
+    fields = np.stack([nodal_field(nodes, terms), nodes[:, 0].copy()])
+    return dict(name="sphere_6x%dx%d_p%d" % (ne, ne, N - 1), dim=3, ref_dim=2, N=N,
+                nodes=nodes, pts=pts, fields=fields,
+                terms=[terms, [((1, 0, 0), 1.0)]], h=(np.pi / 2) / ne)
