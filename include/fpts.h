@@ -1,0 +1,174 @@
+/*
+ * fpts -- general field evaluation ("findpts") on high-order quad, hex and
+ * surface meshes, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Mittal, Parik, Dutta, Fischer, Kolev, Lottes, "General Field
+ * Evaluation in High-Order Meshes on GPUs", arXiv 2501.12349.  This library
+ * implements the processor-local path: Setup (Section 3.1, surface variants
+ * Section 4.1-4.3), Find (Section 3.2, 3.2.1, 4.4) and Interpolate (Section
+ * 3.3).  The multi-rank global map of Section 3.1.4 is not part of it.
+ *
+ * Conventions shared by every entry point
+ *  - Status: 0 on success, a negative FPTS_E* value on error.  Errors never
+ *    abort the process.  Invalid point coordinates (NaN, Inf, far away) are
+ *    data, not errors: such points come back NOT_FOUND.
+ *  - Pointers named d_* are device memory owned by the caller.  Every call
+ *    only enqueues work on `stream` (a hipStream_t, NULL = default stream)
+ *    and returns; the caller keeps the buffers alive until the stream has
+ *    drained.  Host pointers (h_*) are read before the call returns.
+ *  - All floating point data is IEEE double unless stated otherwise.
+ *  - A mesh handle is read-only after setup.  Calls on one mesh from several
+ *    streams may overlap as long as each call has its own workspace.
+ */
+#ifndef FPTS_H
+#define FPTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Point codes c* of the computational coordinates (Section 3.2). */
+enum {
+    FPTS_INTERIOR = 0,   /* r* inside the open reference box (and, for
+                            surfaces, squared distance below eps_d) */
+    FPTS_BORDER = 1,     /* in some element's boxes, not interior to any:
+                            closest point of the best element */
+    FPTS_NOT_FOUND = 2   /* outside the boxes of every element */
+};
+
+/* Status codes. */
+enum {
+    FPTS_OK = 0,
+    FPTS_EINVAL = -1,    /* bad argument (dimension, order, null pointer,
+                            size out of range, workspace too small) */
+    FPTS_ENOMEM = -2,    /* host or device allocation failed */
+    FPTS_EDEVICE = -3,   /* HIP error (launch failure, sticky error, no
+                            device) */
+    FPTS_EUNSUPPORTED = -4 /* valid request this build has no kernel for */
+};
+
+/* Newton precision of fpts_find. */
+enum {
+    FPTS_FP64 = 0,       /* every Newton pass in FP64 (the method as given) */
+    FPTS_MIXED = 1       /* FP32 passes in element-local coordinates, then
+                            FP64 passes from the FP32 result; boxes, codes,
+                            distances and the final residual are FP64 */
+};
+
+/* Setup parameters (Section 3.1).  Zero-initialise, then set fields;
+ * fpts_params_default fills the paper's defaults. */
+typedef struct fpts_params {
+    int dim;            /* D, space dimension: 2 or 3 */
+    int ref_dim;        /* D_r: dim (quad/hex mesh) or 2 with dim 3 (surface
+                           quads) */
+    int nodes_1d;       /* N = p + 1 GLL nodes per direction, 2..10 */
+    int hash_n;         /* N_L cells per direction of the local map; 0 picks
+                           the smallest n with n^D >= n_elem (Section 3.1.3) */
+    int64_t n_elem;     /* number of elements, >= 1 */
+    double bbox_tol;    /* box expansion, fraction of the extent added in
+                           total (Section 3.1.1 default 0.1) */
+    double surf_eps_d;  /* surface INTERIOR threshold on the squared distance
+                           (Section 4.4 default 1e-10) */
+    int max_iter;       /* Newton passes per candidate (Section 3.2.1: 50) */
+    double newton_tol;  /* stop when ||dr||_inf < newton_tol (1e-10) */
+} fpts_params;
+
+typedef struct fpts_mesh fpts_mesh;
+
+/* Fill p with the paper's defaults for (dim, ref_dim, nodes_1d, n_elem). */
+void fpts_params_default(fpts_params *p, int dim, int ref_dim, int nodes_1d,
+                         int64_t n_elem);
+
+/* Setup (Section 3.1, 4.1-4.3).  h_nodes: host array
+ * [n_elem][dim][nodes_1d^ref_dim] of node coordinates, the first reference
+ * index fastest (node (i,j,k) at i + N j + N^2 k).  Builds the basis and
+ * bound tables, every element's axis-aligned and oriented bounding box and
+ * the local Cartesian map on the host, then copies nodes, boxes and map to
+ * the current HIP device on `stream` and waits for the copies.  The caller
+ * keeps ownership of h_nodes.  On success *out receives a handle to release
+ * with fpts_destroy.  FPTS_EINVAL for bad params, FPTS_ENOMEM, FPTS_EDEVICE. */
+int fpts_setup(const fpts_params *p, const double *h_nodes, void *stream,
+               fpts_mesh **out);
+
+/* Release every host and device resource of the mesh (synchronises the
+ * device first).  NULL is accepted. */
+int fpts_destroy(fpts_mesh *m);
+
+/* Bytes of device workspace fpts_find needs for n points (an upper bound
+ * that assumes every point hits the largest cell of the local map), or 0
+ * when n is out of range. */
+size_t fpts_find_workspace_size(const fpts_mesh *m, int64_t n);
+
+/* Find (Section 3.2, 3.2.1, 4.4): computational coordinates of n points.
+ *   d_pts   [dim][n]     query coordinates (SoA)
+ *   d_code  [n]  int32   FPTS_INTERIOR / FPTS_BORDER / FPTS_NOT_FOUND
+ *   d_elem  [n]  int32   element id, -1 when NOT_FOUND
+ *   d_r     [ref_dim][n] reference coordinates r* (0 when NOT_FOUND)
+ *   d_dist  [n]          ||x* - x(r*)||_2 (+inf when NOT_FOUND)
+ *   precision            FPTS_FP64 or FPTS_MIXED
+ *   d_ws, ws_bytes       device workspace of at least
+ *                        fpts_find_workspace_size(m, n) bytes, 256-byte
+ *                        aligned; its contents need no initialisation
+ * Candidates of a point are the elements of its cell whose boxes contain it;
+ * each is searched with trust-region Newton; the lowest-id INTERIOR
+ * candidate wins, else the one at the smallest distance (lowest id on ties).
+ * n == 0 is a no-op.  FPTS_EINVAL on null pointers, n < 0, n above 2^31-1,
+ * or a workspace that is too small. */
+int fpts_find(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code,
+              int32_t *d_elem, double *d_r, double *d_dist, int precision,
+              void *d_ws, size_t ws_bytes, void *stream);
+
+/* Bytes of device workspace fpts_eval needs for n points. */
+size_t fpts_eval_workspace_size(const fpts_mesh *m, int64_t n);
+
+/* Interpolate (Section 3.3, eq. eq_u_tensor with the geometry's N):
+ * out[f][p] = sum over element nodes of field[f][elem[p]][node] times the
+ * tensor Lagrange bases at r[p], for n_fields fields given as
+ *   d_field [n_fields][n_elem][nodes_1d^ref_dim],
+ * from the outputs of fpts_find (d_code, d_elem, d_r as documented there).
+ * NOT_FOUND points get NaN.  Points are grouped by element on the device so
+ * that each element's nodal values are read once.  FPTS_EINVAL on null
+ * pointers, n_fields < 1, bad n or a too small workspace. */
+int fpts_eval(fpts_mesh *m, int64_t n, const int32_t *d_code,
+              const int32_t *d_elem, const double *d_r, int n_fields,
+              const double *d_field, double *d_out, void *d_ws,
+              size_t ws_bytes, void *stream);
+
+/* Counters of the last fpts_find that used workspace d_ws (read back with a
+ * device-to-host copy on `stream`, which is synchronised).  Filled:
+ * candidate pairs searched, Newton passes, map evaluations with and without
+ * second derivatives, FP32 passes (mixed mode). */
+typedef struct fpts_find_stats {
+    int64_t pairs;
+    int64_t passes;
+    int64_t evals;          /* map evaluations including the initial ones */
+    int64_t evals_h2;       /* of which with second derivatives */
+    int64_t passes_fp32;    /* FP32 passes of mixed mode */
+    int64_t evals_fp32;     /* FP32 map evaluations of mixed mode */
+} fpts_find_stats;
+
+int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws,
+                        fpts_find_stats *out, void *stream);
+
+/* Read-only views of setup products, for tests and tools: copies to host
+ * arrays sized [n_elem][dim][2] (AABB lo/hi), [n_elem][dim][dim] (OBB
+ * inverse transform) and [n_elem][dim] (OBB centre).  Any pointer may be
+ * NULL. */
+int fpts_get_boxes(const fpts_mesh *m, double *h_aabb, double *h_obb_A,
+                   double *h_obb_c);
+
+/* Local map description: h_lo[dim], h_hi[dim], h_delta[dim]; returns N_L in
+ * *hash_n, cell list entries in *nnz and the largest cell in *max_cell. */
+int fpts_get_hash(const fpts_mesh *m, double *h_lo, double *h_hi,
+                  double *h_delta, int *hash_n, int64_t *nnz, int *max_cell);
+
+/* Text of a status code. */
+const char *fpts_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FPTS_H */

@@ -1,0 +1,363 @@
+// C-ABI entry points of the fpts library: argument checks, workspace layout
+// and the enqueue order of the kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "fpts_internal.hpp"
+
+using namespace fpts;
+
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Cursor {
+    size_t at = 0;
+    size_t take(size_t bytes)
+    {
+        size_t o = at;
+        at = align_up(at + std::max<size_t>(bytes, 1));
+        return o;
+    }
+};
+
+bool sticky_error()
+{
+    hipError_t e = hipGetLastError();
+    return e != hipSuccess;
+}
+
+template <class T>
+T *at(void *base, size_t off)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(base) + off);
+}
+
+constexpr int kCounters = 64;   // ints: task counters
+constexpr int kStats = 8;       // unsigned long long
+
+void free_mesh(fpts_mesh *m)
+{
+    if (!m) return;
+    hipFree(m->d_nodes);
+    hipFree(m->d_nodes32);
+    hipFree(m->d_xc);
+    hipFree(m->d_box);
+    hipFree(m->d_cell_off);
+    hipFree(m->d_cell_el);
+    delete m;
+}
+
+}  // namespace
+
+namespace fpts {
+
+FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
+{
+    FindWs w;
+    Cursor c;
+    w.cap = std::max<int64_t>(1, n * (int64_t)std::max(m->max_cell, 1));
+    w.scan_blocks = scan_tmp_blocks(std::max<int64_t>(n, m->nel));
+    w.pt_off = c.take(sizeof(int) * (n + 1));
+    w.elem_cnt = c.take(sizeof(int) * m->nel);
+    w.elem_off = c.take(sizeof(int) * (m->nel + 1));
+    w.elem_fill = c.take(sizeof(int) * m->nel);
+    w.chunk_off = c.take(sizeof(int) * (m->nel + 1));
+    w.scan_tmp = c.take(sizeof(int) * w.scan_blocks);
+    w.slot_pt = c.take(sizeof(int) * w.cap);
+    w.slot_elem = c.take(sizeof(int) * w.cap);
+    w.sorted = c.take(sizeof(int) * w.cap);
+    w.res_r = c.take(sizeof(double) * m->R * w.cap);
+    w.res_dist = c.take(sizeof(double) * w.cap);
+    w.res_code = c.take(sizeof(int) * w.cap);
+    w.counters = c.take(sizeof(int) * kCounters);
+    w.stats = c.take(sizeof(unsigned long long) * kStats);
+    w.total = c.at;
+    return w;
+}
+
+EvalWs eval_ws_layout(const fpts_mesh *m, int64_t n)
+{
+    EvalWs w;
+    Cursor c;
+    w.elem_cnt = c.take(sizeof(int) * m->nel);
+    w.elem_off = c.take(sizeof(int) * (m->nel + 1));
+    w.elem_fill = c.take(sizeof(int) * m->nel);
+    w.chunk_off = c.take(sizeof(int) * (m->nel + 1));
+    w.scan_tmp = c.take(sizeof(int) * scan_tmp_blocks(m->nel));
+    w.sorted = c.take(sizeof(int) * std::max<int64_t>(n, 1));
+    w.counters = c.take(sizeof(int) * kCounters);
+    w.total = c.at;
+    return w;
+}
+
+}  // namespace fpts
+
+extern "C" {
+
+void fpts_params_default(fpts_params *p, int dim, int ref_dim, int nodes_1d, int64_t n_elem)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->dim = dim;
+    p->ref_dim = ref_dim;
+    p->nodes_1d = nodes_1d;
+    p->n_elem = n_elem;
+    p->hash_n = 0;
+    p->bbox_tol = 0.1;
+    p->surf_eps_d = 1e-10;
+    p->max_iter = 50;
+    p->newton_tol = 1e-10;
+}
+
+const char *fpts_status_string(int s)
+{
+    switch (s) {
+    case FPTS_OK: return "ok";
+    case FPTS_EINVAL: return "invalid argument";
+    case FPTS_ENOMEM: return "out of memory";
+    case FPTS_EDEVICE: return "HIP device error";
+    case FPTS_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+    }
+}
+
+int fpts_setup(const fpts_params *p, const double *h_nodes, void *stream, fpts_mesh **out)
+{
+    if (!p || !h_nodes || !out) return FPTS_EINVAL;
+    *out = nullptr;
+    const bool vol = p->ref_dim == p->dim && (p->dim == 2 || p->dim == 3);
+    const bool surf = p->dim == 3 && p->ref_dim == 2;
+    if (!(vol || surf)) return FPTS_EINVAL;
+    if (p->nodes_1d < 2 || p->nodes_1d > kMaxN) return FPTS_EINVAL;
+    if (p->n_elem < 1 || p->n_elem > INT32_MAX / 2) return FPTS_EINVAL;
+    if (!(p->bbox_tol >= 0.0) || !(p->newton_tol > 0.0) || p->max_iter < 1 ||
+        p->max_iter > 1000 || !(p->surf_eps_d >= 0.0) || p->hash_n < 0)
+        return FPTS_EINVAL;
+    if (sticky_error()) return FPTS_EDEVICE;
+    fpts_mesh *m = new (std::nothrow) fpts_mesh();
+    if (!m) return FPTS_ENOMEM;
+    m->p = *p;
+    m->D = p->dim;
+    m->R = p->ref_dim;
+    m->N = p->nodes_1d;
+    m->NP = m->R == 3 ? m->N * m->N * m->N : m->N * m->N;
+    m->nel = p->n_elem;
+    if (hipGetDevice(&m->device) != hipSuccess ||
+        hipDeviceGetAttribute(&m->cus, hipDeviceAttributeMultiprocessorCount, m->device) !=
+            hipSuccess) {
+        delete m;
+        return FPTS_EDEVICE;
+    }
+    int st;
+    try {
+        st = host_setup(m, h_nodes);
+    } catch (const std::bad_alloc &) {
+        st = FPTS_ENOMEM;
+    }
+    if (st != FPTS_OK) {
+        delete m;
+        return st;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nn = (size_t)m->nel * m->D * m->NP;
+    const size_t nb = m->box.size(), nx = m->xc.size();
+    bool ok = hipMalloc(&m->d_nodes, sizeof(double) * nn) == hipSuccess &&
+              hipMalloc(&m->d_nodes32, sizeof(float) * nn) == hipSuccess &&
+              hipMalloc(&m->d_xc, sizeof(double) * nx) == hipSuccess &&
+              hipMalloc(&m->d_box, sizeof(double) * nb) == hipSuccess &&
+              hipMalloc(&m->d_cell_off, sizeof(int) * m->cell_off.size()) == hipSuccess &&
+              hipMalloc(&m->d_cell_el, sizeof(int) * m->cell_el.size()) == hipSuccess;
+    if (!ok) {
+        hipGetLastError();
+        free_mesh(m);
+        return FPTS_ENOMEM;
+    }
+    ok = hipMemcpyAsync(m->d_nodes, h_nodes, sizeof(double) * nn, hipMemcpyHostToDevice, s) ==
+             hipSuccess &&
+         hipMemcpyAsync(m->d_xc, m->xc.data(), sizeof(double) * nx, hipMemcpyHostToDevice, s) ==
+             hipSuccess &&
+         hipMemcpyAsync(m->d_box, m->box.data(), sizeof(double) * nb, hipMemcpyHostToDevice,
+                        s) == hipSuccess &&
+         hipMemcpyAsync(m->d_cell_off, m->cell_off.data(), sizeof(int) * m->cell_off.size(),
+                        hipMemcpyHostToDevice, s) == hipSuccess &&
+         hipMemcpyAsync(m->d_cell_el, m->cell_el.data(), sizeof(int) * m->cell_el.size(),
+                        hipMemcpyHostToDevice, s) == hipSuccess &&
+         launch_nodes32(m, s) == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
+        hipGetLastError();
+        free_mesh(m);
+        return FPTS_EDEVICE;
+    }
+    *out = m;
+    return FPTS_OK;
+}
+
+int fpts_destroy(fpts_mesh *m)
+{
+    if (!m) return FPTS_OK;
+    hipDeviceSynchronize();
+    free_mesh(m);
+    return FPTS_OK;
+}
+
+size_t fpts_find_workspace_size(const fpts_mesh *m, int64_t n)
+{
+    if (!m || n < 0 || n > INT32_MAX - 1) return 0;
+    FindWs w = find_ws_layout(m, n);
+    if (w.cap > INT32_MAX) return 0;
+    return w.total;
+}
+
+int fpts_find(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int32_t *d_elem,
+              double *d_r, double *d_dist, int precision, void *d_ws, size_t ws_bytes,
+              void *stream)
+{
+    if (!m || n < 0 || n > INT32_MAX - 1) return FPTS_EINVAL;
+    if (precision != FPTS_FP64 && precision != FPTS_MIXED) return FPTS_EINVAL;
+    if (n == 0) return FPTS_OK;
+    if (!d_pts || !d_code || !d_elem || !d_r || !d_dist || !d_ws) return FPTS_EINVAL;
+    if (((uintptr_t)d_ws & 255) != 0) return FPTS_EINVAL;
+    const FindWs w = find_ws_layout(m, n);
+    if (w.cap > INT32_MAX || ws_bytes < w.total) return FPTS_EINVAL;
+    if (sticky_error()) return FPTS_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    int *pt_off = at<int>(d_ws, w.pt_off);
+    int *elem_cnt = at<int>(d_ws, w.elem_cnt);
+    int *elem_off = at<int>(d_ws, w.elem_off);
+    int *elem_fill = at<int>(d_ws, w.elem_fill);
+    int *chunk_off = at<int>(d_ws, w.chunk_off);
+    int *tmp = at<int>(d_ws, w.scan_tmp);
+    int *slot_pt = at<int>(d_ws, w.slot_pt);
+    int *slot_elem = at<int>(d_ws, w.slot_elem);
+    int *sorted = at<int>(d_ws, w.sorted);
+    double *res_r = at<double>(d_ws, w.res_r);
+    double *res_dist = at<double>(d_ws, w.res_dist);
+    int *res_code = at<int>(d_ws, w.res_code);
+    int *counters = at<int>(d_ws, w.counters);
+    unsigned long long *stats = at<unsigned long long>(d_ws, w.stats);
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+    };
+    chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
+    chk(launch_fill_i32(elem_fill, m->nel, 0, s));
+    chk(launch_fill_i32(counters, kCounters, 0, s));
+    chk(launch_fill_i32(reinterpret_cast<int *>(stats), 2 * kStats, 0, s));
+    chk(launch_locate(m, 0, n, d_pts, pt_off, elem_cnt, nullptr, nullptr, nullptr, nullptr,
+                      nullptr, s));
+    chk(launch_exclusive_scan(pt_off, pt_off, n, 1, tmp, w.scan_blocks, s));
+    chk(launch_exclusive_scan(elem_cnt, elem_off, m->nel, 1, tmp, w.scan_blocks, s));
+    chk(launch_exclusive_scan(elem_cnt, chunk_off, m->nel, kChunk, tmp, w.scan_blocks, s));
+    chk(launch_locate(m, 1, n, d_pts, pt_off, nullptr, elem_off, elem_fill, slot_pt, slot_elem,
+                      sorted, s));
+    chk(launch_newton(m, precision, n, d_pts, slot_pt, sorted, elem_off, chunk_off, w.cap, res_r,
+                      res_dist, res_code, counters, stats, s));
+    chk(launch_select(m, n, pt_off, slot_elem, w.cap, res_r, res_dist, res_code, d_code, d_elem,
+                      d_r, d_dist, s));
+    return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;
+}
+
+size_t fpts_eval_workspace_size(const fpts_mesh *m, int64_t n)
+{
+    if (!m || n < 0 || n > INT32_MAX - 1) return 0;
+    return eval_ws_layout(m, n).total;
+}
+
+int fpts_eval(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_t *d_elem,
+              const double *d_r, int n_fields, const double *d_field, double *d_out, void *d_ws,
+              size_t ws_bytes, void *stream)
+{
+    if (!m || n < 0 || n > INT32_MAX - 1 || n_fields < 1) return FPTS_EINVAL;
+    if (n == 0) return FPTS_OK;
+    if (!d_code || !d_elem || !d_r || !d_field || !d_out || !d_ws) return FPTS_EINVAL;
+    if (((uintptr_t)d_ws & 255) != 0) return FPTS_EINVAL;
+    const EvalWs w = eval_ws_layout(m, n);
+    if (ws_bytes < w.total) return FPTS_EINVAL;
+    if (sticky_error()) return FPTS_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    int *elem_cnt = at<int>(d_ws, w.elem_cnt);
+    int *elem_off = at<int>(d_ws, w.elem_off);
+    int *elem_fill = at<int>(d_ws, w.elem_fill);
+    int *chunk_off = at<int>(d_ws, w.chunk_off);
+    int *tmp = at<int>(d_ws, w.scan_tmp);
+    int *sorted = at<int>(d_ws, w.sorted);
+    int *counters = at<int>(d_ws, w.counters);
+    const int64_t tb = scan_tmp_blocks(m->nel);
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+    };
+    chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
+    chk(launch_fill_i32(elem_fill, m->nel, 0, s));
+    chk(launch_fill_i32(counters, kCounters, 0, s));
+    chk(launch_eval_bin(m, 0, n, d_code, d_elem, n_fields, d_out, elem_cnt, nullptr, nullptr,
+                        nullptr, s));
+    chk(launch_exclusive_scan(elem_cnt, elem_off, m->nel, 1, tmp, tb, s));
+    chk(launch_exclusive_scan(elem_cnt, chunk_off, m->nel, kChunk, tmp, tb, s));
+    chk(launch_eval_bin(m, 1, n, d_code, d_elem, n_fields, d_out, nullptr, elem_off, elem_fill,
+                        sorted, s));
+    chk(launch_eval(m, n, d_r, n_fields, d_field, d_out, sorted, elem_off, chunk_off, counters,
+                    s));
+    return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;
+}
+
+int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws, fpts_find_stats *out,
+                        void *stream)
+{
+    if (!m || !d_ws || !out || n < 0) return FPTS_EINVAL;
+    const FindWs w = find_ws_layout(m, n);
+    unsigned long long v[kStats] = {0};
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(v, static_cast<const char *>(d_ws) + w.stats, sizeof(v),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return FPTS_EDEVICE;
+    out->pairs = (int64_t)v[0];
+    out->passes = (int64_t)v[1];
+    out->evals = (int64_t)v[2];
+    out->evals_h2 = (int64_t)v[3];
+    out->passes_fp32 = (int64_t)v[4];
+    out->evals_fp32 = (int64_t)v[5];
+    return FPTS_OK;
+}
+
+int fpts_get_boxes(const fpts_mesh *m, double *h_aabb, double *h_obb_A, double *h_obb_c)
+{
+    if (!m) return FPTS_EINVAL;
+    const int D = m->D, W = box_words(D);
+    for (int64_t e = 0; e < m->nel; ++e) {
+        const double *rec = &m->box[(size_t)e * W];
+        for (int d = 0; d < D; ++d) {
+            if (h_aabb) {
+                h_aabb[((size_t)e * D + d) * 2] = rec[d];
+                h_aabb[((size_t)e * D + d) * 2 + 1] = rec[D + d];
+            }
+            if (h_obb_c) h_obb_c[(size_t)e * D + d] = rec[2 * D + d];
+        }
+        if (h_obb_A)
+            for (int a = 0; a < D * D; ++a) h_obb_A[(size_t)e * D * D + a] = rec[3 * D + a];
+    }
+    return FPTS_OK;
+}
+
+int fpts_get_hash(const fpts_mesh *m, double *h_lo, double *h_hi, double *h_delta, int *hash_n,
+                  int64_t *nnz, int *max_cell)
+{
+    if (!m) return FPTS_EINVAL;
+    for (int d = 0; d < m->D; ++d) {
+        if (h_lo) h_lo[d] = m->hlo[d];
+        if (h_hi) h_hi[d] = m->hhi[d];
+        if (h_delta) h_delta[d] = m->hdel[d];
+    }
+    if (hash_n) *hash_n = m->NL;
+    if (nnz) *nnz = (int64_t)m->cell_off.back();
+    if (max_cell) *max_cell = m->max_cell;
+    return FPTS_OK;
+}
+
+}  // extern "C"

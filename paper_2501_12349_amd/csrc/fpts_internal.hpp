@@ -1,0 +1,110 @@
+// Internal declarations of the fpts library (host setup, kernel launchers).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "fpts.h"
+
+namespace fpts {
+
+constexpr int kMaxN = 10;        // nodes per direction with compiled kernels
+constexpr int kWave = 64;        // CDNA wavefront
+constexpr int kChunk = 64;       // (point, element) pairs per wave task
+
+// GLL nodes z_i and product-form weights w_i = 1 / prod_{m != i}(z_i - z_m):
+// phi_i(r) = w_i prod_{m != i}(r - z_m).
+struct Basis {
+    double z[16];
+    double w[16];
+};
+
+// Packed box record of one element: AABB lo[D], hi[D]; OBB centre c[D] and
+// inverse transform A[D][D] (all zero when the centre Jacobian is singular,
+// which makes the OBB test pass).
+inline int box_words(int D) { return 3 * D + D * D; }
+
+// Local map on the device: implicit Cartesian grid + CSR cell lists.
+struct HashView {
+    double lo[3], hi[3], del[3];
+    int NL;
+    const int *cell_off;   // [NL^D + 1]
+    const int *cell_el;    // [nnz], ascending element id per cell
+    const double *box;     // [nel][box_words(D)]
+};
+
+// Byte offsets of the find workspace for n points (every array 256-aligned).
+struct FindWs {
+    size_t pt_off, elem_cnt, elem_off, elem_fill, chunk_off, scan_tmp, slot_pt,
+        slot_elem, sorted, res_r, res_dist, res_code, counters, stats, total;
+    int64_t cap;            // pair capacity
+    int64_t scan_blocks;
+};
+
+struct EvalWs {
+    size_t elem_cnt, elem_off, elem_fill, chunk_off, scan_tmp, sorted, counters,
+        total;
+};
+
+}  // namespace fpts
+
+struct fpts_mesh {
+    fpts_params p;
+    int D, R, N, NP;
+    int64_t nel;
+    int device;
+    int cus;                 // compute units of the device
+    fpts::Basis basis;
+    // host copies of setup products
+    std::vector<double> box;      // [nel][box_words]
+    std::vector<double> xc;       // [nel][D] element centre x(0)
+    std::vector<int> cell_off, cell_el;
+    double hlo[3], hhi[3], hdel[3];
+    int NL;
+    int max_cell;
+    // device copies
+    double *d_nodes = nullptr;    // [nel][D][NP]
+    float *d_nodes32 = nullptr;   // [nel][D][NP] x - x_c in FP32 (mixed mode)
+    double *d_xc = nullptr;       // [nel][D]
+    double *d_box = nullptr;
+    int *d_cell_off = nullptr, *d_cell_el = nullptr;
+};
+
+namespace fpts {
+
+// host setup (setup.cpp)
+int host_setup(fpts_mesh *m, const double *h_nodes);
+
+// workspace layouts (api.cpp)
+FindWs find_ws_layout(const fpts_mesh *m, int64_t n);
+EvalWs eval_ws_layout(const fpts_mesh *m, int64_t n);
+
+// launchers (kernels_*.hip); all return hipError_t of the last launch
+hipError_t launch_fill_i32(int *p, int64_t count, int value, hipStream_t s);
+hipError_t launch_exclusive_scan(const int *in, int *out, int64_t n, int ceil_div,
+                                 int *tmp, int64_t tmp_blocks, hipStream_t s);
+int64_t scan_tmp_blocks(int64_t n);
+hipError_t launch_locate(const fpts_mesh *m, int pass, int64_t n, const double *pts,
+                         int *pt_cnt_or_off, int *elem_cnt, const int *elem_off,
+                         int *elem_fill, int *slot_pt, int *slot_elem, int *sorted,
+                         hipStream_t s);
+hipError_t launch_newton(const fpts_mesh *m, int precision, int64_t n, const double *pts,
+                         const int *slot_pt, const int *sorted, const int *elem_off,
+                         const int *chunk_off, int64_t cap, double *res_r, double *res_dist,
+                         int *res_code, int *counter, unsigned long long *stats,
+                         hipStream_t s);
+hipError_t launch_select(const fpts_mesh *m, int64_t n, const int *pt_off,
+                         const int *slot_elem, int64_t cap, const double *res_r,
+                         const double *res_dist, const int *res_code, int32_t *code,
+                         int32_t *elem, double *r, double *dist, hipStream_t s);
+hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
+                           const int32_t *elem, int n_fields, double *out, int *elem_cnt,
+                           const int *elem_off, int *elem_fill, int *sorted, hipStream_t s);
+hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fields,
+                       const double *field, double *out, const int *sorted,
+                       const int *elem_off, const int *chunk_off, int *counter,
+                       hipStream_t s);
+hipError_t launch_nodes32(const fpts_mesh *m, hipStream_t s);
+
+}  // namespace fpts

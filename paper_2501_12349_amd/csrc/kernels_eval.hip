@@ -1,0 +1,196 @@
+// Interpolate (Section 3.3): u_f(r*) = sum_ijk u_f,ijk phi_i(r) phi_j(s)
+// phi_k(t) (eq. eq_u_tensor) at the computational coordinates from Find.
+//
+// Points are first counted and scattered into per-element buckets (the
+// grouping by element the paper's CPU code uses, Section 5 remark), then a
+// wavefront takes up to 64 points of ONE element, reads the element's nodal
+// values with scalar loads (once per wave, not once per point) and each lane
+// contracts them sum-factorised: N^3 + N^2 + N FMAs per field and point.
+// Also: the FP32 element-local node copy used by mixed-precision Newton.
+#include "fpts_internal.hpp"
+
+namespace fpts {
+namespace {
+
+typedef const __attribute__((address_space(4))) double cdouble;
+
+// pass 0: count points per element and write NaN for NOT_FOUND points;
+// pass 1: scatter point ids into their element's bucket.
+__global__ __launch_bounds__(256) void k_eval_bin(int pass, int n, int nel, const int32_t *code,
+                                                 const int32_t *elem, int n_fields, double *out,
+                                                 int *elem_cnt, const int *elem_off,
+                                                 int *elem_fill, int *sorted)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int e = elem[p];
+    const bool found = code[p] != FPTS_NOT_FOUND && e >= 0 && e < nel;
+    if (pass == 0) {
+        if (found) atomicAdd(&elem_cnt[e], 1);
+        else
+            for (int f = 0; f < n_fields; ++f) out[(size_t)f * n + p] = __builtin_nan("");
+    } else if (found) {
+        sorted[elem_off[e] + atomicAdd(&elem_fill[e], 1)] = p;
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void basis_v(double r, const double *z, const double *w, double (&v)[N])
+{
+    double pv[N];
+    pv[0] = 1.0;
+#pragma unroll
+    for (int i = 1; i < N; ++i) pv[i] = pv[i - 1] * (r - z[i - 1]);
+    double sv = 1.0;
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        v[i] = w[i] * (pv[i] * sv);
+        sv *= r - z[i];
+    }
+}
+
+struct EvalArgs {
+    const double *r;        // [R][n]
+    int n;
+    int nel;
+    int n_fields;
+    const double *field;    // [n_fields][nel][NP]
+    double *out;            // [n_fields][n]
+    const int *sorted;
+    const int *elem_off;
+    const int *chunk_off;
+    int *counter;
+    Basis basis;
+};
+
+template <int R, int N>
+__global__ __launch_bounds__(64) void k_eval(EvalArgs a)
+{
+    constexpr int NP = (R == 3) ? N * N * N : N * N;
+    const int lane = threadIdx.x;
+    const int total = a.chunk_off[a.nel];
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(a.counter, 1);
+        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
+        if (t >= total) break;
+        int lo = 0, hi = a.nel;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.chunk_off[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        const int e = __builtin_amdgcn_readfirstlane(lo);
+        const int beg = a.elem_off[e] + (t - a.chunk_off[e]) * kChunk;
+        const int end = min(a.elem_off[e + 1], beg + kChunk);
+        const int idx = beg + lane;
+        const bool has = idx < end;
+        const int p = has ? a.sorted[idx] : 0;
+        double v0[N], v1[N], v2[N];
+        basis_v<N>(has ? a.r[p] : 0.0, a.basis.z, a.basis.w, v0);
+        basis_v<N>(has ? a.r[(size_t)a.n + p] : 0.0, a.basis.z, a.basis.w, v1);
+        if (R == 3) basis_v<N>(has ? a.r[(size_t)2 * a.n + p] : 0.0, a.basis.z, a.basis.w, v2);
+        for (int f = 0; f < a.n_fields; ++f) {
+            cdouble *u = (cdouble *)(a.field + ((size_t)f * a.nel + e) * NP);
+            double acc = 0.0;
+            if constexpr (R == 3) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    double B = 0.0;
+#pragma unroll
+                    for (int j = 0; j < N; ++j) {
+                        double A = 0.0;
+#pragma unroll
+                        for (int i = 0; i < N; ++i) A = fma(u[i + N * (j + N * k)], v0[i], A);
+                        B = fma(A, v1[j], B);
+                    }
+                    acc = fma(B, v2[k], acc);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < N; ++j) {
+                    double A = 0.0;
+#pragma unroll
+                    for (int i = 0; i < N; ++i) A = fma(u[i + N * j], v0[i], A);
+                    acc = fma(A, v1[j], acc);
+                }
+            }
+            if (has) a.out[(size_t)f * a.n + p] = acc;
+        }
+    }
+}
+
+__global__ void k_nodes32(const double *nodes, const double *xc, float *out, int64_t nel, int D,
+                          int NP)
+{
+    const int64_t total = nel * D * NP;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = i / ((int64_t)D * NP);
+        const int c = (int)((i / NP) % D);
+        out[i] = (float)(nodes[i] - xc[e * D + c]);
+    }
+}
+
+typedef void (*EvalFn)(EvalArgs);
+
+template <int R>
+EvalFn pick_eval(int N)
+{
+    switch (N) {
+    case 2: return k_eval<R, 2>;
+    case 3: return k_eval<R, 3>;
+    case 4: return k_eval<R, 4>;
+    case 5: return k_eval<R, 5>;
+    case 6: return k_eval<R, 6>;
+    case 7: return k_eval<R, 7>;
+    case 8: return k_eval<R, 8>;
+    case 9: return k_eval<R, 9>;
+    case 10: return k_eval<R, 10>;
+    default: return nullptr;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
+                           const int32_t *elem, int n_fields, double *out, int *elem_cnt,
+                           const int *elem_off, int *elem_fill, int *sorted, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eval_bin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pass,
+                       (int)n, (int)m->nel, code, elem, n_fields, out, elem_cnt, elem_off,
+                       elem_fill, sorted);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fields,
+                       const double *field, double *out, const int *sorted, const int *elem_off,
+                       const int *chunk_off, int *counter, hipStream_t s)
+{
+    EvalFn fn = m->R == 3 ? pick_eval<3>(m->N) : pick_eval<2>(m->N);
+    if (!fn) return hipErrorInvalidValue;
+    EvalArgs a;
+    a.r = r;
+    a.n = (int)n;
+    a.nel = (int)m->nel;
+    a.n_fields = n_fields;
+    a.field = field;
+    a.out = out;
+    a.sorted = sorted;
+    a.elem_off = elem_off;
+    a.chunk_off = chunk_off;
+    a.counter = counter;
+    a.basis = m->basis;
+    hipLaunchKernelGGL(fn, dim3(m->cus * 16), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_nodes32(const fpts_mesh *m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nodes32, dim3(4096), dim3(256), 0, s, m->d_nodes, m->d_xc,
+                       m->d_nodes32, (int64_t)m->nel, m->D, m->NP);
+    return hipGetLastError();
+}
+
+}  // namespace fpts

@@ -1,0 +1,222 @@
+"""Python binding of the fpts C-ABI (include/fpts.h): argument marshalling
+only.  Device memory and streams come from PyTorch; every step of Find and
+Interpolate runs in the HIP kernels of libfpts.so.  There is no CPU path:
+without the library or a HIP device the calls raise."""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfpts.so")
+
+INTERIOR, BORDER, NOT_FOUND = 0, 1, 2
+FP64, MIXED = 0, 1
+_PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
+
+# Entry points declared in include/fpts.h.
+EXPORTS = ("fpts_params_default", "fpts_setup", "fpts_destroy",
+           "fpts_find_workspace_size", "fpts_find", "fpts_eval_workspace_size",
+           "fpts_eval", "fpts_find_stats_get", "fpts_get_boxes", "fpts_get_hash",
+           "fpts_status_string")
+
+
+class FptsError(RuntimeError):
+    pass
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("ref_dim", ctypes.c_int),
+                ("nodes_1d", ctypes.c_int), ("hash_n", ctypes.c_int),
+                ("n_elem", ctypes.c_int64), ("bbox_tol", ctypes.c_double),
+                ("surf_eps_d", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("newton_tol", ctypes.c_double)]
+
+
+class FindStats(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_int64), ("passes", ctypes.c_int64),
+                ("evals", ctypes.c_int64), ("evals_h2", ctypes.c_int64),
+                ("passes_fp32", ctypes.c_int64), ("evals_fp32", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libfpts.so (built by build.py); raises when it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FptsError("libfpts.so is not built (run __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    vp, i64, dbl, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    L.fpts_params_default.argtypes = [ctypes.POINTER(Params), i32, i32, i32, i64]
+    L.fpts_params_default.restype = None
+    L.fpts_setup.argtypes = [ctypes.POINTER(Params), vp, vp, ctypes.POINTER(vp)]
+    L.fpts_destroy.argtypes = [vp]
+    L.fpts_find_workspace_size.argtypes = [vp, i64]
+    L.fpts_find_workspace_size.restype = ctypes.c_size_t
+    L.fpts_find.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp, ctypes.c_size_t, vp]
+    L.fpts_eval_workspace_size.argtypes = [vp, i64]
+    L.fpts_eval_workspace_size.restype = ctypes.c_size_t
+    L.fpts_eval.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
+    L.fpts_find_stats_get.argtypes = [vp, i64, vp, ctypes.POINTER(FindStats), vp]
+    L.fpts_get_boxes.argtypes = [vp, vp, vp, vp]
+    L.fpts_get_hash.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i32),
+                                ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    L.fpts_status_string.argtypes = [i32]
+    L.fpts_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        raise FptsError("fpts error %d: %s" % (
+            status, load_library().fpts_status_string(status).decode()))
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """A mesh resident on the current HIP device (fpts_setup).
+
+    nodes: host array [n_elem][dim][nodes_1d^ref_dim] (first reference
+    index fastest).  dim/ref_dim default to the volume case of nodes'
+    shape; pass ref_dim=2 with dim=3 for surface quads."""
+
+    def __init__(self, nodes, nodes_1d, dim=None, ref_dim=None, bbox_tol=0.1, hash_n=0,
+                 surf_eps_d=1e-10, max_iter=50, newton_tol=1e-10, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise FptsError("no HIP device visible")
+        L = load_library()
+        nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        nel, D, NP = nodes.shape
+        dim = D if dim is None else dim
+        if ref_dim is None:
+            ref_dim = dim if NP == nodes_1d ** dim else dim - 1
+        p = Params()
+        L.fpts_params_default(ctypes.byref(p), dim, ref_dim, nodes_1d, nel)
+        p.bbox_tol, p.hash_n, p.surf_eps_d = bbox_tol, hash_n, surf_eps_d
+        p.max_iter, p.newton_tol = max_iter, newton_tol
+        if NP != nodes_1d ** ref_dim or D != dim:
+            raise FptsError("nodes shape %s does not match dim/ref_dim/nodes_1d" %
+                            (nodes.shape,))
+        h = ctypes.c_void_p()
+        _check(L.fpts_setup(ctypes.byref(p), nodes.ctypes.data_as(ctypes.c_void_p),
+                            _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self.dim, self.ref_dim, self.N, self.n_elem, self.NP = dim, ref_dim, nodes_1d, nel, NP
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().fpts_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- workspaces
+    def find_workspace_bytes(self, n):
+        return load_library().fpts_find_workspace_size(self._h, n)
+
+    def eval_workspace_bytes(self, n):
+        return load_library().fpts_eval_workspace_size(self._h, n)
+
+    def workspace(self, nbytes):
+        """A cached uint8 device buffer of at least nbytes (256-aligned)."""
+        import torch
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = None
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    # -- Find
+    def find(self, pts, precision="fp64", out=None, ws=None, stream=None):
+        """pts: float64 device tensor [dim][n] -> dict(code, elem, r, dist)."""
+        import torch
+        L = load_library()
+        if pts.dtype != torch.float64 or not pts.is_cuda or pts.dim() != 2 or \
+                pts.shape[0] != self.dim:
+            raise FptsError("pts must be a float64 device tensor [dim][n]")
+        pts = pts.contiguous()
+        n = pts.shape[1]
+        if out is None:
+            out = dict(code=torch.empty(n, dtype=torch.int32, device=pts.device),
+                       elem=torch.empty(n, dtype=torch.int32, device=pts.device),
+                       r=torch.empty((self.ref_dim, n), dtype=torch.float64, device=pts.device),
+                       dist=torch.empty(n, dtype=torch.float64, device=pts.device))
+        need = self.find_workspace_bytes(n)
+        if need == 0:
+            raise FptsError("too many points for one find call")
+        wsb = ws if ws is not None else self.workspace(need)
+        _check(L.fpts_find(self._h, n, _dptr(pts), _dptr(out["code"]), _dptr(out["elem"]),
+                           _dptr(out["r"]), _dptr(out["dist"]), _PREC[precision],
+                           _dptr(wsb), wsb.numel(), _stream_ptr(stream)))
+        self._last_find_ws = (wsb, n)
+        return out
+
+    def find_stats(self, stream=None):
+        """Counters of the last find (synchronises the stream)."""
+        wsb, n = self._last_find_ws
+        st = FindStats()
+        _check(load_library().fpts_find_stats_get(self._h, n, _dptr(wsb), ctypes.byref(st),
+                                                  _stream_ptr(stream)))
+        return {k: getattr(st, k) for k, _ in FindStats._fields_}
+
+    # -- Interpolate
+    def eval(self, res, field, out=None, ws=None, stream=None):
+        """field: float64 device tensor [n_fields][n_elem][NP] (or
+        [n_elem][NP]) -> [n_fields][n]."""
+        import torch
+        L = load_library()
+        if field.dim() == 2:
+            field = field.unsqueeze(0)
+        if field.dtype != torch.float64 or not field.is_cuda or \
+                tuple(field.shape[1:]) != (self.n_elem, self.NP):
+            raise FptsError("field must be float64 [n_fields][n_elem][NP] on the device")
+        field = field.contiguous()
+        n = res["code"].shape[0]
+        nf = field.shape[0]
+        if out is None:
+            out = torch.empty((nf, n), dtype=torch.float64, device=field.device)
+        need = self.eval_workspace_bytes(n)
+        wsb = ws if ws is not None else self.workspace(need)
+        _check(L.fpts_eval(self._h, n, _dptr(res["code"]), _dptr(res["elem"]),
+                           _dptr(res["r"].contiguous()), nf, _dptr(field), _dptr(out),
+                           _dptr(wsb), wsb.numel(), _stream_ptr(stream)))
+        return out
+
+    # -- setup products
+    def boxes(self):
+        D = self.dim
+        aabb = np.zeros((self.n_elem, D, 2))
+        A = np.zeros((self.n_elem, D, D))
+        c = np.zeros((self.n_elem, D))
+        _check(load_library().fpts_get_boxes(self._h, aabb.ctypes.data, A.ctypes.data,
+                                             c.ctypes.data))
+        return aabb, A, c
+
+    def hash_info(self):
+        D = self.dim
+        lo, hi, de = np.zeros(D), np.zeros(D), np.zeros(D)
+        nl, mc = ctypes.c_int(), ctypes.c_int()
+        nnz = ctypes.c_int64()
+        _check(load_library().fpts_get_hash(self._h, lo.ctypes.data, hi.ctypes.data,
+                                            de.ctypes.data, ctypes.byref(nl),
+                                            ctypes.byref(nnz), ctypes.byref(mc)))
+        return dict(NL=nl.value, lo=lo, hi=hi, delta=de, nnz=nnz.value, max_cell=mc.value)

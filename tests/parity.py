@@ -1,0 +1,94 @@
+"""Comparison of GPU find/eval results with the oracle.
+
+Unambiguous points (the oracle's margins say no rounding-level change of the
+inputs can change the answer) must match exactly in element and code, with
+|dr| <= 1e-10 and |ddist| <= 1e-10 h.  Ambiguous points (within 1e-6 h of an
+element face, at a box boundary, with two candidates at nearly equal
+distance, or at the surface threshold) must carry a valid answer: a real
+element whose map at the returned r reproduces the returned distance, no
+worse than the oracle's best, and consistent with its code."""
+import numpy as np
+
+import oracle
+
+R_TOL = 1e-10
+D_TOL = 1e-10
+MARGIN_R = 2e-6       # reference units, ~1e-6 h from a face
+MARGIN_BOX = 1e-9
+MARGIN_GAP = 1e-8
+MARGIN_EPS = 1e-6
+
+
+def ambiguous(orc, surface=False):
+    m = orc["margin"]
+    code = orc["code"]
+    amb = (code == oracle.INTERIOR) & (m[0] < MARGIN_R)
+    amb |= (code != oracle.INTERIOR) & (m[1] < MARGIN_BOX)
+    amb |= (code == oracle.BORDER) & ((m[2] < MARGIN_GAP) | (m[3] < MARGIN_GAP))
+    if surface:
+        amb |= (code != oracle.NOT_FOUND) & (m[4] < MARGIN_EPS)
+    return amb
+
+
+def compare_find(omesh, pts, orc, gpu, h, surface=False, r_tol=R_TOL, d_tol=D_TOL):
+    """Returns a report dict; raises AssertionError on any violation."""
+    code_g, elem_g = gpu["code"], gpu["elem"]
+    r_g, dist_g = gpu["r"], gpu["dist"]
+    amb = ambiguous(orc, surface)
+    una = ~amb
+    rep = dict(n=len(code_g), ambiguous=int(amb.sum()))
+    bad_code = una & (code_g != orc["code"])
+    bad_elem = una & (elem_g != orc["elem"])
+    assert not bad_code.any(), "code mismatch at %s" % np.nonzero(bad_code)[0][:10]
+    assert not bad_elem.any(), "element mismatch at %s" % np.nonzero(bad_elem)[0][:10]
+    found = una & (orc["code"] != oracle.NOT_FOUND)
+    dr = np.abs(r_g[:, found] - orc["r"][:, found]).max() if found.any() else 0.0
+    dd = np.abs(dist_g[found] - orc["dist"][found]).max() if found.any() else 0.0
+    rep["max_dr"], rep["max_ddist"] = float(dr), float(dd)
+    assert dr <= r_tol, "max |dr| %g" % dr
+    assert dd <= d_tol * h, "max |ddist| %g" % dd
+    nf = una & (orc["code"] == oracle.NOT_FOUND)
+    assert np.all(elem_g[nf] == -1) and np.all(np.isinf(dist_g[nf]))
+    # ambiguous points: validity
+    for p in np.nonzero(amb)[0]:
+        cg, eg = int(code_g[p]), int(elem_g[p])
+        co = int(orc["code"][p])
+        if cg == oracle.NOT_FOUND:
+            assert co == oracle.NOT_FOUND or orc["margin"][1][p] < MARGIN_BOX, p
+            continue
+        assert 0 <= eg < omesh.nel, p
+        x, _, _ = omesh.map(eg, r_g[:, p])
+        dchk = np.linalg.norm(pts[:, p] - x)
+        assert abs(dchk - dist_g[p]) <= d_tol * h + 1e-14, (p, dchk, dist_g[p])
+        assert np.all(np.abs(r_g[:, p]) <= 1.0), p
+        if co != oracle.NOT_FOUND:
+            assert dist_g[p] <= orc["dist"][p] + 1e-9 * h, (p, dist_g[p], orc["dist"][p])
+        if cg == oracle.INTERIOR:
+            assert np.all(np.abs(r_g[:, p]) < 1.0), p
+            if surface:
+                assert dist_g[p] ** 2 < omesh_eps(omesh) * (1 + 1e-6), p
+        if co == oracle.INTERIOR and cg == oracle.BORDER:
+            assert dist_g[p] <= 1e-9 * h, p
+    return rep
+
+
+def omesh_eps(omesh):
+    return 1e-10
+
+
+def compare_eval(orc_u, gpu_u, code, rel_tol=1e-10):
+    """|du| <= rel_tol * max(|u_oracle|, max |u| over the points), NaN where
+    NOT_FOUND."""
+    nf = code == oracle.NOT_FOUND
+    assert np.all(np.isnan(gpu_u[:, nf]))
+    ok = ~nf
+    if not ok.any():
+        return 0.0
+    scale = np.maximum(np.abs(orc_u[:, ok]), np.abs(orc_u[:, ok]).max(axis=1, keepdims=True))
+    err = np.abs(gpu_u[:, ok] - orc_u[:, ok]) / scale
+    assert err.max() <= rel_tol, err.max()
+    return float(err.max())
+
+
+def to_np(res):
+    return {k: v.cpu().numpy() for k, v in res.items()}
