@@ -1,0 +1,215 @@
+"""Benchmark: located + interpolated points per second on one MI355X.
+
+One step = fpts_find (hash lookup, box filter, trust-region Newton,
+selection) + fpts_eval of all fields, over one batch of device-resident
+points.  Default workload: 48^3 curved hexes, p = 7 (N = 8 GLL nodes per
+direction), 2^24 points uniform in the cube, 3 fields.  Both Newton
+precisions are timed (FP64, and FP32 passes + FP64 polish); `value` is the
+FP64 path, the mixed result sits beside it.
+
+Prints one JSON line (see the driver contract) with a roofline object for
+the dominant kernel (trust-region Newton, measured with HIP events on the
+stream it runs on) and the oracle timed on the host cores over a bounded
+sample of the same points.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_VALU_PEAK_TFLOPS = 78.6    # 256 CUs x 2.4 GHz x 128 FP64 flop/clk
+FP32_VALU_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def eval_flops(D, R, N, h2):
+    """Algorithmic FLOPs of one map evaluation (x, G = dx/dr and, with h2,
+    the second derivatives) at one reference point, as the kernel computes
+    it: sum-factorised contraction + product-form basis jets + objective
+    terms (FMA = 2 FLOPs)."""
+    if R == 3:
+        con = 2 * D * ((3 * N ** 3 + 6 * N ** 2 + 10 * N) if h2 else
+                       (2 * N ** 3 + 3 * N ** 2 + 4 * N))
+    else:
+        con = 2 * D * ((3 * N ** 2 + 6 * N) if h2 else (2 * N ** 2 + 3 * N))
+    basis = R * (27 * N if h2 else 14 * N)
+    obj = 2 * D * (1 + R + (2 * R * R if h2 else R * R))
+    return con + basis + obj
+
+
+def newton_flops(stats, D, R, N):
+    """FLOPs of one Newton launch from its exact counters: nearest-node
+    scans (3 D FLOPs per node and pair) plus every map evaluation."""
+    NP = N ** R
+    f = stats["pairs"] * NP * 3 * D
+    f += (stats["evals"] - stats["evals_h2"]) * eval_flops(D, R, N, False)
+    f += stats["evals_h2"] * eval_flops(D, R, N, True)
+    f += stats["evals_fp32"] * eval_flops(D, R, N, False)
+    return float(f)
+
+
+def make_workload(name):
+    from paper_2501_12349_amd import workloads as W
+    if name == "hex48":
+        return W.hex48()
+    if name == "hex16":
+        return W.hex16()
+    if name == "sphere":
+        return W.sphere()
+    if name == "quad2d":
+        return W.quad2d()
+    raise SystemExit("unknown workload %s" % name)
+
+
+def cpu_baseline(wl, sample, log_):
+    """The oracle (FP64, OpenMP over points) on the first `sample` points:
+    find + eval timed, setup excluded."""
+    import oracle
+    t0 = time.perf_counter()
+    om = oracle.Mesh(wl["nodes"], wl["dim"], wl["ref_dim"], wl["N"])
+    t_setup = time.perf_counter() - t0
+    pts = np.ascontiguousarray(wl["pts"][:, :sample])
+    log_("cpu baseline: oracle setup %.1f s, timing find+eval on %d points" % (t_setup, sample))
+    t0 = time.perf_counter()
+    res = om.find(pts)
+    if wl.get("fields") is not None:
+        om.eval(res, wl["fields"])
+    t = time.perf_counter() - t0
+    return dict(value=sample / t / 1e6, unit="Mpts/s", cores=oracle.max_threads(),
+                kind="oracle",
+                sample="first %d of the %d points, same mesh and %d fields; find+eval %.1f s, "
+                       "oracle setup %.1f s excluded" % (
+                           sample, wl["pts"].shape[1],
+                           0 if wl.get("fields") is None else wl["fields"].shape[0], t, t_setup))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="hex48")
+    ap.add_argument("--cpu-sample", type=int, default=60000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--modes", default="fp64,mixed")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this benchmark runs on exactly one GPU: the find/eval path has no "
+              "multi-GPU mode (see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2501_12349_amd import fpts
+
+    t0 = time.perf_counter()
+    wl = make_workload(args.workload)
+    log("workload %s generated in %.1f s" % (wl["name"], time.perf_counter() - t0))
+    D, R, N = wl["dim"], wl["ref_dim"], wl["N"]
+    n = wl["pts"].shape[1]
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    gm = fpts.Mesh(wl["nodes"], N, dim=D, ref_dim=R)
+    t_setup = time.perf_counter() - t0
+    log("setup %.2f s (host boxes + map, upload)" % t_setup)
+    pts = torch.from_numpy(wl["pts"]).to(dev)
+    fields = torch.from_numpy(wl["fields"]).to(dev)
+    nf = fields.shape[0]
+    out = dict(code=torch.empty(n, dtype=torch.int32, device=dev),
+               elem=torch.empty(n, dtype=torch.int32, device=dev),
+               r=torch.empty((R, n), dtype=torch.float64, device=dev),
+               dist=torch.empty(n, dtype=torch.float64, device=dev))
+    u = torch.empty((nf, n), dtype=torch.float64, device=dev)
+    ws_f = torch.empty(gm.find_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    ws_e = torch.empty(gm.eval_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    log("workspace find %.2f GB, eval %.2f GB" % (ws_f.numel() / 1e9, ws_e.numel() / 1e9))
+
+    def step(prec):
+        gm.find(pts, precision=prec, out=out, ws=ws_f)
+        gm.eval(out, fields, out=u, ws=ws_e)
+
+    results = {}
+    for mode in args.modes.split(","):
+        for _ in range(args.warmup):
+            step(mode)
+        torch.cuda.synchronize()
+        stats = gm.find_stats()
+        gm.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(mode)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kt = gm.profile_read()
+        gm.profile(False)
+        codes = torch.bincount(out["code"].long(), minlength=3).cpu().tolist()
+        ms = dt / args.steps * 1e3
+        newton_ms = kt["newton_ms"] / max(kt["find_calls"], 1)
+        fl = newton_flops(stats, D, R, N)
+        results[mode] = dict(ms_per_step=ms, mpts=n / (dt / args.steps) / 1e6, kt=kt,
+                             newton_ms=newton_ms, stats=stats, flops=fl, codes=codes)
+        log("%s: %.3f ms/step  %.1f Mpts/s  newton %.3f ms (%.1f TFLOP/s)  locate %.3f "
+            "select %.3f eval_bin %.3f eval %.3f ms/call  codes %s  stats %s" % (
+                mode, ms, n / (dt / args.steps) / 1e6, newton_ms, fl / newton_ms / 1e9,
+                kt["locate_ms"] / kt["find_calls"], kt["select_ms"] / kt["find_calls"],
+                kt["eval_bin_ms"] / kt["eval_calls"], kt["eval_ms"] / kt["eval_calls"],
+                codes, stats))
+
+    main_mode = "fp64" if "fp64" in results else list(results)[0]
+    r0 = results[main_mode]
+    achieved = r0["flops"] / (r0["newton_ms"] * 1e-3) / 1e12
+    line = {
+        "metric": "located+interpolated points/s (Mpts/s) FP64 vs mixed; p50/p99 request latency",
+        "value": round(r0["mpts"], 3),
+        "unit": "Mpts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r0["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%s_%dpts_%dfields" % (wl["name"], n, nf),
+                   "n_elem": int(wl["nodes"].shape[0]), "nodes_1d": N, "dim": D,
+                   "ref_dim": R, "n_points": n, "n_fields": nf, "precision": main_mode,
+                   "step": "find + eval of all fields, inputs resident in HBM"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_newton (FP64 trust-region Newton)",
+                     "kernel_ms": round(r0["newton_ms"], 4),
+                     "flops_per_launch": r0["flops"]},
+        "setup_s": round(t_setup, 3),
+        "codes": dict(zip(("interior", "border", "not_found"), r0["codes"])),
+    }
+    if "mixed" in results and main_mode != "mixed":
+        rm = results["mixed"]
+        line["mixed"] = {"value": round(rm["mpts"], 3), "unit": "Mpts/s",
+                         "ms_per_step": round(rm["ms_per_step"], 4),
+                         "speedup_vs_fp64": round(rm["mpts"] / r0["mpts"], 4),
+                         "newton_kernel_ms": round(rm["newton_ms"], 4)}
+    kt = r0["kt"]
+    line["kernel_ms"] = {k: round(kt[k + "_ms"] / max(kt["find_calls" if k in
+                         ("locate", "newton", "select") else "eval_calls"], 1), 4)
+                         for k in ("locate", "newton", "select", "eval_bin", "eval")}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, n), log)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

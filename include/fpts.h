@@ -153,6 +153,27 @@ typedef struct fpts_find_stats {
 int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws,
                         fpts_find_stats *out, void *stream);
 
+/* Kernel timing with HIP events recorded on the caller's stream around
+ * each group of kernels of fpts_find / fpts_eval: locate (both locate passes
+ * and the scans), newton (the trust-region Newton kernel), select, eval
+ * (point binning and interpolation).  Sums over the calls since profiling
+ * was enabled.  Meant for one stream at a time. */
+typedef struct fpts_kernel_times {
+    double locate_ms;
+    double newton_ms;
+    double select_ms;
+    double eval_bin_ms;
+    double eval_ms;
+    int64_t find_calls;
+    int64_t eval_calls;
+} fpts_kernel_times;
+
+/* enable != 0 starts recording (clearing earlier records); 0 stops. */
+int fpts_profile(fpts_mesh *m, int enable);
+
+/* Wait for the recorded events, return the sums and clear the records. */
+int fpts_profile_read(fpts_mesh *m, fpts_kernel_times *out);
+
 /* Read-only views of setup products, for tests and tools: copies to host
  * arrays sized [n_elem][dim][2] (AABB lo/hi), [n_elem][dim][dim] (OBB
  * inverse transform) and [n_elem][dim] (OBB centre).  Any pointer may be

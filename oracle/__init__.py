@@ -66,8 +66,14 @@ def lib():
                                D, I, I, ctypes.c_int]
         L.orc_eval.argtypes = [P, ctypes.c_longlong, I, I, D, ctypes.c_int, D, D,
                                ctypes.c_int]
+        L.orc_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def max_threads():
+    """OpenMP threads the oracle uses."""
+    return int(lib().orc_max_threads())
 
 
 def _d(a):

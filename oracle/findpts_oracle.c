@@ -1089,3 +1089,13 @@ void orc_eval(const orc_mesh *m, long long n, const int32_t *code, const int32_t
         }
     }
 }
+
+/* Threads an OpenMP region of this library uses by default. */
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -40,9 +40,46 @@ T *at(void *base, size_t off)
 constexpr int kCounters = 64;   // ints: task counters
 constexpr int kStats = 8;       // unsigned long long
 
+void clear_events(fpts_mesh *m)
+{
+    for (auto &v : m->ev) {
+        for (auto &pr : v) {
+            hipEventDestroy(pr.first);
+            hipEventDestroy(pr.second);
+        }
+        v.clear();
+    }
+    m->prof_find = m->prof_eval = 0;
+}
+
+// Records an event pair around a kernel group when profiling is on.
+struct Span {
+    fpts_mesh *m;
+    int k;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    Span(fpts_mesh *m_, int k_, hipStream_t s_) : m(m_), k(k_), s(s_)
+    {
+        if (!m->profiling) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            hipGetLastError();
+            a = b = nullptr;
+            return;
+        }
+        hipEventRecord(a, s);
+    }
+    ~Span()
+    {
+        if (!a) return;
+        hipEventRecord(b, s);
+        m->ev[k].emplace_back(a, b);
+    }
+};
+
 void free_mesh(fpts_mesh *m)
 {
     if (!m) return;
+    clear_events(m);
     hipFree(m->d_nodes);
     hipFree(m->d_nodes32);
     hipFree(m->d_xc);
@@ -244,21 +281,31 @@ int fpts_find(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     auto chk = [&](hipError_t x) {
         if (e == hipSuccess) e = x;
     };
-    chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
-    chk(launch_fill_i32(elem_fill, m->nel, 0, s));
-    chk(launch_fill_i32(counters, kCounters, 0, s));
-    chk(launch_fill_i32(reinterpret_cast<int *>(stats), 2 * kStats, 0, s));
-    chk(launch_locate(m, 0, n, d_pts, pt_off, elem_cnt, nullptr, nullptr, nullptr, nullptr,
-                      nullptr, s));
-    chk(launch_exclusive_scan(pt_off, pt_off, n, 1, tmp, w.scan_blocks, s));
-    chk(launch_exclusive_scan(elem_cnt, elem_off, m->nel, 1, tmp, w.scan_blocks, s));
-    chk(launch_exclusive_scan(elem_cnt, chunk_off, m->nel, kChunk, tmp, w.scan_blocks, s));
-    chk(launch_locate(m, 1, n, d_pts, pt_off, nullptr, elem_off, elem_fill, slot_pt, slot_elem,
-                      sorted, s));
-    chk(launch_newton(m, precision, n, d_pts, slot_pt, sorted, elem_off, chunk_off, w.cap, res_r,
-                      res_dist, res_code, counters, stats, s));
-    chk(launch_select(m, n, pt_off, slot_elem, w.cap, res_r, res_dist, res_code, d_code, d_elem,
-                      d_r, d_dist, s));
+    {
+        Span sp(m, 0, s);
+        chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
+        chk(launch_fill_i32(elem_fill, m->nel, 0, s));
+        chk(launch_fill_i32(counters, kCounters, 0, s));
+        chk(launch_fill_i32(reinterpret_cast<int *>(stats), 2 * kStats, 0, s));
+        chk(launch_locate(m, 0, n, d_pts, pt_off, elem_cnt, nullptr, nullptr, nullptr, nullptr,
+                          nullptr, s));
+        chk(launch_exclusive_scan(pt_off, pt_off, n, 1, tmp, w.scan_blocks, s));
+        chk(launch_exclusive_scan(elem_cnt, elem_off, m->nel, 1, tmp, w.scan_blocks, s));
+        chk(launch_exclusive_scan(elem_cnt, chunk_off, m->nel, kChunk, tmp, w.scan_blocks, s));
+        chk(launch_locate(m, 1, n, d_pts, pt_off, nullptr, elem_off, elem_fill, slot_pt,
+                          slot_elem, sorted, s));
+    }
+    {
+        Span sp(m, 1, s);
+        chk(launch_newton(m, precision, n, d_pts, slot_pt, sorted, elem_off, chunk_off, w.cap,
+                          res_r, res_dist, res_code, counters, stats, s));
+    }
+    {
+        Span sp(m, 2, s);
+        chk(launch_select(m, n, pt_off, slot_elem, w.cap, res_r, res_dist, res_code, d_code,
+                          d_elem, d_r, d_dist, s));
+    }
+    if (m->profiling) m->prof_find++;
     return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;
 }
 
@@ -292,17 +339,24 @@ int fpts_eval(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_t *d_e
     auto chk = [&](hipError_t x) {
         if (e == hipSuccess) e = x;
     };
-    chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
-    chk(launch_fill_i32(elem_fill, m->nel, 0, s));
-    chk(launch_fill_i32(counters, kCounters, 0, s));
-    chk(launch_eval_bin(m, 0, n, d_code, d_elem, n_fields, d_out, elem_cnt, nullptr, nullptr,
-                        nullptr, s));
-    chk(launch_exclusive_scan(elem_cnt, elem_off, m->nel, 1, tmp, tb, s));
-    chk(launch_exclusive_scan(elem_cnt, chunk_off, m->nel, kChunk, tmp, tb, s));
-    chk(launch_eval_bin(m, 1, n, d_code, d_elem, n_fields, d_out, nullptr, elem_off, elem_fill,
-                        sorted, s));
-    chk(launch_eval(m, n, d_r, n_fields, d_field, d_out, sorted, elem_off, chunk_off, counters,
-                    s));
+    {
+        Span sp(m, 3, s);
+        chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
+        chk(launch_fill_i32(elem_fill, m->nel, 0, s));
+        chk(launch_fill_i32(counters, kCounters, 0, s));
+        chk(launch_eval_bin(m, 0, n, d_code, d_elem, n_fields, d_out, elem_cnt, nullptr, nullptr,
+                            nullptr, s));
+        chk(launch_exclusive_scan(elem_cnt, elem_off, m->nel, 1, tmp, tb, s));
+        chk(launch_exclusive_scan(elem_cnt, chunk_off, m->nel, kChunk, tmp, tb, s));
+        chk(launch_eval_bin(m, 1, n, d_code, d_elem, n_fields, d_out, nullptr, elem_off,
+                            elem_fill, sorted, s));
+    }
+    {
+        Span sp(m, 4, s);
+        chk(launch_eval(m, n, d_r, n_fields, d_field, d_out, sorted, elem_off, chunk_off,
+                        counters, s));
+    }
+    if (m->profiling) m->prof_eval++;
     return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;
 }
 
@@ -323,6 +377,40 @@ int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws, fpts_fi
     out->evals_h2 = (int64_t)v[3];
     out->passes_fp32 = (int64_t)v[4];
     out->evals_fp32 = (int64_t)v[5];
+    return FPTS_OK;
+}
+
+int fpts_profile(fpts_mesh *m, int enable)
+{
+    if (!m) return FPTS_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess) return FPTS_EDEVICE;
+    clear_events(m);
+    m->profiling = enable != 0;
+    return FPTS_OK;
+}
+
+int fpts_profile_read(fpts_mesh *m, fpts_kernel_times *out)
+{
+    if (!m || !out) return FPTS_EINVAL;
+    double ms[5] = {0, 0, 0, 0, 0};
+    for (int k = 0; k < 5; ++k)
+        for (auto &pr : m->ev[k]) {
+            float t = 0.0f;
+            if (hipEventSynchronize(pr.second) != hipSuccess ||
+                hipEventElapsedTime(&t, pr.first, pr.second) != hipSuccess)
+                return FPTS_EDEVICE;
+            ms[k] += t;
+        }
+    out->locate_ms = ms[0];
+    out->newton_ms = ms[1];
+    out->select_ms = ms[2];
+    out->eval_bin_ms = ms[3];
+    out->eval_ms = ms[4];
+    out->find_calls = m->prof_find;
+    out->eval_calls = m->prof_eval;
+    const bool on = m->profiling;
+    clear_events(m);
+    m->profiling = on;
     return FPTS_OK;
 }
 

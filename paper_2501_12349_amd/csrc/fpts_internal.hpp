@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
 #include <vector>
 
 #include "fpts.h"
@@ -63,6 +64,10 @@ struct fpts_mesh {
     double hlo[3], hhi[3], hdel[3];
     int NL;
     int max_cell;
+    // profiling: event pairs per kernel group
+    bool profiling = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[5];
+    int64_t prof_find = 0, prof_eval = 0;
     // device copies
     double *d_nodes = nullptr;    // [nel][D][NP]
     float *d_nodes32 = nullptr;   // [nel][D][NP] x - x_c in FP32 (mixed mode)

@@ -17,8 +17,8 @@ _PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
 # Entry points declared in include/fpts.h.
 EXPORTS = ("fpts_params_default", "fpts_setup", "fpts_destroy",
            "fpts_find_workspace_size", "fpts_find", "fpts_eval_workspace_size",
-           "fpts_eval", "fpts_find_stats_get", "fpts_get_boxes", "fpts_get_hash",
-           "fpts_status_string")
+           "fpts_eval", "fpts_find_stats_get", "fpts_profile", "fpts_profile_read",
+           "fpts_get_boxes", "fpts_get_hash", "fpts_status_string")
 
 
 class FptsError(RuntimeError):
@@ -37,6 +37,13 @@ class FindStats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_int64), ("passes", ctypes.c_int64),
                 ("evals", ctypes.c_int64), ("evals_h2", ctypes.c_int64),
                 ("passes_fp32", ctypes.c_int64), ("evals_fp32", ctypes.c_int64)]
+
+
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("locate_ms", ctypes.c_double), ("newton_ms", ctypes.c_double),
+                ("select_ms", ctypes.c_double), ("eval_bin_ms", ctypes.c_double),
+                ("eval_ms", ctypes.c_double), ("find_calls", ctypes.c_int64),
+                ("eval_calls", ctypes.c_int64)]
 
 
 _lib = None
@@ -62,6 +69,8 @@ def load_library(path=LIB_PATH):
     L.fpts_eval_workspace_size.restype = ctypes.c_size_t
     L.fpts_eval.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
     L.fpts_find_stats_get.argtypes = [vp, i64, vp, ctypes.POINTER(FindStats), vp]
+    L.fpts_profile.argtypes = [vp, i32]
+    L.fpts_profile_read.argtypes = [vp, ctypes.POINTER(KernelTimes)]
     L.fpts_get_boxes.argtypes = [vp, vp, vp, vp]
     L.fpts_get_hash.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i32),
                                 ctypes.POINTER(i64), ctypes.POINTER(i32)]
@@ -200,6 +209,15 @@ class Mesh:
                            _dptr(res["r"].contiguous()), nf, _dptr(field), _dptr(out),
                            _dptr(wsb), wsb.numel(), _stream_ptr(stream)))
         return out
+
+    # -- kernel timing (HIP events on the call's stream)
+    def profile(self, enable=True):
+        _check(load_library().fpts_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        kt = KernelTimes()
+        _check(load_library().fpts_profile_read(self._h, ctypes.byref(kt)))
+        return {k: getattr(kt, k) for k, _ in KernelTimes._fields_}
 
     # -- setup products
     def boxes(self):
