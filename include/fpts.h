@@ -138,16 +138,19 @@ int fpts_eval(fpts_mesh *m, int64_t n, const int32_t *d_code,
               size_t ws_bytes, void *stream);
 
 /* Counters of the last fpts_find that used workspace d_ws (read back with a
- * device-to-host copy on `stream`, which is synchronised).  Filled:
- * candidate pairs searched, Newton passes, map evaluations with and without
- * second derivatives, FP32 passes (mixed mode). */
+ * device-to-host copy on `stream`, which is synchronised), summed over both
+ * Newton passes (primary candidates, then the other candidates of points the
+ * primary did not settle). */
 typedef struct fpts_find_stats {
-    int64_t pairs;
-    int64_t passes;
-    int64_t evals;          /* map evaluations including the initial ones */
-    int64_t evals_h2;       /* of which with second derivatives */
+    int64_t pairs;          /* (point, element) pairs searched */
+    int64_t passes;         /* FP64 Newton passes */
+    int64_t evals;          /* FP64 map evaluations, initial ones included */
+    int64_t evals_h2;       /* of which needed second derivatives */
     int64_t passes_fp32;    /* FP32 passes of mixed mode */
     int64_t evals_fp32;     /* FP32 map evaluations of mixed mode */
+    int64_t evals_h2_exec;  /* FP64 evaluations computed with second
+                               derivatives because a lane of the wavefront
+                               needed them */
 } fpts_find_stats;
 
 int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws,

@@ -23,8 +23,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Wno-unused-command-line-argument",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
-SOURCES = ["api.cpp", "setup.cpp", "kernels_find.hip", "kernels_newton.hip",
-           "kernels_eval.hip"]
+SOURCES = ["kernels_newton_hex.hip", "kernels_newton_surf.hip", "kernels_newton_quad.hip",
+           "kernels_find.hip", "kernels_eval.hip", "api.cpp", "setup.cpp"]
 
 
 def _compile(src):

@@ -38,14 +38,14 @@ T *at(void *base, size_t off)
 }
 
 constexpr int kCounters = 64;   // ints: task counters
-constexpr int kStats = 8;       // unsigned long long
+constexpr int kStats = 8;       // unsigned long long: Newton counters
 
 void clear_events(fpts_mesh *m)
 {
     for (auto &v : m->ev) {
         for (auto &pr : v) {
-            hipEventDestroy(pr.first);
-            hipEventDestroy(pr.second);
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
         }
         v.clear();
     }
@@ -62,16 +62,16 @@ struct Span {
     {
         if (!m->profiling) return;
         if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-            hipGetLastError();
+            (void)hipGetLastError();
             a = b = nullptr;
             return;
         }
-        hipEventRecord(a, s);
+        (void)hipEventRecord(a, s);
     }
     ~Span()
     {
         if (!a) return;
-        hipEventRecord(b, s);
+        (void)hipEventRecord(b, s);
         m->ev[k].emplace_back(a, b);
     }
 };
@@ -80,12 +80,12 @@ void free_mesh(fpts_mesh *m)
 {
     if (!m) return;
     clear_events(m);
-    hipFree(m->d_nodes);
-    hipFree(m->d_nodes32);
-    hipFree(m->d_xc);
-    hipFree(m->d_box);
-    hipFree(m->d_cell_off);
-    hipFree(m->d_cell_el);
+    (void)hipFree(m->d_nodes);
+    (void)hipFree(m->d_nodes32);
+    (void)hipFree(m->d_xc);
+    (void)hipFree(m->d_box);
+    (void)hipFree(m->d_cell_off);
+    (void)hipFree(m->d_cell_el);
     delete m;
 }
 
@@ -97,21 +97,38 @@ FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
 {
     FindWs w;
     Cursor c;
-    w.cap = std::max<int64_t>(1, n * (int64_t)std::max(m->max_cell, 1));
-    w.scan_blocks = scan_tmp_blocks(std::max<int64_t>(n, m->nel));
-    w.pt_off = c.take(sizeof(int) * (n + 1));
-    w.elem_cnt = c.take(sizeof(int) * m->nel);
-    w.elem_off = c.take(sizeof(int) * (m->nel + 1));
-    w.elem_fill = c.take(sizeof(int) * m->nel);
-    w.chunk_off = c.take(sizeof(int) * (m->nel + 1));
-    w.scan_tmp = c.take(sizeof(int) * w.scan_blocks);
-    w.slot_pt = c.take(sizeof(int) * w.cap);
-    w.slot_elem = c.take(sizeof(int) * w.cap);
-    w.sorted = c.take(sizeof(int) * w.cap);
-    w.res_r = c.take(sizeof(double) * m->R * w.cap);
-    w.res_dist = c.take(sizeof(double) * w.cap);
-    w.res_code = c.take(sizeof(int) * w.cap);
-    w.counters = c.take(sizeof(int) * kCounters);
+    int64_t ncell = 1;
+    for (int d = 0; d < m->D; ++d) ncell *= m->NL;
+    w.ncell = ncell;
+    w.cap2 = std::max<int64_t>(1, n * (int64_t)std::max(m->max_cell - 1, 1));
+    w.scan_blocks = scan_tmp_blocks(std::max<int64_t>(std::max<int64_t>(n, m->nel), ncell));
+    const size_t I = sizeof(int);
+    w.cell_cnt = c.take(I * ncell);
+    w.cell_fill = c.take(I * ncell);
+    w.cell_poff = c.take(I * (ncell + 1));
+    w.cell_choff = c.take(I * (ncell + 1));
+    w.cellpt = c.take(I * n);
+    w.pbin = c.take(I * n);
+    w.ncand = c.take(I * n);
+    w.primary = c.take(I * n);
+    w.elem_cnt = c.take(I * m->nel);
+    w.elem_fill = c.take(I * m->nel);
+    w.elem_off = c.take(I * (m->nel + 1));
+    w.chunk_off = c.take(I * (m->nel + 1));
+    w.sorted = c.take(I * n);
+    w.off2 = c.take(I * (n + 1));
+    w.elem_cnt2 = c.take(I * m->nel);
+    w.elem_fill2 = c.take(I * m->nel);
+    w.elem_off2 = c.take(I * (m->nel + 1));
+    w.chunk_off2 = c.take(I * (m->nel + 1));
+    w.slot_pt = c.take(I * w.cap2);
+    w.slot_elem = c.take(I * w.cap2);
+    w.sorted2 = c.take(I * w.cap2);
+    w.res_r = c.take(sizeof(double) * m->R * w.cap2);
+    w.res_dist = c.take(sizeof(double) * w.cap2);
+    w.res_code = c.take(I * w.cap2);
+    w.scan_tmp = c.take(I * w.scan_blocks);
+    w.counters = c.take(I * kCounters);
     w.stats = c.take(sizeof(unsigned long long) * kStats);
     w.total = c.at;
     return w;
@@ -130,6 +147,15 @@ EvalWs eval_ws_layout(const fpts_mesh *m, int64_t n)
     w.counters = c.take(sizeof(int) * kCounters);
     w.total = c.at;
     return w;
+}
+
+hipError_t launch_newton(const fpts_mesh *m, int precision, int64_t n, const double *pts,
+                         const NewtonIO &io, hipStream_t s)
+{
+    const bool mixed = precision == FPTS_MIXED;
+    if (m->D == 3 && m->R == 3) return launch_newton_hex(m, mixed, n, pts, io, s);
+    if (m->D == 2 && m->R == 2) return launch_newton_quad(m, mixed, n, pts, io, s);
+    return launch_newton_surf(m, mixed, n, pts, io, s);
 }
 
 }  // namespace fpts
@@ -210,7 +236,7 @@ int fpts_setup(const fpts_params *p, const double *h_nodes, void *stream, fpts_m
               hipMalloc(&m->d_cell_off, sizeof(int) * m->cell_off.size()) == hipSuccess &&
               hipMalloc(&m->d_cell_el, sizeof(int) * m->cell_el.size()) == hipSuccess;
     if (!ok) {
-        hipGetLastError();
+        (void)hipGetLastError();
         free_mesh(m);
         return FPTS_ENOMEM;
     }
@@ -226,7 +252,7 @@ int fpts_setup(const fpts_params *p, const double *h_nodes, void *stream, fpts_m
                         hipMemcpyHostToDevice, s) == hipSuccess &&
          launch_nodes32(m, s) == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
     if (!ok) {
-        hipGetLastError();
+        (void)hipGetLastError();
         free_mesh(m);
         return FPTS_EDEVICE;
     }
@@ -237,7 +263,7 @@ int fpts_setup(const fpts_params *p, const double *h_nodes, void *stream, fpts_m
 int fpts_destroy(fpts_mesh *m)
 {
     if (!m) return FPTS_OK;
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     free_mesh(m);
     return FPTS_OK;
 }
@@ -246,7 +272,7 @@ size_t fpts_find_workspace_size(const fpts_mesh *m, int64_t n)
 {
     if (!m || n < 0 || n > INT32_MAX - 1) return 0;
     FindWs w = find_ws_layout(m, n);
-    if (w.cap > INT32_MAX) return 0;
+    if (w.cap2 > INT32_MAX) return 0;
     return w.total;
 }
 
@@ -260,50 +286,71 @@ int fpts_find(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     if (!d_pts || !d_code || !d_elem || !d_r || !d_dist || !d_ws) return FPTS_EINVAL;
     if (((uintptr_t)d_ws & 255) != 0) return FPTS_EINVAL;
     const FindWs w = find_ws_layout(m, n);
-    if (w.cap > INT32_MAX || ws_bytes < w.total) return FPTS_EINVAL;
+    if (w.cap2 > INT32_MAX || ws_bytes < w.total) return FPTS_EINVAL;
     if (sticky_error()) return FPTS_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
-    int *pt_off = at<int>(d_ws, w.pt_off);
-    int *elem_cnt = at<int>(d_ws, w.elem_cnt);
-    int *elem_off = at<int>(d_ws, w.elem_off);
-    int *elem_fill = at<int>(d_ws, w.elem_fill);
-    int *chunk_off = at<int>(d_ws, w.chunk_off);
-    int *tmp = at<int>(d_ws, w.scan_tmp);
-    int *slot_pt = at<int>(d_ws, w.slot_pt);
-    int *slot_elem = at<int>(d_ws, w.slot_elem);
-    int *sorted = at<int>(d_ws, w.sorted);
-    double *res_r = at<double>(d_ws, w.res_r);
-    double *res_dist = at<double>(d_ws, w.res_dist);
-    int *res_code = at<int>(d_ws, w.res_code);
+    int *cell_cnt = at<int>(d_ws, w.cell_cnt), *cell_fill = at<int>(d_ws, w.cell_fill);
+    int *cell_poff = at<int>(d_ws, w.cell_poff), *cell_choff = at<int>(d_ws, w.cell_choff);
+    int *cellpt = at<int>(d_ws, w.cellpt), *pbin = at<int>(d_ws, w.pbin);
+    int *ncand = at<int>(d_ws, w.ncand), *primary = at<int>(d_ws, w.primary);
+    int *elem_cnt = at<int>(d_ws, w.elem_cnt), *elem_fill = at<int>(d_ws, w.elem_fill);
+    int *elem_off = at<int>(d_ws, w.elem_off), *chunk_off = at<int>(d_ws, w.chunk_off);
+    int *sorted = at<int>(d_ws, w.sorted), *off2 = at<int>(d_ws, w.off2);
+    int *elem_cnt2 = at<int>(d_ws, w.elem_cnt2), *elem_fill2 = at<int>(d_ws, w.elem_fill2);
+    int *elem_off2 = at<int>(d_ws, w.elem_off2), *chunk_off2 = at<int>(d_ws, w.chunk_off2);
+    int *slot_pt = at<int>(d_ws, w.slot_pt), *slot_elem = at<int>(d_ws, w.slot_elem);
+    int *sorted2 = at<int>(d_ws, w.sorted2);
+    double *res_r = at<double>(d_ws, w.res_r), *res_dist = at<double>(d_ws, w.res_dist);
+    int *res_code = at<int>(d_ws, w.res_code), *tmp = at<int>(d_ws, w.scan_tmp);
     int *counters = at<int>(d_ws, w.counters);
     unsigned long long *stats = at<unsigned long long>(d_ws, w.stats);
+    const int64_t nel = m->nel, ncell = w.ncell, tb = w.scan_blocks;
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) {
         if (e == hipSuccess) e = x;
     };
-    {
+    {   // phases A and B: bin points by cell, candidates and primaries
         Span sp(m, 0, s);
-        chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
-        chk(launch_fill_i32(elem_fill, m->nel, 0, s));
+        chk(launch_fill_i32(cell_cnt, ncell, 0, s));
+        chk(launch_fill_i32(cell_fill, ncell, 0, s));
+        chk(launch_fill_i32(elem_cnt, nel, 0, s));
+        chk(launch_fill_i32(elem_fill, nel, 0, s));
+        chk(launch_fill_i32(elem_cnt2, nel, 0, s));
+        chk(launch_fill_i32(elem_fill2, nel, 0, s));
         chk(launch_fill_i32(counters, kCounters, 0, s));
         chk(launch_fill_i32(reinterpret_cast<int *>(stats), 2 * kStats, 0, s));
-        chk(launch_locate(m, 0, n, d_pts, pt_off, elem_cnt, nullptr, nullptr, nullptr, nullptr,
-                          nullptr, s));
-        chk(launch_exclusive_scan(pt_off, pt_off, n, 1, tmp, w.scan_blocks, s));
-        chk(launch_exclusive_scan(elem_cnt, elem_off, m->nel, 1, tmp, w.scan_blocks, s));
-        chk(launch_exclusive_scan(elem_cnt, chunk_off, m->nel, kChunk, tmp, w.scan_blocks, s));
-        chk(launch_locate(m, 1, n, d_pts, pt_off, nullptr, elem_off, elem_fill, slot_pt,
-                          slot_elem, sorted, s));
+        chk(launch_cell_bin(m, 0, n, d_pts, cellpt, cell_cnt, nullptr, nullptr, nullptr, ncand,
+                            primary, d_code, d_elem, d_r, d_dist, s));
+        chk(launch_exclusive_scan(cell_cnt, cell_poff, ncell, 1, tmp, tb, s));
+        chk(launch_exclusive_scan(cell_cnt, cell_choff, ncell, kChunk, tmp, tb, s));
+        chk(launch_cell_bin(m, 1, n, d_pts, cellpt, nullptr, cell_poff, cell_fill, pbin,
+                            nullptr, nullptr, d_code, d_elem, d_r, d_dist, s));
+        chk(launch_locate_cells(m, n, d_pts, pbin, cell_poff, cell_choff, ncell, ncand, primary,
+                                elem_cnt, counters + 0, d_code, d_elem, d_r, d_dist, s));
+        chk(launch_exclusive_scan(elem_cnt, elem_off, nel, 1, tmp, tb, s));
+        chk(launch_exclusive_scan(elem_cnt, chunk_off, nel, kChunk, tmp, tb, s));
+        chk(launch_primary_scatter(n, nel, primary, elem_off, elem_fill, sorted, s));
     }
-    {
+    {   // phase C: Newton on the primary candidates, results straight to the outputs
         Span sp(m, 1, s);
-        chk(launch_newton(m, precision, n, d_pts, slot_pt, sorted, elem_off, chunk_off, w.cap,
-                          res_r, res_dist, res_code, counters, stats, s));
+        NewtonIO io{sorted, elem_off, chunk_off, nullptr, d_code, d_elem, d_r, n, d_dist,
+                    counters + 1, stats};
+        chk(launch_newton(m, precision, n, d_pts, io, s));
     }
-    {
+    {   // phase D: other candidates of unsettled points, then the selection rule
         Span sp(m, 2, s);
-        chk(launch_select(m, n, pt_off, slot_elem, w.cap, res_r, res_dist, res_code, d_code,
-                          d_elem, d_r, d_dist, s));
+        chk(launch_resolve(m, 0, n, d_pts, cellpt, ncand, primary, d_code, d_r, off2, elem_cnt2,
+                           nullptr, nullptr, nullptr, nullptr, nullptr, s));
+        chk(launch_exclusive_scan(off2, off2, n, 1, tmp, tb, s));
+        chk(launch_exclusive_scan(elem_cnt2, elem_off2, nel, 1, tmp, tb, s));
+        chk(launch_exclusive_scan(elem_cnt2, chunk_off2, nel, kChunk, tmp, tb, s));
+        chk(launch_resolve(m, 1, n, d_pts, cellpt, ncand, primary, d_code, d_r, off2, nullptr,
+                           elem_off2, elem_fill2, slot_pt, slot_elem, sorted2, s));
+        NewtonIO io{sorted2, elem_off2, chunk_off2, slot_pt, res_code, nullptr, res_r, w.cap2,
+                    res_dist, counters + 2, stats};
+        chk(launch_newton(m, precision, n, d_pts, io, s));
+        chk(launch_select2(m, n, off2, primary, slot_elem, w.cap2, res_r, res_dist, res_code,
+                           d_code, d_elem, d_r, d_dist, s));
     }
     if (m->profiling) m->prof_find++;
     return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;
@@ -377,6 +424,7 @@ int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws, fpts_fi
     out->evals_h2 = (int64_t)v[3];
     out->passes_fp32 = (int64_t)v[4];
     out->evals_fp32 = (int64_t)v[5];
+    out->evals_h2_exec = (int64_t)v[6];
     return FPTS_OK;
 }
 

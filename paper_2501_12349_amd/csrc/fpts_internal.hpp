@@ -36,16 +36,38 @@ struct HashView {
 };
 
 // Byte offsets of the find workspace for n points (every array 256-aligned).
+// Phase A bins points by cell of the local map, phase B tests each cell's
+// candidates and picks a primary candidate per point, phase C runs Newton on
+// the primaries, phase D runs the remaining candidates of the points the
+// primary did not settle.
 struct FindWs {
-    size_t pt_off, elem_cnt, elem_off, elem_fill, chunk_off, scan_tmp, slot_pt,
-        slot_elem, sorted, res_r, res_dist, res_code, counters, stats, total;
-    int64_t cap;            // pair capacity
+    size_t cell_cnt, cell_fill, cell_poff, cell_choff, cellpt, pbin, ncand, primary,
+        elem_cnt, elem_fill, elem_off, chunk_off, sorted, off2, elem_cnt2, elem_fill2,
+        elem_off2, chunk_off2, slot_pt, slot_elem, sorted2, res_r, res_dist, res_code,
+        scan_tmp, counters, stats, total;
+    int64_t cap2;           // capacity for second-pass (point, candidate) pairs
     int64_t scan_blocks;
+    int64_t ncell;
 };
 
 struct EvalWs {
     size_t elem_cnt, elem_off, elem_fill, chunk_off, scan_tmp, sorted, counters,
         total;
+};
+
+// Where one Newton launch reads its work and writes its results.
+struct NewtonIO {
+    const int *list;        // bucketed item ids, element-major
+    const int *elem_off;    // [nel+1] bucket offsets into list
+    const int *chunk_off;   // [nel+1] offsets of 64-item tasks
+    const int *slot_pt;     // item -> point (nullptr: the item is the point)
+    int32_t *code;          // [item]
+    int32_t *elem;          // [item] or nullptr
+    double *r;              // [R][ostride]
+    int64_t ostride;
+    double *dist;           // [item]
+    int *counter;           // task counter (zeroed before the launch)
+    unsigned long long *stats;
 };
 
 }  // namespace fpts
@@ -90,19 +112,35 @@ hipError_t launch_fill_i32(int *p, int64_t count, int value, hipStream_t s);
 hipError_t launch_exclusive_scan(const int *in, int *out, int64_t n, int ceil_div,
                                  int *tmp, int64_t tmp_blocks, hipStream_t s);
 int64_t scan_tmp_blocks(int64_t n);
-hipError_t launch_locate(const fpts_mesh *m, int pass, int64_t n, const double *pts,
-                         int *pt_cnt_or_off, int *elem_cnt, const int *elem_off,
-                         int *elem_fill, int *slot_pt, int *slot_elem, int *sorted,
-                         hipStream_t s);
+// phase A: pass 0 counts points per cell (and writes NOT_FOUND for points
+// outside the map), pass 1 scatters point ids into cell buckets
+hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double *pts,
+                           int *cellpt, int *cell_cnt, const int *cell_poff, int *cell_fill,
+                           int *pbin, int *ncand, int *primary, int32_t *code, int32_t *elem,
+                           double *r, double *dist, hipStream_t s);
+// phase B: candidates of each point from its cell's list (one wave per 64
+// points of one cell), primary = deepest inside its OBB
+hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
+                               const int *pbin, const int *cell_poff, const int *cell_choff,
+                               int64_t ncell, int *ncand, int *primary, int *elem_cnt,
+                               int *counter, int32_t *code, int32_t *elem, double *r,
+                               double *dist, hipStream_t s);
+hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int *primary,
+                                  const int *elem_off, int *elem_fill, int *sorted,
+                                  hipStream_t s);
+// phase D: pass 0 counts the other candidates of unsettled points, pass 1
+// writes their (point, element) slots into element buckets
+hipError_t launch_resolve(const fpts_mesh *m, int pass, int64_t n, const double *pts,
+                          const int *cellpt, const int *ncand, const int *primary,
+                          const int32_t *code, const double *r, int *cnt_or_off,
+                          int *elem_cnt2, const int *elem_off2, int *elem_fill2, int *slot_pt,
+                          int *slot_elem, int *sorted2, hipStream_t s);
+hipError_t launch_select2(const fpts_mesh *m, int64_t n, const int *off2, const int *primary,
+                          const int *slot_elem, int64_t cap2, const double *res_r,
+                          const double *res_dist, const int *res_code, int32_t *code,
+                          int32_t *elem, double *r, double *dist, hipStream_t s);
 hipError_t launch_newton(const fpts_mesh *m, int precision, int64_t n, const double *pts,
-                         const int *slot_pt, const int *sorted, const int *elem_off,
-                         const int *chunk_off, int64_t cap, double *res_r, double *res_dist,
-                         int *res_code, int *counter, unsigned long long *stats,
-                         hipStream_t s);
-hipError_t launch_select(const fpts_mesh *m, int64_t n, const int *pt_off,
-                         const int *slot_elem, int64_t cap, const double *res_r,
-                         const double *res_dist, const int *res_code, int32_t *code,
-                         int32_t *elem, double *r, double *dist, hipStream_t s);
+                         const NewtonIO &io, hipStream_t s);
 hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
                            const int32_t *elem, int n_fields, double *out, int *elem_cnt,
                            const int *elem_off, int *elem_fill, int *sorted, hipStream_t s);
@@ -111,5 +149,13 @@ hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fie
                        const int *elem_off, const int *chunk_off, int *counter,
                        hipStream_t s);
 hipError_t launch_nodes32(const fpts_mesh *m, hipStream_t s);
+
+// Newton launchers per element kind (kernels_newton_*.hip)
+hipError_t launch_newton_hex(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
+                             const NewtonIO &io, hipStream_t s);
+hipError_t launch_newton_quad(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
+                              const NewtonIO &io, hipStream_t s);
+hipError_t launch_newton_surf(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
+                              const NewtonIO &io, hipStream_t s);
 
 }  // namespace fpts

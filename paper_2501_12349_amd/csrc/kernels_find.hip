@@ -1,8 +1,10 @@
-// Find, outside Newton (Section 3.2): candidate lookup in the local map
-// (Section 3.1.3) with the AABB and OBB tests (eqs. eq_AABB_test,
-// eq_OBB_test), grouping of (point, element) pairs by element, and the
-// per-point selection of the result.  Also the int32 exclusive scan and
-// fill kernels used by find and eval.
+// Find, outside Newton (Section 3.2): points are binned by cell of the local
+// map (Section 3.1.3); each cell's candidates are tested with the AABB and
+// OBB tests (eqs. eq_AABB_test, eq_OBB_test); the primary candidate of each
+// point is bucketed by element for Newton; points the primary does not
+// settle get their other candidates in a second pass and the selection rule
+// of Section 3.2.  Also the int32 exclusive scan and fill kernels used by
+// find and eval.
 #include "fpts_internal.hpp"
 
 namespace fpts {
@@ -105,105 +107,250 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int *out, int64_t n, 
 // boxes (subtract, divide, floor, clamp), so a point inside an element's AABB
 // always lands in a cell that lists the element.
 template <int D>
-__device__ inline int64_t cell_of(const HashView &h, const double *x)
+__device__ inline int cell_of(const HashView &h, const double *x)
 {
-    int64_t cell = 0, mul = 1;
+    int cell = 0, mul = 1;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         if (!__builtin_isfinite(x[d]) || !(x[d] >= h.lo[d] && x[d] <= h.hi[d])) return -1;
         double t = floor((x[d] - h.lo[d]) / h.del[d]);
         t = fmin(fmax(t, 0.0), (double)(h.NL - 1));
-        cell += mul * (int64_t)t;
+        cell += mul * (int)t;
         mul *= h.NL;
     }
     return cell;
 }
 
-// Box filter of element e (eq. eq_AABB_test, then eq. eq_OBB_test).
-template <int D>
-__device__ inline bool box_pass(const HashView &h, int e, const double *x)
+typedef const __attribute__((address_space(4))) double cdouble;
+
+// Box filter of element e (eq. eq_AABB_test, then eq. eq_OBB_test); `depth`
+// receives ||A(x - c)||_inf, the point's OBB depth (smaller = deeper).
+template <int D, typename P>
+__device__ inline bool box_pass(P rec, const double *x, double &depth)
 {
-    const double *rec = h.box + (size_t)e * (3 * D + D * D);
+    bool in = true;
 #pragma unroll
-    for (int d = 0; d < D; ++d)
-        if (!((x[d] - rec[d]) * (rec[D + d] - x[d]) >= 0.0)) return false;
+    for (int d = 0; d < D; ++d) in = in && ((x[d] - rec[d]) * (rec[D + d] - x[d]) >= 0.0);
     double y[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) y[d] = x[d] - rec[2 * D + d];
+    double mx = 0.0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         double t = 0.0;
 #pragma unroll
         for (int b = 0; b < D; ++b) t += rec[3 * D + a * D + b] * y[b];
-        if (!(fabs(t) <= 1.0)) return false;
+        mx = fmax(mx, fabs(t));
     }
-    return true;
+    depth = mx;
+    return in && (mx <= 1.0);
 }
 
-// pass 0: count candidates per point and per element.
-// pass 1: write the pairs: slot s = pt_off[p] + k for the k-th candidate
-// (ascending element id), and scatter s into its element's bucket.
+__device__ inline void write_not_found(int p, int n, int R, int32_t *code, int32_t *elem,
+                                       double *r, double *dist)
+{
+    code[p] = FPTS_NOT_FOUND;
+    elem[p] = -1;
+    dist[p] = __builtin_huge_val();
+    for (int a = 0; a < R; ++a) r[(size_t)a * n + p] = 0.0;
+}
+
+// Phase A.  pass 0: cell of each point, count per cell, NOT_FOUND for points
+// outside the map; pass 1: scatter point ids into their cell's bucket.
 template <int D>
-__global__ __launch_bounds__(256) void k_locate(HashView h, int pass, int n, const double *pts,
-                                               int *pt_cnt_or_off, int *elem_cnt,
-                                               const int *elem_off, int *elem_fill,
-                                               int *slot_pt, int *slot_elem, int *sorted)
+__global__ __launch_bounds__(256) void k_cell_bin(HashView h, int pass, int n, int R,
+                                                 const double *pts, int *cellpt, int *cell_cnt,
+                                                 const int *cell_poff, int *cell_fill,
+                                                 int *pbin, int *ncand, int *primary,
+                                                 int32_t *code, int32_t *elem, double *r,
+                                                 double *dist)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
+    if (pass == 0) {
+        double x[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = pts[(size_t)d * n + p];
+        const int c = cell_of<D>(h, x);
+        cellpt[p] = c;
+        // every point gets defined candidate data, also those no cell holds
+        ncand[p] = 0;
+        primary[p] = -1;
+        if (c < 0) write_not_found(p, n, R, code, elem, r, dist);
+        else atomicAdd(&cell_cnt[c], 1);
+    } else {
+        const int c = cellpt[p];
+        if (c >= 0) pbin[cell_poff[c] + atomicAdd(&cell_fill[c], 1)] = p;
+    }
+}
+
+// Phase B: one wavefront per task of up to 64 points of one cell.  The
+// cell's candidate list and each candidate's box record are wave-uniform and
+// read with scalar loads; every lane tests its own point.  Per point: number
+// of candidates, primary candidate (smallest OBB depth, lowest id on ties),
+// and the primary's bucket count.
+template <int D>
+__global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, const double *pts,
+                                                    const int *pbin, const int *cell_poff,
+                                                    const int *cell_choff, int ncell,
+                                                    int *ncand, int *primary, int *elem_cnt,
+                                                    int *counter, int32_t *code, int32_t *elem,
+                                                    double *r, double *dist)
+{
+    const int lane = threadIdx.x;
+    const int total = cell_choff[ncell];
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(counter, 1);
+        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
+        if (t >= total) break;
+        int lo = 0, hi = ncell;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cell_choff[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        const int c = __builtin_amdgcn_readfirstlane(lo);
+        const int beg = cell_poff[c] + (t - cell_choff[c]) * kChunk;
+        const int end = min(cell_poff[c + 1], beg + kChunk);
+        const bool has = beg + lane < end;
+        const int p = has ? pbin[beg + lane] : 0;
+        double x[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = has ? pts[(size_t)d * n + p] : 0.0;
+        const int q0 = __builtin_amdgcn_readfirstlane(h.cell_off[c]);
+        const int q1 = __builtin_amdgcn_readfirstlane(h.cell_off[c + 1]);
+        int cnt = 0, prim = -1;
+        double best = __builtin_huge_val();
+        for (int q = q0; q < q1; ++q) {
+            const int e = __builtin_amdgcn_readfirstlane(h.cell_el[q]);
+            cdouble *rec = (cdouble *)(h.box + (size_t)e * (3 * D + D * D));
+            double depth;
+            if (box_pass<D>(rec, x, depth)) {
+                ++cnt;
+                if (depth < best) {
+                    best = depth;
+                    prim = e;
+                }
+            }
+        }
+        if (has) {
+            ncand[p] = cnt;
+            primary[p] = prim;
+            if (prim >= 0) atomicAdd(&elem_cnt[prim], 1);
+            else write_not_found(p, n, R, code, elem, r, dist);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_primary_scatter(int n, int nel, const int *primary,
+                                                        const int *elem_off, int *elem_fill,
+                                                        int *sorted)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int e = primary[p];
+    if (e >= 0 && e < nel) sorted[elem_off[e] + atomicAdd(&elem_fill[e], 1)] = p;
+}
+
+// A primary result settles the point when it is INTERIOR at least `guard`
+// inside the reference box: no other element can then hold the point in its
+// interior (it would overlap the primary), so the paper's rule -- first
+// INTERIOR candidate in ascending id order -- picks the same element.
+constexpr double kSettleGuard = 1e-9;
+
+__device__ inline bool settled(int p, int n, int R, const int *ncand, const int32_t *code,
+                               const double *r)
+{
+    if (ncand[p] <= 1) return true;
+    if (code[p] != FPTS_INTERIOR) return false;
+    double m = 1.0;
+    for (int a = 0; a < R; ++a) m = fmin(m, 1.0 - fabs(r[(size_t)a * n + p]));
+    return m > kSettleGuard;
+}
+
+// Phase D.  pass 0: for unsettled points count the other candidates (and
+// per element); pass 1: write their slots (k-th other candidate in
+// ascending id at off2[p] + k) and bucket them by element.
+template <int D>
+__global__ __launch_bounds__(256) void k_resolve(HashView h, int pass, int n, int R,
+                                                const double *pts, const int *cellpt,
+                                                const int *ncand, const int *primary,
+                                                const int32_t *code, const double *r,
+                                                int *cnt_or_off, int *elem_cnt2,
+                                                const int *elem_off2, int *elem_fill2,
+                                                int *slot_pt, int *slot_elem, int *sorted2)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int prim = primary[p];
+    const bool todo = cellpt[p] >= 0 && prim >= 0 && !settled(p, n, R, ncand, code, r);
+    if (pass == 0 && !todo) {
+        cnt_or_off[p] = 0;
+        return;
+    }
+    if (!todo) return;
     double x[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) x[d] = pts[(size_t)d * n + p];
-    const int64_t cell = cell_of<D>(h, x);
+    const int c = cellpt[p];
+    const int s0 = pass ? cnt_or_off[p] : 0;
     int k = 0;
-    int s0 = pass ? pt_cnt_or_off[p] : 0;
-    if (cell >= 0) {
-        const int q0 = h.cell_off[cell], q1 = h.cell_off[cell + 1];
-        for (int q = q0; q < q1; ++q) {
-            const int e = h.cell_el[q];
-            if (!box_pass<D>(h, e, x)) continue;
-            if (pass == 0) {
-                atomicAdd(&elem_cnt[e], 1);
-            } else {
-                const int s = s0 + k;
-                slot_pt[s] = p;
-                slot_elem[s] = e;
-                sorted[elem_off[e] + atomicAdd(&elem_fill[e], 1)] = s;
-            }
-            ++k;
+    for (int q = h.cell_off[c]; q < h.cell_off[c + 1]; ++q) {
+        const int e = h.cell_el[q];
+        if (e == prim) continue;
+        double depth;
+        if (!box_pass<D>(h.box + (size_t)e * (3 * D + D * D), x, depth)) continue;
+        if (pass == 0) {
+            atomicAdd(&elem_cnt2[e], 1);
+        } else {
+            const int s = s0 + k;
+            slot_pt[s] = p;
+            slot_elem[s] = e;
+            sorted2[elem_off2[e] + atomicAdd(&elem_fill2[e], 1)] = s;
         }
+        ++k;
     }
-    if (pass == 0) pt_cnt_or_off[p] = k;
+    if (pass == 0) cnt_or_off[p] = k;
 }
 
-// Section 3.2 selection: the first INTERIOR candidate in ascending element
-// order, else the smallest distance (first on ties); NOT_FOUND without
-// candidates.
-__global__ __launch_bounds__(256) void k_select(int n, int R, const int *pt_off,
-                                               const int *slot_elem, int64_t cap,
-                                               const double *res_r, const double *res_dist,
-                                               const int *res_code, int32_t *code, int32_t *elem,
-                                               double *r, double *dist)
+// Section 3.2 selection over the primary and the other candidates of an
+// unsettled point: the lowest-id INTERIOR candidate, else the smallest
+// distance (lowest id on ties).
+__global__ __launch_bounds__(256) void k_select2(int n, int R, const int *off2,
+                                                const int *primary, const int *slot_elem,
+                                                int64_t cap2, const double *res_r,
+                                                const double *res_dist, const int *res_code,
+                                                int32_t *code, int32_t *elem, double *r,
+                                                double *dist)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const int s0 = pt_off[p], s1 = pt_off[p + 1];
+    const int s0 = off2[p], s1 = off2[p + 1];
+    if (s0 == s1) return;
+    // best so far: the primary (slot -1)
     int best = -1;
+    int bcode = code[p], belem = primary[p];
+    double bdist = dist[p];
     for (int s = s0; s < s1; ++s) {
-        if (res_code[s] == FPTS_INTERIOR) { best = s; break; }
-        if (best < 0 || res_dist[s] < res_dist[best]) best = s;
+        const int e = slot_elem[s], cd = res_code[s];
+        const double dd = res_dist[s];
+        bool take;
+        if (bcode == FPTS_INTERIOR) take = cd == FPTS_INTERIOR && e < belem;
+        else if (cd == FPTS_INTERIOR) take = true;
+        else take = dd < bdist || (dd == bdist && e < belem);
+        if (take) {
+            best = s;
+            bcode = cd;
+            belem = e;
+            bdist = dd;
+        }
     }
-    if (best < 0) {
-        code[p] = FPTS_NOT_FOUND;
-        elem[p] = -1;
-        dist[p] = __builtin_huge_val();
-        for (int a = 0; a < R; ++a) r[(size_t)a * n + p] = 0.0;
-        return;
-    }
-    code[p] = res_code[best];
-    elem[p] = slot_elem[best];
-    dist[p] = res_dist[best];
-    for (int a = 0; a < R; ++a) r[(size_t)a * n + p] = res_r[(size_t)a * cap + best];
+    if (best < 0) return;
+    code[p] = bcode;
+    elem[p] = belem;
+    dist[p] = bdist;
+    for (int a = 0; a < R; ++a) r[(size_t)a * n + p] = res_r[(size_t)a * cap2 + best];
 }
 
 inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
@@ -252,32 +399,70 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int64_t n, int ceil_di
     return hipGetLastError();
 }
 
-hipError_t launch_locate(const fpts_mesh *m, int pass, int64_t n, const double *pts,
-                         int *pt_cnt_or_off, int *elem_cnt, const int *elem_off, int *elem_fill,
-                         int *slot_pt, int *slot_elem, int *sorted, hipStream_t s)
+hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double *pts,
+                           int *cellpt, int *cell_cnt, const int *cell_poff, int *cell_fill,
+                           int *pbin, int *ncand, int *primary, int32_t *code, int32_t *elem,
+                           double *r, double *dist, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     HashView h = hash_view(m);
     const int grid = grid_for(n, 256);
-    if (m->D == 2)
-        hipLaunchKernelGGL(k_locate<2>, dim3(grid), dim3(256), 0, s, h, pass, (int)n, pts,
-                           pt_cnt_or_off, elem_cnt, elem_off, elem_fill, slot_pt, slot_elem,
-                           sorted);
-    else
-        hipLaunchKernelGGL(k_locate<3>, dim3(grid), dim3(256), 0, s, h, pass, (int)n, pts,
-                           pt_cnt_or_off, elem_cnt, elem_off, elem_fill, slot_pt, slot_elem,
-                           sorted);
+    auto k = m->D == 2 ? k_cell_bin<2> : k_cell_bin<3>;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, h, pass, (int)n, m->R, pts, cellpt,
+                       cell_cnt, cell_poff, cell_fill, pbin, ncand, primary, code, elem, r,
+                       dist);
     return hipGetLastError();
 }
 
-hipError_t launch_select(const fpts_mesh *m, int64_t n, const int *pt_off, const int *slot_elem,
-                         int64_t cap, const double *res_r, const double *res_dist,
-                         const int *res_code, int32_t *code, int32_t *elem, double *r,
-                         double *dist, hipStream_t s)
+hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
+                               const int *pbin, const int *cell_poff, const int *cell_choff,
+                               int64_t ncell, int *ncand, int *primary, int *elem_cnt,
+                               int *counter, int32_t *code, int32_t *elem, double *r,
+                               double *dist, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_select, dim3(grid_for(n, 256)), dim3(256), 0, s, (int)n, m->R, pt_off,
-                       slot_elem, cap, res_r, res_dist, res_code, code, elem, r, dist);
+    HashView h = hash_view(m);
+    auto k = m->D == 2 ? k_locate_cells<2> : k_locate_cells<3>;
+    hipLaunchKernelGGL(k, dim3(m->cus * 16), dim3(64), 0, s, h, (int)n, m->R, pts, pbin,
+                       cell_poff, cell_choff, (int)ncell, ncand, primary, elem_cnt, counter,
+                       code, elem, r, dist);
+    return hipGetLastError();
+}
+
+hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int *primary,
+                                  const int *elem_off, int *elem_fill, int *sorted,
+                                  hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_primary_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, (int)n,
+                       (int)nel, primary, elem_off, elem_fill, sorted);
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve(const fpts_mesh *m, int pass, int64_t n, const double *pts,
+                          const int *cellpt, const int *ncand, const int *primary,
+                          const int32_t *code, const double *r, int *cnt_or_off,
+                          int *elem_cnt2, const int *elem_off2, int *elem_fill2, int *slot_pt,
+                          int *slot_elem, int *sorted2, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    HashView h = hash_view(m);
+    auto k = m->D == 2 ? k_resolve<2> : k_resolve<3>;
+    hipLaunchKernelGGL(k, dim3(grid_for(n, 256)), dim3(256), 0, s, h, pass, (int)n, m->R, pts,
+                       cellpt, ncand, primary, code, r, cnt_or_off, elem_cnt2, elem_off2,
+                       elem_fill2, slot_pt, slot_elem, sorted2);
+    return hipGetLastError();
+}
+
+hipError_t launch_select2(const fpts_mesh *m, int64_t n, const int *off2, const int *primary,
+                          const int *slot_elem, int64_t cap2, const double *res_r,
+                          const double *res_dist, const int *res_code, int32_t *code,
+                          int32_t *elem, double *r, double *dist, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_select2, dim3(grid_for(n, 256)), dim3(256), 0, s, (int)n, m->R, off2,
+                       primary, slot_elem, cap2, res_r, res_dist, res_code, code, elem, r,
+                       dist);
     return hipGetLastError();
 }
 

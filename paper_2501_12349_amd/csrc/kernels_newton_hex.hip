@@ -1,0 +1,12 @@
+// Trust-region Newton kernels for hexahedral elements (D = 3, R = 3).
+#include "newton_impl.hpp"
+
+namespace fpts {
+
+hipError_t launch_newton_hex(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
+                            const NewtonIO &io, hipStream_t s)
+{
+    return newton::launch_newton_kind<3, 3>(m, mixed, n, pts, io, s);
+}
+
+}  // namespace fpts

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "fpts_internal.hpp"
+#include "gll_table.hpp"
 
 namespace fpts {
 namespace {
@@ -27,33 +28,6 @@ void leg(int n, double x, double &p, double &dp)
     p = b;
     // P_n' = n (x P_n - P_{n-1}) / (x^2 - 1), valid for |x| < 1
     dp = n * (x * b - a) / (x * x - 1.0);
-}
-
-// GLL nodes: interior roots of P'_{N-1} by Newton on P' with P'' from the
-// Legendre equation, started at Chebyshev-Gauss-Lobatto points.
-void gll_nodes(int N, double *z)
-{
-    const int n = N - 1;
-    z[0] = -1.0;
-    z[N - 1] = 1.0;
-    for (int j = 1; j < N - 1; ++j) {
-        double x = std::cos(M_PI * (N - 1 - j) / n);
-        for (int it = 0; it < 60; ++it) {
-            double p, dp;
-            leg(n, x, p, dp);
-            double ddp = (2.0 * x * dp - n * (n + 1.0) * p) / (1.0 - x * x);
-            double step = dp / ddp;
-            x -= step;
-            if (std::fabs(step) <= 1e-17) break;
-        }
-        z[j] = x;
-    }
-    for (int j = 0; j < N / 2; ++j) {
-        double h = 0.5 * (z[N - 1 - j] - z[j]);
-        z[j] = -h;
-        z[N - 1 - j] = h;
-    }
-    if (N & 1) z[N / 2] = 0.0;
 }
 
 // Gauss-Legendre rule with Q points.
@@ -453,13 +427,8 @@ int cell_coord(const fpts_mesh *m, int d, double x)
 int host_setup(fpts_mesh *m, const double *h_nodes)
 {
     const int D = m->D, N = m->N, W = box_words(D);
-    gll_nodes(N, m->basis.z);
-    for (int i = 0; i < N; ++i) {
-        double den = 1.0;
-        for (int k = 0; k < N; ++k)
-            if (k != i) den *= m->basis.z[i] - m->basis.z[k];
-        m->basis.w[i] = 1.0 / den;
-    }
+    // the same compile-time GLL table the kernels use
+    gll::fill(N, m->basis.z, m->basis.w);
     Tables T;
     make_tables(m->basis, N, T);
     m->box.assign((size_t)m->nel * W, 0.0);

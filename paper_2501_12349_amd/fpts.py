@@ -36,7 +36,8 @@ class Params(ctypes.Structure):
 class FindStats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_int64), ("passes", ctypes.c_int64),
                 ("evals", ctypes.c_int64), ("evals_h2", ctypes.c_int64),
-                ("passes_fp32", ctypes.c_int64), ("evals_fp32", ctypes.c_int64)]
+                ("passes_fp32", ctypes.c_int64), ("evals_fp32", ctypes.c_int64),
+                ("evals_h2_exec", ctypes.c_int64)]
 
 
 class KernelTimes(ctypes.Structure):
