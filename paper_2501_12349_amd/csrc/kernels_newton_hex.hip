@@ -1,5 +1,5 @@
 // Trust-region Newton kernels for hexahedral elements (D = 3, R = 3).
-#include "newton_impl.hpp"
+#include "newton_mfma.hpp"
 
 namespace fpts {
 

@@ -1,5 +1,5 @@
 // Trust-region Newton kernels for quadrilateral elements (D = 2, R = 2).
-#include "newton_impl.hpp"
+#include "newton_mfma.hpp"
 
 namespace fpts {
 

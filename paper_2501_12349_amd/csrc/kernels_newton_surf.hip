@@ -1,5 +1,5 @@
 // Trust-region Newton kernels for surface quadrilateral elements (D = 3, R = 2).
-#include "newton_impl.hpp"
+#include "newton_mfma.hpp"
 
 namespace fpts {
 

@@ -1,0 +1,852 @@
+// Trust-region Newton inversion of the element map (Section 3.2.1) for
+// (point, candidate element) pairs grouped by element, with the element-map
+// contraction on the matrix cores.  Shared by kernels_newton_*.hip.
+//
+// Task = one element and the queue of its pairs.  The wave stages the
+// element's nodal coordinates in LDS and serves 16 pairs at a time, one per
+// slot; slot s owns lanes s, s+16, s+32, s+48 (g = lane / 16 picks the
+// quarter).  When a slot's pair is done it takes the next pair of the queue.
+//
+// One map evaluation for the 16 slots at their reference points q_s:
+//   stage 1 (MFMA, v_mfma_{f64,f32}_16x16x4):
+//       C[row][s] = sum_i X[c][i][row] phi_i(q_s,0)   (and phi' / phi'')
+//     where row = (j, k) flattened (hex) or j (quad); A = node rows from LDS,
+//     B = the slot's bases (lane provides phi_i for i = 4 ks + g), so the
+//     16 MFMA columns are the 16 slots and lane l receives four rows of each
+//     16-row tile (which four depends on the instruction) for its own slot.
+//   stage 2+3 (VALU): each lane weights its rows with phi_j(s) phi_k(t) (and
+//     derivatives) of its slot, read from a per-slot LDS table, and the four
+//     lanes of a slot are summed with two xor-shuffles.  Floating-point
+//     addition is commutative, so the four lanes end with bit-identical sums
+//     and run the Newton update redundantly and in step.
+// Second derivatives (beta = 1 passes on faces/edges, eq. eq_newton_hessian)
+// are computed in a separate sweep contracted with the slot's residual dx,
+// run when enough slots wait for it (or nothing else can proceed).
+//
+// Mixed precision: the FP32 phase runs every pair of the element on FP32
+// nodes stored as offsets from the element centre (points shifted the same
+// way in FP64 before rounding) to ||dr|| < 1e-5 or 10 passes; the FP64 phase
+// then restarts each pair from that r with alpha = 1.  Codes, distances and
+// the final residual come from the FP64 phase.
+#pragma once
+#include <cfloat>
+#include <type_traits>
+
+#include "fpts_internal.hpp"
+#include "gll_table.hpp"
+
+namespace fpts {
+namespace newton {
+
+template <typename T> struct V4;
+template <> struct V4<double> { typedef double __attribute__((ext_vector_type(4))) type; };
+template <> struct V4<float> { typedef float __attribute__((ext_vector_type(4))) type; };
+
+__device__ __forceinline__ V4<double>::type mfma16(double a, double b, V4<double>::type c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ V4<float>::type mfma16(float a, float b, V4<float>::type c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T> __device__ inline T eps_of();
+template <> __device__ inline double eps_of<double>() { return DBL_EPSILON; }
+template <> __device__ inline float eps_of<float>() { return FLT_EPSILON; }
+
+template <typename T> __device__ __forceinline__ T xor_shfl(T v, int m);
+template <> __device__ __forceinline__ double xor_shfl<double>(double v, int m)
+{
+    return __shfl_xor(v, m);
+}
+template <> __device__ __forceinline__ float xor_shfl<float>(float v, int m)
+{
+    return __shfl_xor(v, m);
+}
+
+// Sum over the four lanes of a slot (lanes l, l^16, l^32, l^48).
+template <typename T>
+__device__ __forceinline__ T slot_sum(T v)
+{
+    v += xor_shfl(v, 16);
+    v += xor_shfl(v, 32);
+    return v;
+}
+
+// Row of the 16x16 output tile held by lane quarter g in item qq: the FP64
+// instruction interleaves rows (g + 4 qq), the FP32 one gives each quarter
+// four consecutive rows (4 g + qq); both checked on gfx950.
+template <typename T> __device__ __forceinline__ int out_row(int g, int qq);
+template <> __device__ __forceinline__ int out_row<double>(int g, int qq) { return g + 4 * qq; }
+template <> __device__ __forceinline__ int out_row<float>(int g, int qq) { return 4 * g + qq; }
+
+template <int D, int R, int N>
+struct Shape {
+    static constexpr int NP = (R == 3) ? N * N * N : N * N;
+    static constexpr int ROWS = (R == 3) ? N * N : N;   // contraction rows
+    static constexpr int MT = (ROWS + 15) / 16;         // 16-row tiles
+    static constexpr int KS = (N + 3) / 4;              // 4-wide K steps
+};
+
+// Packed symmetric R x R matrices: diagonal first, then the upper triangle.
+template <int R> constexpr int kSym = R * (R + 1) / 2;
+template <int R>
+__device__ constexpr int sym(int a, int b)
+{
+    if (a == b) return a;
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    return R == 2 ? 2 : (lo == 0 ? (hi == 1 ? 3 : 4) : 5);
+}
+
+// phi_i, phi_i', phi_i'' at x for ONE index i (runtime, per lane): the
+// product over m != i of (x - z_m) carried as a jet, times w_i.
+template <typename T, int N>
+__device__ __forceinline__ void basis_at(T x, int i, T &v, T &d, T &dd)
+{
+    constexpr gll::Table<N> G = gll::Nodes<N>::t;
+    T pv = T(1), pd = T(0), pdd = T(0), wi = T(0);
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+        const bool self = (m == i);
+        const T u = self ? T(1) : x - T(G.z[m]);
+        const T du = self ? T(0) : T(1);
+        pdd = pdd * u + T(2) * pd * du;
+        pd = pd * u + pv * du;
+        pv = pv * u;
+        wi = self ? T(G.w[m]) : wi;
+    }
+    v = wi * pv;
+    d = wi * pd;
+    dd = wi * pdd;
+}
+
+// All N bases of one direction at x (prefix/suffix jets), written to the
+// per-slot LDS table tab[kind][i][slot] (kind 0: phi, 1: phi', 2: phi'').
+template <typename T, int N, bool H2>
+__device__ __forceinline__ void basis_table(T x, T *tab, int slot)
+{
+    constexpr gll::Table<N> G = gll::Nodes<N>::t;
+    T pv[N], pd[N], pdd[N];
+    pv[0] = T(1);
+    pd[0] = T(0);
+    pdd[0] = T(0);
+#pragma unroll
+    for (int i = 1; i < N; ++i) {
+        const T t = x - T(G.z[i - 1]);
+        if (H2) pdd[i] = pdd[i - 1] * t + T(2) * pd[i - 1];
+        pd[i] = pd[i - 1] * t + pv[i - 1];
+        pv[i] = pv[i - 1] * t;
+    }
+    T sv = T(1), sd = T(0), sdd = T(0);
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+        tab[(0 * N + i) * 16 + slot] = T(G.w[i]) * (pv[i] * sv);
+        tab[(1 * N + i) * 16 + slot] = T(G.w[i]) * (pd[i] * sv + pv[i] * sd);
+        if (H2)
+            tab[(2 * N + i) * 16 + slot] =
+                T(G.w[i]) * (pdd[i] * sv + T(2) * pd[i] * sd + pv[i] * sdd);
+        const T t = x - T(G.z[i]);
+        if (H2) sdd = sdd * t + T(2) * sd;
+        sd = sd * t + sv;
+        sv = sv * t;
+    }
+}
+
+// LDS layout of one wave: nodes [D][NP] of type T, then the per-slot basis
+// tables of directions 1 and 2 (s, t): [2][3][N][16] of type T.
+template <typename T, int D, int R, int N>
+struct Lds {
+    static constexpr int NODES = D * Shape<D, R, N>::NP;
+    static constexpr int TAB = 3 * N * 16;
+    static constexpr size_t bytes() { return sizeof(T) * (NODES + 2 * TAB); }
+};
+
+// Sweep 1 for all 16 slots: x(q) and G = dx/dr of each slot's point.
+template <typename T, int D, int R, int N>
+__device__ __forceinline__ void sweep1(const T *xl, T *tab, int lane, const T (&q)[R], T (&X)[D],
+                                       T (&G)[D][R])
+{
+    typedef Shape<D, R, N> S;
+    typedef typename V4<T>::type v4;
+    const int slot = lane & 15, g = lane >> 4;
+    // B operand: this lane's bases in direction 0 for i = 4 ks + g
+    T b0[S::KS], b1[S::KS];
+#pragma unroll
+    for (int ks = 0; ks < S::KS; ++ks) {
+        const int i = 4 * ks + g;
+        T v, d, dd;
+        basis_at<T, N>(q[0], i, v, d, dd);
+        b0[ks] = i < N ? v : T(0);
+        b1[ks] = i < N ? d : T(0);
+    }
+    // per-slot tables of directions 1 (and 2); all four lanes of a slot
+    // write identical values
+    basis_table<T, N, false>(q[1], tab, slot);
+    if (R == 3) basis_table<T, N, false>(q[2], tab + 3 * N * 16, slot);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        X[c] = T(0);
+#pragma unroll
+        for (int a = 0; a < R; ++a) G[c][a] = T(0);
+    }
+#pragma unroll 1
+    for (int m = 0; m < S::MT; ++m) {
+        v4 acc0[D], acc1[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            acc0[c] = v4{0, 0, 0, 0};
+            acc1[c] = v4{0, 0, 0, 0};
+        }
+        const int arow = 16 * m + slot;     // A-operand row of this lane
+#pragma unroll
+        for (int ks = 0; ks < S::KS; ++ks) {
+            const int ai = 4 * ks + g;      // A-operand column (node index i)
+            const bool aok = arow < S::ROWS && ai < N;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const T a = xl[aok ? c * S::NP + ai + N * arow : 0] * T(aok ? 1 : 0);
+                acc0[c] = mfma16(a, b0[ks], acc0[c]);
+                acc1[c] = mfma16(a, b1[ks], acc1[c]);
+            }
+        }
+        // rows 4g + qq of tile m belong to this lane's slot
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const int row = 16 * m + out_row<T>(g, qq);
+            if (row >= S::ROWS) continue;
+            if constexpr (R == 3) {
+                const int j = row % N, k = row / N;
+                const T sv = tab[(0 * N + j) * 16 + slot], sd = tab[(1 * N + j) * 16 + slot];
+                const T tv = tab[3 * N * 16 + (0 * N + k) * 16 + slot];
+                const T td = tab[3 * N * 16 + (1 * N + k) * 16 + slot];
+                const T w00 = sv * tv, w10 = sd * tv, w01 = sv * td;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    X[c] = fma(acc0[c][qq], w00, X[c]);
+                    G[c][0] = fma(acc1[c][qq], w00, G[c][0]);
+                    G[c][1] = fma(acc0[c][qq], w10, G[c][1]);
+                    G[c][2] = fma(acc0[c][qq], w01, G[c][2]);
+                }
+            } else {
+                const int j = row;
+                const T sv = tab[(0 * N + j) * 16 + slot], sd = tab[(1 * N + j) * 16 + slot];
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    X[c] = fma(acc0[c][qq], sv, X[c]);
+                    G[c][0] = fma(acc1[c][qq], sv, G[c][0]);
+                    G[c][1] = fma(acc0[c][qq], sd, G[c][1]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        X[c] = slot_sum(X[c]);
+#pragma unroll
+        for (int a = 0; a < R; ++a) G[c][a] = slot_sum(G[c][a]);
+    }
+}
+
+// Sweep 2: S_ab = sum_c dx_c d2x_c/dr_a dr_b at each slot's q.
+template <typename T, int D, int R, int N>
+__device__ __forceinline__ void sweep2(const T *xl, T *tab, int lane, const T (&q)[R],
+                                       const T (&dx)[D], T (&Sout)[kSym<R>])
+{
+    typedef Shape<D, R, N> S;
+    typedef typename V4<T>::type v4;
+    const int slot = lane & 15, g = lane >> 4;
+    T b0[S::KS], b1[S::KS], b2[S::KS];
+#pragma unroll
+    for (int ks = 0; ks < S::KS; ++ks) {
+        const int i = 4 * ks + g;
+        T v, d, dd;
+        basis_at<T, N>(q[0], i, v, d, dd);
+        b0[ks] = i < N ? v : T(0);
+        b1[ks] = i < N ? d : T(0);
+        b2[ks] = i < N ? dd : T(0);
+    }
+    basis_table<T, N, true>(q[1], tab, slot);
+    if (R == 3) basis_table<T, N, true>(q[2], tab + 3 * N * 16, slot);
+    T Sa[kSym<R>];
+#pragma unroll
+    for (int a = 0; a < kSym<R>; ++a) Sa[a] = T(0);
+#pragma unroll 1
+    for (int m = 0; m < S::MT; ++m) {
+        // the slot's residual enters the B operand, so one accumulator per
+        // basis kind collects sum_c dx_c C_c[row][slot] over the coordinates
+        v4 acc0 = v4{0, 0, 0, 0}, acc1 = v4{0, 0, 0, 0}, acc2 = v4{0, 0, 0, 0};
+        const int arow = 16 * m + slot;
+#pragma unroll
+        for (int ks = 0; ks < S::KS; ++ks) {
+            const int ai = 4 * ks + g;
+            const bool aok = arow < S::ROWS && ai < N;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const T a = xl[aok ? c * S::NP + ai + N * arow : 0] * T(aok ? 1 : 0);
+                acc0 = mfma16(a, dx[c] * b0[ks], acc0);
+                acc1 = mfma16(a, dx[c] * b1[ks], acc1);
+                acc2 = mfma16(a, dx[c] * b2[ks], acc2);
+            }
+        }
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const int row = 16 * m + out_row<T>(g, qq);
+            if (row >= S::ROWS) continue;
+            const T C0 = acc0[qq], C1 = acc1[qq], C2 = acc2[qq];
+            if constexpr (R == 3) {
+                const int j = row % N, k = row / N;
+                const T sv = tab[(0 * N + j) * 16 + slot], sd = tab[(1 * N + j) * 16 + slot];
+                const T sdd = tab[(2 * N + j) * 16 + slot];
+                const T *tt = tab + 3 * N * 16;
+                const T tv = tt[(0 * N + k) * 16 + slot], td = tt[(1 * N + k) * 16 + slot];
+                const T tdd = tt[(2 * N + k) * 16 + slot];
+                Sa[0] = fma(C2, sv * tv, Sa[0]);    // rr
+                Sa[1] = fma(C0, sdd * tv, Sa[1]);   // ss
+                Sa[2] = fma(C0, sv * tdd, Sa[2]);   // tt
+                Sa[3] = fma(C1, sd * tv, Sa[3]);    // rs
+                Sa[4] = fma(C1, sv * td, Sa[4]);    // rt
+                Sa[5] = fma(C0, sd * td, Sa[5]);    // st
+            } else {
+                const int j = row;
+                const T sv = tab[(0 * N + j) * 16 + slot], sd = tab[(1 * N + j) * 16 + slot];
+                const T sdd = tab[(2 * N + j) * 16 + slot];
+                Sa[0] = fma(C2, sv, Sa[0]);         // rr
+                Sa[1] = fma(C0, sdd, Sa[1]);        // ss
+                Sa[2] = fma(C1, sd, Sa[2]);         // rs
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < kSym<R>; ++a) Sout[a] = slot_sum(Sa[a]);
+}
+
+// Objective at a point: f = |x* - x|^2, g = G^T dx, Hgn = G^T G (packed).
+template <typename T, int D, int R>
+struct Obj {
+    T f;
+    T g[R];
+    T Hgn[kSym<R>];
+};
+
+template <typename T, int D, int R>
+__device__ __forceinline__ void objective(const T (&xs)[D], const T (&X)[D], const T (&G)[D][R],
+                                          Obj<T, D, R> &o, T (&dx)[D])
+{
+    o.f = T(0);
+#pragma unroll
+    for (int a = 0; a < R; ++a) o.g[a] = T(0);
+#pragma unroll
+    for (int a = 0; a < kSym<R>; ++a) o.Hgn[a] = T(0);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        dx[c] = xs[c] - X[c];
+        o.f = fma(dx[c], dx[c], o.f);
+#pragma unroll
+        for (int a = 0; a < R; ++a) {
+            o.g[a] = fma(G[c][a], dx[c], o.g[a]);
+#pragma unroll
+            for (int b = a; b < R; ++b)
+                o.Hgn[sym<R>(a, b)] = fma(G[c][a], G[c][b], o.Hgn[sym<R>(a, b)]);
+        }
+    }
+}
+
+// Solve H dr = g on the free coordinates (rows/columns of held coordinates
+// replaced by the identity, right-hand side 0) by LDL^T; false when a pivot
+// is not positive.
+template <typename T, int R>
+__device__ __forceinline__ bool solve_free(const T (&H)[kSym<R>], const T (&g)[R],
+                                           const bool (&held)[R], T (&x)[R])
+{
+    T A[R][R], b[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+        b[a] = held[a] ? T(0) : g[a];
+#pragma unroll
+        for (int c = 0; c < R; ++c)
+            A[a][c] = (held[a] || held[c]) ? (a == c ? T(1) : T(0)) : H[sym<R>(a, c)];
+    }
+    T L[R][R], d[R];
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+        T s = A[a][a];
+#pragma unroll
+        for (int k = 0; k < a; ++k) s -= L[a][k] * L[a][k] * d[k];
+        d[a] = s;
+        ok = ok && (s > T(0));
+        const T inv = T(1) / s;
+#pragma unroll
+        for (int c = a + 1; c < R; ++c) {
+            T t = A[c][a];
+#pragma unroll
+            for (int k = 0; k < a; ++k) t -= L[c][k] * L[a][k] * d[k];
+            L[c][a] = t * inv;
+        }
+    }
+    T y[R];
+#pragma unroll
+    for (int a = 0; a < R; ++a) {
+        T s = b[a];
+#pragma unroll
+        for (int k = 0; k < a; ++k) s -= L[a][k] * y[k];
+        y[a] = s;
+    }
+#pragma unroll
+    for (int a = R - 1; a >= 0; --a) {
+        T s = y[a] / d[a];
+#pragma unroll
+        for (int k = a + 1; k < R; ++k) s -= L[k][a] * x[k];
+        x[a] = s;
+    }
+    return ok;
+}
+
+template <typename T, int R>
+__device__ __forceinline__ bool on_face(const T (&r)[R])
+{
+    bool b = false;
+#pragma unroll
+    for (int a = 0; a < R; ++a) b = b || (fabs(r[a]) == T(1));
+    return b;
+}
+
+struct NewtonArgs {
+    const double *nodes;     // [nel][D][NP]
+    const float *nodes32;    // [nel][D][NP] x - x_c (mixed mode)
+    const double *xc;        // [nel][D]     (mixed mode)
+    const double *pts;       // [D][n]
+    int n;
+    int nel;
+    NewtonIO io;             // io.r holds the start on entry, the result on exit
+    int max_iter;
+    double tol;
+    double eps_d;
+    int max_iter32;
+    float tol32;
+};
+
+enum { S_FREE = 0, S_INIT = 1, S_STEP = 2, S_WAIT = 3 };
+
+struct Counters {
+    unsigned long long pairs = 0, passes = 0, evals = 0, evals_h2 = 0, passes32 = 0,
+                       evals32 = 0, evals_h2_exec = 0;
+};
+
+// Run the iteration of Section 3.2.1 for every pair of element e (its queue
+// [q0, q1) in io.list), in precision T, 16 slots at a time.  FINAL: write
+// code/elem/dist/r (FP64 phase); otherwise write r only (FP32 phase of mixed
+// mode).  Each trip evaluates either sweep 1 at the slots' query points
+// (start points of new pairs, trial points of the others) or, when enough
+// slots wait for it, sweep 2 at the waiting slots' current points.
+template <typename T, int D, int R, int N, bool FINAL>
+__device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, int q1,
+                                            const T *xl, T *tab, int lane, int max_iter, T tol,
+                                            const double *shift, Counters &cn)
+{
+    const int slot = lane & 15;
+    const bool leader = lane < 16;
+    const NewtonIO &io = a.io;
+    int state = S_FREE, item = 0, pass = 0;
+    T xs[D], r[R], q[R], dx[D], Hs[kSym<R>], alpha = T(1), pred = T(0), dmax = T(0),
+        xnorm = T(0);
+    Obj<T, D, R> cur;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        xs[c] = T(0);
+        dx[c] = T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        r[k] = T(0);
+        q[k] = T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < kSym<R>; ++k) Hs[k] = T(0);
+    cur.f = T(0);
+#pragma unroll
+    for (int k = 0; k < R; ++k) cur.g[k] = T(0);
+#pragma unroll
+    for (int k = 0; k < kSym<R>; ++k) cur.Hgn[k] = T(0);
+    bool hb_ok = false;
+    int head = q0;
+    const int guard = (q1 - q0 + 16) * (2 * max_iter + 4);
+    for (int trip = 0; trip < guard; ++trip) {
+        // refill free slots from the element's queue
+        const unsigned long long freem = __ballot(leader && state == S_FREE);
+        const int nfree = __popcll(freem);
+        if (nfree && head < q1) {
+            if (state == S_FREE) {
+                const int rank = __popcll(freem & ((1ull << slot) - 1));
+                const int idx = head + rank;
+                if (idx < q1) {
+                    item = io.list[idx];
+                    const int p = io.slot_pt ? io.slot_pt[item] : item;
+#pragma unroll
+                    for (int c = 0; c < D; ++c)
+                        xs[c] = T(a.pts[(size_t)c * a.n + p] - (shift ? shift[c] : 0.0));
+                    // agent-scope loads: in mixed mode the FP32 phase of this
+                    // wave stored these values moments ago
+#pragma unroll
+                    for (int k = 0; k < R; ++k)
+                        r[k] = T(__hip_atomic_load(io.r + (size_t)k * io.ostride + item,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    T xn = T(0);
+#pragma unroll
+                    for (int c = 0; c < D; ++c) xn = fma(xs[c], xs[c], xn);
+                    xnorm = sqrt(xn);
+                    state = S_INIT;
+                    pass = 0;
+                    alpha = T(1);
+                    hb_ok = false;
+                    if (leader) cn.pairs++;
+                }
+            }
+            head += nfree;
+        }
+        const unsigned long long waitm = __ballot(leader && state == S_WAIT);
+        const unsigned long long stepm = __ballot(leader && (state == S_STEP || state == S_INIT));
+        if (!waitm && !stepm) break;
+        const bool do_s2 = waitm && (__popcll(waitm) >= 4 || !stepm);
+        if (do_s2) {
+            T Sn[kSym<R>];
+            sweep2<T, D, R, N>(xl, tab, lane, r, dx, Sn);
+            if (state == S_WAIT) {
+#pragma unroll
+                for (int k = 0; k < kSym<R>; ++k) Hs[k] = Sn[k];
+                hb_ok = true;
+                state = S_STEP;
+                if (leader && FINAL) cn.evals_h2++;
+            }
+            if (leader && FINAL && state != S_FREE) cn.evals_h2_exec++;
+            continue;
+        }
+        // query points: start points (INIT) or trial points (STEP)
+        if (state == S_INIT) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) q[k] = r[k];
+        } else if (state == S_STEP) {
+            const bool beta = (pass > 0) && on_face(r);
+            if (beta && !hb_ok) {
+                // a face pass needs second derivatives at r: dx at r is
+                // current (r was evaluated last), so wait for sweep 2
+                state = S_WAIT;
+            } else {
+                T H[kSym<R>];
+#pragma unroll
+                for (int k = 0; k < kSym<R>; ++k) H[k] = beta ? cur.Hgn[k] - Hs[k] : cur.Hgn[k];
+                bool held[R];
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    held[k] = (r[k] == T(1) && cur.g[k] > T(0)) ||
+                              (r[k] == T(-1) && cur.g[k] < T(0));
+                T x[R];
+                bool ok = solve_free<T, R>(H, cur.g, held, x);
+                if (!ok && beta) {
+#pragma unroll
+                    for (int k = 0; k < kSym<R>; ++k) H[k] = cur.Hgn[k];
+                    ok = solve_free<T, R>(H, cur.g, held, x);
+                }
+                T dr[R];
+                dmax = T(0);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    T d = ok ? x[k] : T(0);
+                    d = fmin(fmax(d, -alpha), alpha);
+                    const T t = fmin(fmax(r[k] + d, T(-1)), T(1));
+                    q[k] = t;
+                    dr[k] = t - r[k];
+                    dmax = fmax(dmax, fabs(dr[k]));
+                }
+                T gd = T(0), dHd = T(0);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    gd = fma(cur.g[k], dr[k], gd);
+#pragma unroll
+                    for (int b = 0; b < R; ++b) dHd = fma(dr[k] * H[sym<R>(k, b)], dr[b], dHd);
+                }
+                pred = T(2) * gd - dHd;
+            }
+        }
+        if (state != S_INIT && state != S_STEP) {
+#pragma unroll
+            for (int k = 0; k < R; ++k) q[k] = r[k];
+        }
+        T X[D], Gm[D][R], dxn[D];
+        sweep1<T, D, R, N>(xl, tab, lane, q, X, Gm);
+        Obj<T, D, R> nw;
+        objective<T, D, R>(xs, X, Gm, nw, dxn);
+        if (state == S_INIT) {
+            cur = nw;
+#pragma unroll
+            for (int c = 0; c < D; ++c) dx[c] = dxn[c];
+            hb_ok = false;
+            state = S_STEP;
+            if (leader) {
+                if (FINAL) cn.evals++;
+                else cn.evals32++;
+            }
+        } else if (state == S_STEP) {
+            ++pass;
+            if (leader) {
+                if (FINAL) {
+                    cn.evals++;
+                    cn.passes++;
+                } else {
+                    cn.evals32++;
+                    cn.passes32++;
+                }
+            }
+            bool accept, stop = false;
+            if (dmax < tol) {
+                accept = true;
+                stop = true;
+            } else {
+                const T decr = cur.f - nw.f;
+                const T sf = sqrt(cur.f);
+                const T noise = T(64) * eps_of<T>() * sf * (xnorm + sf);
+                if (pred > T(0) && pred <= noise) {
+                    accept = true;
+                } else if (pred > T(0) && decr >= T(0.9) * pred) {
+                    accept = true;
+                    alpha *= T(2);
+                } else if (pred > T(0) && decr >= T(0.01) * pred) {
+                    accept = true;
+                } else {
+                    accept = false;
+                    alpha *= T(0.25);
+                }
+            }
+            if (accept) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) r[k] = q[k];
+                cur = nw;
+#pragma unroll
+                for (int c = 0; c < D; ++c) dx[c] = dxn[c];
+                hb_ok = false;
+            }
+            if (stop || pass >= max_iter) {
+                // pair done: results out, slot free
+                if (leader) {
+                    if (FINAL) {
+                        bool inside = true;
+#pragma unroll
+                        for (int k = 0; k < R; ++k) inside = inside && (fabs(r[k]) < T(1));
+                        if (R < D) inside = inside && (cur.f < T(a.eps_d));
+                        io.code[item] = inside ? FPTS_INTERIOR : FPTS_BORDER;
+                        if (io.elem) io.elem[item] = e;
+                        io.dist[item] = sqrt((double)cur.f);
+                    }
+#pragma unroll
+                    for (int k = 0; k < R; ++k) io.r[(size_t)k * io.ostride + item] = (double)r[k];
+                }
+                state = S_FREE;
+            } else if (accept && on_face(r)) {
+                // the next pass uses beta = 1 here: wait for sweep 2
+                state = S_WAIT;
+            }
+        }
+    }
+}
+
+// Nearest element node of each pair (Euclidean; lowest node index on
+// ties), as the start of Newton (Section 3.2.1); written to io.r.  One wave
+// per task of up to 64 pairs of one element, nodes staged in LDS.
+template <typename T>
+__device__ __forceinline__ void stage(T *lds, const T *src, int count, int lane)
+{
+    typedef __attribute__((ext_vector_type(4))) unsigned int u4;
+    const int words = count * (int)sizeof(T) / 16;
+    const u4 *s = reinterpret_cast<const u4 *>(src);
+    u4 *d = reinterpret_cast<u4 *>(lds);
+    for (int k = lane; k < words; k += kWave) d[k] = s[k];
+    const int rest = count * (int)sizeof(T) - words * 16;   // 0, 4, 8 or 12 bytes
+    const unsigned *s4 = reinterpret_cast<const unsigned *>(src);
+    unsigned *d4 = reinterpret_cast<unsigned *>(lds);
+    if (lane < rest / 4) d4[words * 4 + lane] = s4[words * 4 + lane];
+    __syncthreads();
+}
+
+template <int D, int R, int N, bool MIXED>
+__global__ __launch_bounds__(64) void k_nearest(NewtonArgs a)
+{
+    typedef Shape<D, R, N> S;
+    constexpr gll::Table<N> GT = gll::Nodes<N>::t;
+    extern __shared__ double lds_raw[];
+    typedef typename std::conditional<MIXED, float, double>::type T;
+    T *xl = reinterpret_cast<T *>(lds_raw);
+    const int lane = threadIdx.x;
+    const NewtonIO &io = a.io;
+    const int total = io.chunk_off[a.nel];
+    for (;;) {
+        int t = 0;
+        if (lane == 0) t = atomicAdd(io.counter, 1);
+        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
+        if (t >= total) break;
+        int lo = 0, hi = a.nel;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (io.chunk_off[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        const int e = __builtin_amdgcn_readfirstlane(lo);
+        const int beg = io.elem_off[e] + (t - io.chunk_off[e]) * kChunk;
+        const int end = min(io.elem_off[e + 1], beg + kChunk);
+        const bool has = beg + lane < end;
+        const int item = has ? io.list[beg + lane] : 0;
+        const int p = has ? (io.slot_pt ? io.slot_pt[item] : item) : 0;
+        __syncthreads();
+        if (MIXED) stage<T>(xl, (const T *)(a.nodes32 + (size_t)e * D * S::NP), D * S::NP, lane);
+        else stage<T>(xl, (const T *)(a.nodes + (size_t)e * D * S::NP), D * S::NP, lane);
+        T xs[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            const double x = has ? a.pts[(size_t)c * a.n + p] : 0.0;
+            xs[c] = MIXED ? T(x - a.xc[(size_t)e * D + c]) : T(x);
+        }
+        T best = T(__builtin_huge_valf());
+        int bi = 0;
+#pragma unroll 1
+        for (int row = 0; row < S::ROWS; ++row) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int idx = row * N + i;
+                T d2 = T(0);
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    const T u = xs[c] - xl[c * S::NP + idx];
+                    d2 = fma(u, u, d2);
+                }
+                if (d2 < best) {
+                    best = d2;
+                    bi = idx;
+                }
+            }
+        }
+        if (has) {
+            const int ii[3] = {bi % N, (bi / N) % N, bi / (N * N)};
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                double v = GT.z[0];
+#pragma unroll
+                for (int m = 1; m < N; ++m)
+                    if (ii[k] == m) v = GT.z[m];
+                io.r[(size_t)k * io.ostride + item] = v;
+            }
+        }
+    }
+}
+
+// Newton over the element queue: one wave per element (task counter over
+// elements that have pairs).
+template <int D, int R, int N, bool MIXED>
+__global__ __launch_bounds__(64) void k_newton(NewtonArgs a)
+{
+    typedef Shape<D, R, N> S;
+    extern __shared__ double lds_raw[];
+    const int lane = threadIdx.x;
+    const NewtonIO &io = a.io;
+    Counters cn;
+    for (;;) {
+        int e = 0;
+        if (lane == 0) {
+            // next element with a non-empty queue
+            for (;;) {
+                e = atomicAdd(io.counter + 8, 1);
+                if (e >= a.nel || io.elem_off[e + 1] > io.elem_off[e]) break;
+            }
+        }
+        e = __builtin_amdgcn_readfirstlane(__shfl(e, 0));
+        if (e >= a.nel) break;
+        const int q0 = io.elem_off[e], q1 = io.elem_off[e + 1];
+        __syncthreads();
+        if constexpr (MIXED) {
+            float *xl32 = reinterpret_cast<float *>(lds_raw);
+            float *tab32 = xl32 + Lds<float, D, R, N>::NODES;
+            stage<float>(xl32, a.nodes32 + (size_t)e * D * S::NP, D * S::NP, lane);
+            run_element<float, D, R, N, false>(a, e, q0, q1, xl32, tab32, lane, a.max_iter32,
+                                               a.tol32, a.xc + (size_t)e * D, cn);
+            __threadfence();   // the FP32 results are stored before they are reloaded
+            __syncthreads();
+        }
+        double *xl = lds_raw;
+        double *tab = xl + Lds<double, D, R, N>::NODES;
+        stage<double>(xl, a.nodes + (size_t)e * D * S::NP, D * S::NP, lane);
+        run_element<double, D, R, N, true>(a, e, q0, q1, xl, tab, lane, a.max_iter, a.tol,
+                                           nullptr, cn);
+    }
+    unsigned long long v[7] = {cn.pairs, cn.passes, cn.evals, cn.evals_h2, cn.passes32,
+                               cn.evals32, cn.evals_h2_exec};
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        unsigned long long x = v[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (lane == 0 && x) atomicAdd(&io.stats[k], x);
+    }
+}
+
+typedef void (*KernelFn)(NewtonArgs);
+
+template <int D, int R, bool MIXED>
+void pick_kernels(int N, KernelFn &nn, KernelFn &nt, size_t &lds_nn, size_t &lds_nt)
+{
+#define FPTS_CASE(NN)                                                                       \
+    case NN:                                                                                \
+        nn = k_nearest<D, R, NN, MIXED>;                                                    \
+        nt = k_newton<D, R, NN, MIXED>;                                                     \
+        lds_nn = sizeof(double) * D * Shape<D, R, NN>::NP;                                  \
+        lds_nt = Lds<double, D, R, NN>::bytes();                                            \
+        break;
+    switch (N) {
+        FPTS_CASE(2)
+        FPTS_CASE(3)
+        FPTS_CASE(4)
+        FPTS_CASE(5)
+        FPTS_CASE(6)
+        FPTS_CASE(7)
+        FPTS_CASE(8)
+        FPTS_CASE(9)
+        FPTS_CASE(10)
+    default:
+        nn = nt = nullptr;
+        lds_nn = lds_nt = 0;
+    }
+#undef FPTS_CASE
+}
+
+// Two launches on the caller's stream: nearest nodes (64-pair tasks over
+// io.chunk_off, counter io.counter[0]) then Newton (element tasks, counter
+// io.counter[8]).  io.counter[0..15] must be zero.
+template <int D, int R>
+hipError_t launch_newton_kind(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
+                              const NewtonIO &io, hipStream_t s)
+{
+    KernelFn nn, nt;
+    size_t lds_nn, lds_nt;
+    if (mixed) pick_kernels<D, R, true>(m->N, nn, nt, lds_nn, lds_nt);
+    else pick_kernels<D, R, false>(m->N, nn, nt, lds_nn, lds_nt);
+    if (!nn) return hipErrorInvalidValue;
+    NewtonArgs a;
+    a.nodes = m->d_nodes;
+    a.nodes32 = m->d_nodes32;
+    a.xc = m->d_xc;
+    a.pts = pts;
+    a.n = (int)n;
+    a.nel = (int)m->nel;
+    a.io = io;
+    a.max_iter = m->p.max_iter;
+    a.tol = m->p.newton_tol;
+    a.eps_d = m->p.surf_eps_d;
+    a.max_iter32 = 10;
+    a.tol32 = 1e-5f;
+    hipLaunchKernelGGL(nn, dim3(m->cus * 16), dim3(64), lds_nn, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(nt, dim3(m->cus * 8), dim3(64), lds_nt, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace newton
+}  // namespace fpts
