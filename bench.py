@@ -48,14 +48,31 @@ def eval_flops(D, R, N, h2):
 
 
 def newton_flops(stats, D, R, N):
-    """FLOPs of one Newton launch from its exact counters: nearest-node
-    scans (3 D FLOPs per node and pair) plus every map evaluation."""
-    NP = N ** R
-    f = stats["pairs"] * NP * 3 * D
-    f += (stats["evals"] - stats["evals_h2"]) * eval_flops(D, R, N, False)
-    f += stats["evals_h2"] * eval_flops(D, R, N, True)
+    """FLOPs of one k_newton launch from its exact counters: every map
+    evaluation the iteration needs (first derivatives at each query point,
+    second derivatives where a face pass needs them), FP32 and FP64."""
+    f = stats["evals"] * eval_flops(D, R, N, False)
+    f += stats["evals_h2"] * (eval_flops(D, R, N, True) - eval_flops(D, R, N, False))
     f += stats["evals_fp32"] * eval_flops(D, R, N, False)
     return float(f)
+
+
+def nearest_flops(stats, D, R, N):
+    """FLOPs of one k_nearest launch: a squared distance (D subtractions and
+    D FMAs = 3 D FLOPs) per element node and pair."""
+    return float(stats["pairs"] * N ** R * 3 * D)
+
+
+def slot_use(stats):
+    """Fraction of busy pair slots per sweep (16 slots per wavefront)."""
+    out = {}
+    if stats["sweeps"]:
+        out["sweep1"] = round(stats["evals"] / (16.0 * stats["sweeps"]), 4)
+    if stats["sweeps_h2"]:
+        out["sweep2"] = round(stats["evals_h2"] / (16.0 * stats["sweeps_h2"]), 4)
+    if stats["sweeps_fp32"]:
+        out["fp32"] = round(stats["evals_fp32"] / (16.0 * stats["sweeps_fp32"]), 4)
+    return out
 
 
 def make_workload(name):
@@ -144,7 +161,8 @@ def main():
         for _ in range(args.warmup):
             step(mode)
         torch.cuda.synchronize()
-        stats = gm.find_stats()
+        stats = gm.find_stats(newton_pass=1)
+        stats_all = gm.find_stats()
         gm.profile(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -159,13 +177,16 @@ def main():
         newton_ms = kt["newton_ms"] / max(kt["find_calls"], 1)
         fl = newton_flops(stats, D, R, N)
         results[mode] = dict(ms_per_step=ms, mpts=n / (dt / args.steps) / 1e6, kt=kt,
-                             newton_ms=newton_ms, stats=stats, flops=fl, codes=codes)
-        log("%s: %.3f ms/step  %.1f Mpts/s  newton %.3f ms (%.1f TFLOP/s)  locate %.3f "
-            "select %.3f eval_bin %.3f eval %.3f ms/call  codes %s  stats %s" % (
+                             newton_ms=newton_ms, stats=stats, stats_all=stats_all, flops=fl,
+                             codes=codes)
+        log("%s: %.3f ms/step  %.1f Mpts/s  k_newton %.3f ms (%.1f TFLOP/s)  nearest %.3f "
+            "locate %.3f select %.3f eval_bin %.3f eval %.3f ms/call  codes %s  slots %s  "
+            "stats %s" % (
                 mode, ms, n / (dt / args.steps) / 1e6, newton_ms, fl / newton_ms / 1e9,
+                kt["nearest_ms"] / kt["find_calls"],
                 kt["locate_ms"] / kt["find_calls"], kt["select_ms"] / kt["find_calls"],
                 kt["eval_bin_ms"] / kt["eval_calls"], kt["eval_ms"] / kt["eval_calls"],
-                codes, stats))
+                codes, slot_use(stats), stats_all))
 
     main_mode = "fp64" if "fp64" in results else list(results)[0]
     r0 = results[main_mode]
@@ -190,9 +211,10 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None,
-                     "kernel": "k_newton (FP64 trust-region Newton)",
+                     "kernel": "k_newton (FP64 trust-region Newton, primary candidates)",
                      "kernel_ms": round(r0["newton_ms"], 4),
-                     "flops_per_launch": r0["flops"]},
+                     "flops_per_launch": r0["flops"],
+                     "slot_use": slot_use(r0["stats"])},
         "setup_s": round(t_setup, 3),
         "codes": dict(zip(("interior", "border", "not_found"), r0["codes"])),
     }
@@ -204,8 +226,9 @@ def main():
                          "newton_kernel_ms": round(rm["newton_ms"], 4)}
     kt = r0["kt"]
     line["kernel_ms"] = {k: round(kt[k + "_ms"] / max(kt["find_calls" if k in
-                         ("locate", "newton", "select") else "eval_calls"], 1), 4)
-                         for k in ("locate", "newton", "select", "eval_bin", "eval")}
+                         ("locate", "nearest", "newton", "select") else "eval_calls"], 1), 4)
+                         for k in ("locate", "nearest", "newton", "select", "eval_bin", "eval")}
+    line["newton_stats"] = {"primary": r0["stats"], "all": r0["stats_all"]}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, n), log)
     print(json.dumps(line), flush=True)

@@ -138,9 +138,11 @@ int fpts_eval(fpts_mesh *m, int64_t n, const int32_t *d_code,
               size_t ws_bytes, void *stream);
 
 /* Counters of the last fpts_find that used workspace d_ws (read back with a
- * device-to-host copy on `stream`, which is synchronised), summed over both
- * Newton passes (primary candidates, then the other candidates of points the
- * primary did not settle). */
+ * device-to-host copy on `stream`, which is synchronised) for one Newton
+ * pass: pass 1 = primary candidates, 2 = the other candidates of points the
+ * primary did not settle, 0 = both summed.  A sweep is one evaluation of the
+ * map by a whole wavefront at up to 16 pairs at once, so evals / (16 sweeps)
+ * is the fraction of busy pair slots.  FPTS_EINVAL for another pass. */
 typedef struct fpts_find_stats {
     int64_t pairs;          /* (point, element) pairs searched */
     int64_t passes;         /* FP64 Newton passes */
@@ -151,18 +153,25 @@ typedef struct fpts_find_stats {
     int64_t evals_h2_exec;  /* FP64 evaluations computed with second
                                derivatives because a lane of the wavefront
                                needed them */
+    int64_t sweeps;         /* FP64 first-derivative sweeps */
+    int64_t sweeps_h2;      /* FP64 second-derivative sweeps */
+    int64_t sweeps_fp32;    /* FP32 sweeps of mixed mode (both kinds) */
 } fpts_find_stats;
 
 int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws,
-                        fpts_find_stats *out, void *stream);
+                        int pass, fpts_find_stats *out, void *stream);
 
 /* Kernel timing with HIP events recorded on the caller's stream around
- * each group of kernels of fpts_find / fpts_eval: locate (both locate passes
- * and the scans), newton (the trust-region Newton kernel), select, eval
- * (point binning and interpolation).  Sums over the calls since profiling
- * was enabled.  Meant for one stream at a time. */
+ * each group of kernels of fpts_find / fpts_eval: locate (point binning,
+ * candidate search and the scans), nearest (the nearest-node start of the
+ * primary pass), newton (the trust-region Newton kernel of the primary pass
+ * alone), select (start, Newton and selection over the other candidates of
+ * unsettled points), eval_bin and eval (point binning and interpolation).
+ * Sums over the calls since profiling was enabled.  Meant for one stream at
+ * a time. */
 typedef struct fpts_kernel_times {
     double locate_ms;
+    double nearest_ms;
     double newton_ms;
     double select_ms;
     double eval_bin_ms;

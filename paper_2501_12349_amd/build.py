@@ -24,7 +24,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 SOURCES = ["kernels_newton_hex.hip", "kernels_newton_surf.hip", "kernels_newton_quad.hip",
-           "kernels_find.hip", "kernels_eval.hip", "api.cpp", "setup.cpp"]
+           "kernels_find.hip", "kernels_eval.hip", "api.cpp", "setup.cpp", "serve.cpp"]
 
 
 def _compile(src):

@@ -38,7 +38,7 @@ T *at(void *base, size_t off)
 }
 
 constexpr int kCounters = 64;   // ints: task counters
-constexpr int kStats = 8;       // unsigned long long: Newton counters
+constexpr int kStats = 16;      // unsigned long long: Newton counters per pass
 
 void clear_events(fpts_mesh *m)
 {
@@ -129,7 +129,7 @@ FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
     w.res_code = c.take(I * w.cap2);
     w.scan_tmp = c.take(I * w.scan_blocks);
     w.counters = c.take(I * kCounters);
-    w.stats = c.take(sizeof(unsigned long long) * kStats);
+    w.stats = c.take(sizeof(unsigned long long) * 2 * kStats);
     w.total = c.at;
     return w;
 }
@@ -150,12 +150,12 @@ EvalWs eval_ws_layout(const fpts_mesh *m, int64_t n)
 }
 
 hipError_t launch_newton(const fpts_mesh *m, int precision, int64_t n, const double *pts,
-                         const NewtonIO &io, hipStream_t s)
+                         const NewtonIO &io, int which, hipStream_t s)
 {
     const bool mixed = precision == FPTS_MIXED;
-    if (m->D == 3 && m->R == 3) return launch_newton_hex(m, mixed, n, pts, io, s);
-    if (m->D == 2 && m->R == 2) return launch_newton_quad(m, mixed, n, pts, io, s);
-    return launch_newton_surf(m, mixed, n, pts, io, s);
+    if (m->D == 3 && m->R == 3) return launch_newton_hex(m, mixed, n, pts, io, which, s);
+    if (m->D == 2 && m->R == 2) return launch_newton_quad(m, mixed, n, pts, io, which, s);
+    return launch_newton_surf(m, mixed, n, pts, io, which, s);
 }
 
 }  // namespace fpts
@@ -318,7 +318,7 @@ int fpts_find(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         chk(launch_fill_i32(elem_cnt2, nel, 0, s));
         chk(launch_fill_i32(elem_fill2, nel, 0, s));
         chk(launch_fill_i32(counters, kCounters, 0, s));
-        chk(launch_fill_i32(reinterpret_cast<int *>(stats), 2 * kStats, 0, s));
+        chk(launch_fill_i32(reinterpret_cast<int *>(stats), 4 * kStats, 0, s));
         chk(launch_cell_bin(m, 0, n, d_pts, cellpt, cell_cnt, nullptr, nullptr, nullptr, ncand,
                             primary, d_code, d_elem, d_r, d_dist, s));
         chk(launch_exclusive_scan(cell_cnt, cell_poff, ncell, 1, tmp, tb, s));
@@ -332,13 +332,17 @@ int fpts_find(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         chk(launch_primary_scatter(n, nel, primary, elem_off, elem_fill, sorted, s));
     }
     {   // phase C: Newton on the primary candidates, results straight to the outputs
-        Span sp(m, 1, s);
         NewtonIO io{sorted, elem_off, chunk_off, nullptr, d_code, d_elem, d_r, n, d_dist,
                     counters + 1, stats};
-        chk(launch_newton(m, precision, n, d_pts, io, s));
+        {
+            Span sp(m, 1, s);
+            chk(launch_newton(m, precision, n, d_pts, io, 1, s));
+        }
+        Span sp(m, 2, s);
+        chk(launch_newton(m, precision, n, d_pts, io, 2, s));
     }
     {   // phase D: other candidates of unsettled points, then the selection rule
-        Span sp(m, 2, s);
+        Span sp(m, 3, s);
         chk(launch_resolve(m, 0, n, d_pts, cellpt, ncand, primary, d_code, d_r, off2, elem_cnt2,
                            nullptr, nullptr, nullptr, nullptr, nullptr, s));
         chk(launch_exclusive_scan(off2, off2, n, 1, tmp, tb, s));
@@ -347,8 +351,8 @@ int fpts_find(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         chk(launch_resolve(m, 1, n, d_pts, cellpt, ncand, primary, d_code, d_r, off2, nullptr,
                            elem_off2, elem_fill2, slot_pt, slot_elem, sorted2, s));
         NewtonIO io{sorted2, elem_off2, chunk_off2, slot_pt, res_code, nullptr, res_r, w.cap2,
-                    res_dist, counters + 2, stats};
-        chk(launch_newton(m, precision, n, d_pts, io, s));
+                    res_dist, counters + 2, stats + kStats};
+        chk(launch_newton(m, precision, n, d_pts, io, 3, s));
         chk(launch_select2(m, n, off2, primary, slot_elem, w.cap2, res_r, res_dist, res_code,
                            d_code, d_elem, d_r, d_dist, s));
     }
@@ -387,7 +391,7 @@ int fpts_eval(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_t *d_e
         if (e == hipSuccess) e = x;
     };
     {
-        Span sp(m, 3, s);
+        Span sp(m, 4, s);
         chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
         chk(launch_fill_i32(elem_fill, m->nel, 0, s));
         chk(launch_fill_i32(counters, kCounters, 0, s));
@@ -399,7 +403,7 @@ int fpts_eval(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_t *d_e
                             elem_fill, sorted, s));
     }
     {
-        Span sp(m, 4, s);
+        Span sp(m, 5, s);
         chk(launch_eval(m, n, d_r, n_fields, d_field, d_out, sorted, elem_off, chunk_off,
                         counters, s));
     }
@@ -407,17 +411,19 @@ int fpts_eval(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_t *d_e
     return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;
 }
 
-int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws, fpts_find_stats *out,
-                        void *stream)
+int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws, int pass,
+                        fpts_find_stats *out, void *stream)
 {
-    if (!m || !d_ws || !out || n < 0) return FPTS_EINVAL;
+    if (!m || !d_ws || !out || n < 0 || pass < 0 || pass > 2) return FPTS_EINVAL;
     const FindWs w = find_ws_layout(m, n);
-    unsigned long long v[kStats] = {0};
+    unsigned long long both[2 * kStats] = {0}, v[kStats] = {0};
     hipStream_t s = (hipStream_t)stream;
-    if (hipMemcpyAsync(v, static_cast<const char *>(d_ws) + w.stats, sizeof(v),
+    if (hipMemcpyAsync(both, static_cast<const char *>(d_ws) + w.stats, sizeof(both),
                        hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return FPTS_EDEVICE;
+    for (int k = 0; k < kStats; ++k)
+        v[k] = (pass != 2 ? both[k] : 0) + (pass != 1 ? both[kStats + k] : 0);
     out->pairs = (int64_t)v[0];
     out->passes = (int64_t)v[1];
     out->evals = (int64_t)v[2];
@@ -425,6 +431,9 @@ int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws, fpts_fi
     out->passes_fp32 = (int64_t)v[4];
     out->evals_fp32 = (int64_t)v[5];
     out->evals_h2_exec = (int64_t)v[6];
+    out->sweeps = (int64_t)v[7];
+    out->sweeps_h2 = (int64_t)v[8];
+    out->sweeps_fp32 = (int64_t)v[9];
     return FPTS_OK;
 }
 
@@ -440,8 +449,8 @@ int fpts_profile(fpts_mesh *m, int enable)
 int fpts_profile_read(fpts_mesh *m, fpts_kernel_times *out)
 {
     if (!m || !out) return FPTS_EINVAL;
-    double ms[5] = {0, 0, 0, 0, 0};
-    for (int k = 0; k < 5; ++k)
+    double ms[kSpans] = {0};
+    for (int k = 0; k < kSpans; ++k)
         for (auto &pr : m->ev[k]) {
             float t = 0.0f;
             if (hipEventSynchronize(pr.second) != hipSuccess ||
@@ -450,10 +459,11 @@ int fpts_profile_read(fpts_mesh *m, fpts_kernel_times *out)
             ms[k] += t;
         }
     out->locate_ms = ms[0];
-    out->newton_ms = ms[1];
-    out->select_ms = ms[2];
-    out->eval_bin_ms = ms[3];
-    out->eval_ms = ms[4];
+    out->nearest_ms = ms[1];
+    out->newton_ms = ms[2];
+    out->select_ms = ms[3];
+    out->eval_bin_ms = ms[4];
+    out->eval_ms = ms[5];
     out->find_calls = m->prof_find;
     out->eval_calls = m->prof_eval;
     const bool on = m->profiling;

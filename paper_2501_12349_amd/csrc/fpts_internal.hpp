@@ -72,6 +72,10 @@ struct NewtonIO {
 
 }  // namespace fpts
 
+// profiling spans: locate, nearest-node start, Newton (primary pass), select
+// (other candidates + selection), eval binning, eval
+constexpr int kSpans = 6;
+
 struct fpts_mesh {
     fpts_params p;
     int D, R, N, NP;
@@ -88,7 +92,7 @@ struct fpts_mesh {
     int max_cell;
     // profiling: event pairs per kernel group
     bool profiling = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[5];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kSpans];
     int64_t prof_find = 0, prof_eval = 0;
     // device copies
     double *d_nodes = nullptr;    // [nel][D][NP]
@@ -139,8 +143,9 @@ hipError_t launch_select2(const fpts_mesh *m, int64_t n, const int *off2, const 
                           const int *slot_elem, int64_t cap2, const double *res_r,
                           const double *res_dist, const int *res_code, int32_t *code,
                           int32_t *elem, double *r, double *dist, hipStream_t s);
+// which: 1 = nearest-node start, 2 = Newton, 3 = both
 hipError_t launch_newton(const fpts_mesh *m, int precision, int64_t n, const double *pts,
-                         const NewtonIO &io, hipStream_t s);
+                         const NewtonIO &io, int which, hipStream_t s);
 hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
                            const int32_t *elem, int n_fields, double *out, int *elem_cnt,
                            const int *elem_off, int *elem_fill, int *sorted, hipStream_t s);
@@ -152,10 +157,10 @@ hipError_t launch_nodes32(const fpts_mesh *m, hipStream_t s);
 
 // Newton launchers per element kind (kernels_newton_*.hip)
 hipError_t launch_newton_hex(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
-                             const NewtonIO &io, hipStream_t s);
+                             const NewtonIO &io, int which, hipStream_t s);
 hipError_t launch_newton_quad(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
-                              const NewtonIO &io, hipStream_t s);
+                              const NewtonIO &io, int which, hipStream_t s);
 hipError_t launch_newton_surf(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
-                              const NewtonIO &io, hipStream_t s);
+                              const NewtonIO &io, int which, hipStream_t s);
 
 }  // namespace fpts

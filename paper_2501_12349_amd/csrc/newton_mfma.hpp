@@ -25,7 +25,7 @@
 //
 // Mixed precision: the FP32 phase runs every pair of the element on FP32
 // nodes stored as offsets from the element centre (points shifted the same
-// way in FP64 before rounding) to ||dr|| < 1e-5 or 10 passes; the FP64 phase
+// way in FP64 before rounding) to ||dr|| < 1e-6 or 10 passes; the FP64 phase
 // then restarts each pair from that r with alpha = 1.  Codes, distances and
 // the final residual come from the FP64 phase.
 #pragma once
@@ -159,7 +159,12 @@ template <typename T, int D, int R, int N>
 struct Lds {
     static constexpr int NODES = D * Shape<D, R, N>::NP;
     static constexpr int TAB = 3 * N * 16;
-    static constexpr size_t bytes() { return sizeof(T) * (NODES + 2 * TAB); }
+    // pair cache: 64 x (point coordinates D, start r R) of type T, 64 items
+    static constexpr int CACHE = 64 * (D + R);
+    static constexpr size_t bytes()
+    {
+        return sizeof(T) * (NODES + 2 * TAB + CACHE) + sizeof(int) * 64;
+    }
 };
 
 // Sweep 1 for all 16 slots: x(q) and G = dx/dr of each slot's point.
@@ -429,9 +434,11 @@ struct NewtonArgs {
 
 enum { S_FREE = 0, S_INIT = 1, S_STEP = 2, S_WAIT = 3 };
 
+// per-slot counters are kept by the slot's leader lane, per-wave (sweep)
+// counters by lane 0
 struct Counters {
     unsigned long long pairs = 0, passes = 0, evals = 0, evals_h2 = 0, passes32 = 0,
-                       evals32 = 0, evals_h2_exec = 0;
+                       evals32 = 0, evals_h2_exec = 0, sweeps = 0, sweeps_h2 = 0, sweeps32 = 0;
 };
 
 // Run the iteration of Section 3.2.1 for every pair of element e (its queue
@@ -442,8 +449,9 @@ struct Counters {
 // slots wait for it, sweep 2 at the waiting slots' current points.
 template <typename T, int D, int R, int N, bool FINAL>
 __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, int q1,
-                                            const T *xl, T *tab, int lane, int max_iter, T tol,
-                                            const double *shift, Counters &cn)
+                                            const T *xl, T *tab, T *cache, int *citem, int lane,
+                                            int max_iter, T tol, const double *shift,
+                                            Counters &cn)
 {
     const int slot = lane & 15;
     const bool leader = lane < 16;
@@ -470,28 +478,45 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
 #pragma unroll
     for (int k = 0; k < kSym<R>; ++k) cur.Hgn[k] = T(0);
     bool hb_ok = false;
-    int head = q0;
+    int head = q0, cstart = q0, cend = q0;
     const int guard = (q1 - q0 + 16) * (2 * max_iter + 4);
     for (int trip = 0; trip < guard; ++trip) {
-        // refill free slots from the element's queue
+        // refill free slots from the element's queue, through a cache of
+        // the next 64 pairs (one coalesced load per 64 pairs)
         const unsigned long long freem = __ballot(leader && state == S_FREE);
         const int nfree = __popcll(freem);
         if (nfree && head < q1) {
-            if (state == S_FREE) {
-                const int rank = __popcll(freem & ((1ull << slot) - 1));
-                const int idx = head + rank;
-                if (idx < q1) {
-                    item = io.list[idx];
-                    const int p = io.slot_pt ? io.slot_pt[item] : item;
+            if (head >= cend) {
+                cstart = head;
+                cend = min(q1, head + 64);
+                const int idx = cstart + lane;
+                if (idx < cend) {
+                    const int it = io.list[idx];
+                    const int p = io.slot_pt ? io.slot_pt[it] : it;
+                    citem[lane] = it;
 #pragma unroll
                     for (int c = 0; c < D; ++c)
-                        xs[c] = T(a.pts[(size_t)c * a.n + p] - (shift ? shift[c] : 0.0));
+                        cache[c * 64 + lane] =
+                            T(a.pts[(size_t)c * a.n + p] - (shift ? shift[c] : 0.0));
                     // agent-scope loads: in mixed mode the FP32 phase of this
                     // wave stored these values moments ago
 #pragma unroll
                     for (int k = 0; k < R; ++k)
-                        r[k] = T(__hip_atomic_load(io.r + (size_t)k * io.ostride + item,
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                        cache[(D + k) * 64 + lane] = T(__hip_atomic_load(
+                            io.r + (size_t)k * io.ostride + it, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT));
+                }
+            }
+            if (state == S_FREE) {
+                const int rank = __popcll(freem & ((1ull << slot) - 1));
+                const int idx = head + rank;
+                if (idx < cend) {
+                    const int c0 = idx - cstart;
+                    item = citem[c0];
+#pragma unroll
+                    for (int c = 0; c < D; ++c) xs[c] = cache[c * 64 + c0];
+#pragma unroll
+                    for (int k = 0; k < R; ++k) r[k] = cache[(D + k) * 64 + c0];
                     T xn = T(0);
 #pragma unroll
                     for (int c = 0; c < D; ++c) xn = fma(xs[c], xs[c], xn);
@@ -500,10 +525,10 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                     pass = 0;
                     alpha = T(1);
                     hb_ok = false;
-                    if (leader) cn.pairs++;
+                    if (leader && FINAL) cn.pairs++;
                 }
             }
-            head += nfree;
+            head = min(head + nfree, cend);
         }
         const unsigned long long waitm = __ballot(leader && state == S_WAIT);
         const unsigned long long stepm = __ballot(leader && (state == S_STEP || state == S_INIT));
@@ -512,6 +537,10 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
         if (do_s2) {
             T Sn[kSym<R>];
             sweep2<T, D, R, N>(xl, tab, lane, r, dx, Sn);
+            if (lane == 0) {
+                if (FINAL) cn.sweeps_h2++;
+                else cn.sweeps32++;
+            }
             if (state == S_WAIT) {
 #pragma unroll
                 for (int k = 0; k < kSym<R>; ++k) Hs[k] = Sn[k];
@@ -575,6 +604,10 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
         }
         T X[D], Gm[D][R], dxn[D];
         sweep1<T, D, R, N>(xl, tab, lane, q, X, Gm);
+        if (lane == 0) {
+            if (FINAL) cn.sweeps++;
+            else cn.sweeps32++;
+        }
         Obj<T, D, R> nw;
         objective<T, D, R>(xs, X, Gm, nw, dxn);
         if (state == S_INIT) {
@@ -669,7 +702,7 @@ __device__ __forceinline__ void stage(T *lds, const T *src, int count, int lane)
 }
 
 template <int D, int R, int N, bool MIXED>
-__global__ __launch_bounds__(64) void k_nearest(NewtonArgs a)
+__device__ __forceinline__ void nearest_body(const NewtonArgs &a)
 {
     typedef Shape<D, R, N> S;
     constexpr gll::Table<N> GT = gll::Nodes<N>::t;
@@ -741,10 +774,12 @@ __global__ __launch_bounds__(64) void k_nearest(NewtonArgs a)
 // Newton over the element queue: one wave per element (task counter over
 // elements that have pairs).
 template <int D, int R, int N, bool MIXED>
-__global__ __launch_bounds__(64) void k_newton(NewtonArgs a)
+__device__ __forceinline__ void newton_body(const NewtonArgs &a)
 {
     typedef Shape<D, R, N> S;
     extern __shared__ double lds_raw[];
+    int *citem = reinterpret_cast<int *>(reinterpret_cast<char *>(lds_raw) +
+                                         Lds<double, D, R, N>::bytes() - sizeof(int) * 64);
     const int lane = threadIdx.x;
     const NewtonIO &io = a.io;
     Counters cn;
@@ -764,22 +799,25 @@ __global__ __launch_bounds__(64) void k_newton(NewtonArgs a)
         if constexpr (MIXED) {
             float *xl32 = reinterpret_cast<float *>(lds_raw);
             float *tab32 = xl32 + Lds<float, D, R, N>::NODES;
+            float *cache32 = tab32 + 2 * Lds<float, D, R, N>::TAB;
             stage<float>(xl32, a.nodes32 + (size_t)e * D * S::NP, D * S::NP, lane);
-            run_element<float, D, R, N, false>(a, e, q0, q1, xl32, tab32, lane, a.max_iter32,
-                                               a.tol32, a.xc + (size_t)e * D, cn);
+            run_element<float, D, R, N, false>(a, e, q0, q1, xl32, tab32, cache32, citem, lane,
+                                               a.max_iter32, a.tol32, a.xc + (size_t)e * D, cn);
             __threadfence();   // the FP32 results are stored before they are reloaded
             __syncthreads();
         }
         double *xl = lds_raw;
         double *tab = xl + Lds<double, D, R, N>::NODES;
+        double *cache = tab + 2 * Lds<double, D, R, N>::TAB;
         stage<double>(xl, a.nodes + (size_t)e * D * S::NP, D * S::NP, lane);
-        run_element<double, D, R, N, true>(a, e, q0, q1, xl, tab, lane, a.max_iter, a.tol,
-                                           nullptr, cn);
+        run_element<double, D, R, N, true>(a, e, q0, q1, xl, tab, cache, citem, lane, a.max_iter,
+                                           a.tol, nullptr, cn);
     }
-    unsigned long long v[7] = {cn.pairs, cn.passes, cn.evals, cn.evals_h2, cn.passes32,
-                               cn.evals32, cn.evals_h2_exec};
+    unsigned long long v[10] = {cn.pairs,  cn.passes,        cn.evals,  cn.evals_h2,
+                                cn.passes32, cn.evals32,     cn.evals_h2_exec,
+                                cn.sweeps, cn.sweeps_h2, cn.sweeps32};
 #pragma unroll
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < 10; ++k) {
         unsigned long long x = v[k];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
@@ -787,15 +825,41 @@ __global__ __launch_bounds__(64) void k_newton(NewtonArgs a)
     }
 }
 
+// The primary pass and the pass over the other candidates of unsettled
+// points run the same code under two kernel names, so that a kernel trace
+// reports them apart.
+template <int D, int R, int N, bool MIXED>
+__global__ __launch_bounds__(64) void k_nearest(NewtonArgs a)
+{
+    nearest_body<D, R, N, MIXED>(a);
+}
+template <int D, int R, int N, bool MIXED>
+__global__ __launch_bounds__(64) void k_nearest_resolve(NewtonArgs a)
+{
+    nearest_body<D, R, N, MIXED>(a);
+}
+template <int D, int R, int N, bool MIXED>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_newton(NewtonArgs a)
+{
+    newton_body<D, R, N, MIXED>(a);
+}
+template <int D, int R, int N, bool MIXED>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+k_newton_resolve(NewtonArgs a)
+{
+    newton_body<D, R, N, MIXED>(a);
+}
+
 typedef void (*KernelFn)(NewtonArgs);
 
 template <int D, int R, bool MIXED>
-void pick_kernels(int N, KernelFn &nn, KernelFn &nt, size_t &lds_nn, size_t &lds_nt)
+void pick_kernels(int N, bool resolve, KernelFn &nn, KernelFn &nt, size_t &lds_nn,
+                  size_t &lds_nt)
 {
 #define FPTS_CASE(NN)                                                                       \
     case NN:                                                                                \
-        nn = k_nearest<D, R, NN, MIXED>;                                                    \
-        nt = k_newton<D, R, NN, MIXED>;                                                     \
+        nn = resolve ? k_nearest_resolve<D, R, NN, MIXED> : k_nearest<D, R, NN, MIXED>;     \
+        nt = resolve ? k_newton_resolve<D, R, NN, MIXED> : k_newton<D, R, NN, MIXED>;       \
         lds_nn = sizeof(double) * D * Shape<D, R, NN>::NP;                                  \
         lds_nt = Lds<double, D, R, NN>::bytes();                                            \
         break;
@@ -816,17 +880,19 @@ void pick_kernels(int N, KernelFn &nn, KernelFn &nt, size_t &lds_nn, size_t &lds
 #undef FPTS_CASE
 }
 
-// Two launches on the caller's stream: nearest nodes (64-pair tasks over
-// io.chunk_off, counter io.counter[0]) then Newton (element tasks, counter
-// io.counter[8]).  io.counter[0..15] must be zero.
+// Launches on the caller's stream: nearest nodes (which & 1; 64-pair tasks
+// over io.chunk_off, counter io.counter[0]), then Newton (which & 2; element
+// tasks, counter io.counter[8]).  io.counter[0..15] must be zero.  A list
+// with io.slot_pt set (other candidates) selects the *_resolve kernels.
 template <int D, int R>
 hipError_t launch_newton_kind(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
-                              const NewtonIO &io, hipStream_t s)
+                              const NewtonIO &io, int which, hipStream_t s)
 {
     KernelFn nn, nt;
     size_t lds_nn, lds_nt;
-    if (mixed) pick_kernels<D, R, true>(m->N, nn, nt, lds_nn, lds_nt);
-    else pick_kernels<D, R, false>(m->N, nn, nt, lds_nn, lds_nt);
+    const bool resolve = io.slot_pt != nullptr;
+    if (mixed) pick_kernels<D, R, true>(m->N, resolve, nn, nt, lds_nn, lds_nt);
+    else pick_kernels<D, R, false>(m->N, resolve, nn, nt, lds_nn, lds_nt);
     if (!nn) return hipErrorInvalidValue;
     NewtonArgs a;
     a.nodes = m->d_nodes;
@@ -840,12 +906,17 @@ hipError_t launch_newton_kind(const fpts_mesh *m, bool mixed, int64_t n, const d
     a.tol = m->p.newton_tol;
     a.eps_d = m->p.surf_eps_d;
     a.max_iter32 = 10;
-    a.tol32 = 1e-5f;
-    hipLaunchKernelGGL(nn, dim3(m->cus * 16), dim3(64), lds_nn, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(nt, dim3(m->cus * 8), dim3(64), lds_nt, s, a);
-    return hipGetLastError();
+    a.tol32 = 1e-6f;
+    if (which & 1) {
+        hipLaunchKernelGGL(nn, dim3(m->cus * 16), dim3(64), lds_nn, s, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (which & 2) {
+        hipLaunchKernelGGL(nt, dim3(m->cus * 8), dim3(64), lds_nt, s, a);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 }  // namespace newton

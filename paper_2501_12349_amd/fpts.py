@@ -20,6 +20,11 @@ EXPORTS = ("fpts_params_default", "fpts_setup", "fpts_destroy",
            "fpts_eval", "fpts_find_stats_get", "fpts_profile", "fpts_profile_read",
            "fpts_get_boxes", "fpts_get_hash", "fpts_status_string")
 
+# Entry points declared in include/fpts_serve.h.
+SERVE_EXPORTS = ("fpts_server_create", "fpts_server_destroy", "fpts_server_add_mesh",
+                 "fpts_server_submit", "fpts_server_poll", "fpts_server_wait",
+                 "fpts_server_drain", "fpts_server_stats_get")
+
 
 class FptsError(RuntimeError):
     pass
@@ -37,14 +42,24 @@ class FindStats(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_int64), ("passes", ctypes.c_int64),
                 ("evals", ctypes.c_int64), ("evals_h2", ctypes.c_int64),
                 ("passes_fp32", ctypes.c_int64), ("evals_fp32", ctypes.c_int64),
-                ("evals_h2_exec", ctypes.c_int64)]
+                ("evals_h2_exec", ctypes.c_int64), ("sweeps", ctypes.c_int64),
+                ("sweeps_h2", ctypes.c_int64), ("sweeps_fp32", ctypes.c_int64)]
 
 
 class KernelTimes(ctypes.Structure):
-    _fields_ = [("locate_ms", ctypes.c_double), ("newton_ms", ctypes.c_double),
+    _fields_ = [("locate_ms", ctypes.c_double), ("nearest_ms", ctypes.c_double),
+                ("newton_ms", ctypes.c_double),
                 ("select_ms", ctypes.c_double), ("eval_bin_ms", ctypes.c_double),
                 ("eval_ms", ctypes.c_double), ("find_calls", ctypes.c_int64),
                 ("eval_calls", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("points", ctypes.c_int64), ("max_in_flight", ctypes.c_int64),
+                ("max_batch_requests", ctypes.c_int64), ("peak_bytes", ctypes.c_size_t),
+                ("budget_bytes", ctypes.c_size_t)]
 
 
 _lib = None
@@ -69,7 +84,7 @@ def load_library(path=LIB_PATH):
     L.fpts_eval_workspace_size.argtypes = [vp, i64]
     L.fpts_eval_workspace_size.restype = ctypes.c_size_t
     L.fpts_eval.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
-    L.fpts_find_stats_get.argtypes = [vp, i64, vp, ctypes.POINTER(FindStats), vp]
+    L.fpts_find_stats_get.argtypes = [vp, i64, vp, i32, ctypes.POINTER(FindStats), vp]
     L.fpts_profile.argtypes = [vp, i32]
     L.fpts_profile_read.argtypes = [vp, ctypes.POINTER(KernelTimes)]
     L.fpts_get_boxes.argtypes = [vp, vp, vp, vp]
@@ -77,6 +92,16 @@ def load_library(path=LIB_PATH):
                                 ctypes.POINTER(i64), ctypes.POINTER(i32)]
     L.fpts_status_string.argtypes = [i32]
     L.fpts_status_string.restype = ctypes.c_char_p
+    L.fpts_server_create.argtypes = [ctypes.c_size_t, i32, i64, ctypes.POINTER(vp)]
+    L.fpts_server_destroy.argtypes = [vp]
+    L.fpts_server_add_mesh.argtypes = [vp, vp, i32, vp, ctypes.POINTER(i32)]
+    L.fpts_server_submit.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, i32,
+                                     ctypes.POINTER(i64)]
+    L.fpts_server_poll.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(dbl),
+                                   ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    L.fpts_server_wait.argtypes = [vp, i64]
+    L.fpts_server_drain.argtypes = [vp]
+    L.fpts_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
     _lib = L
     return L
 
@@ -180,12 +205,13 @@ class Mesh:
         self._last_find_ws = (wsb, n)
         return out
 
-    def find_stats(self, stream=None):
-        """Counters of the last find (synchronises the stream)."""
+    def find_stats(self, stream=None, newton_pass=0):
+        """Counters of the last find (synchronises the stream); newton_pass 1 =
+        primary candidates, 2 = other candidates, 0 = both."""
         wsb, n = self._last_find_ws
         st = FindStats()
-        _check(load_library().fpts_find_stats_get(self._h, n, _dptr(wsb), ctypes.byref(st),
-                                                  _stream_ptr(stream)))
+        _check(load_library().fpts_find_stats_get(self._h, n, _dptr(wsb), int(newton_pass),
+                                                  ctypes.byref(st), _stream_ptr(stream)))
         return {k: getattr(st, k) for k, _ in FindStats._fields_}
 
     # -- Interpolate
@@ -239,3 +265,91 @@ class Mesh:
                                             de.ctypes.data, ctypes.byref(nl),
                                             ctypes.byref(nnz), ctypes.byref(mc)))
         return dict(NL=nl.value, lo=lo, hi=hi, delta=de, nnz=nnz.value, max_cell=mc.value)
+
+
+class Server:
+    """Request loop over resident meshes (include/fpts_serve.h): requests
+    are admitted by device memory, same-mesh requests batched into one
+    find + eval launch set, batches overlapped on n_streams streams."""
+
+    def __init__(self, budget_bytes, n_streams=4, max_batch_points=1 << 22):
+        import torch
+        if not torch.cuda.is_available():
+            raise FptsError("no HIP device visible")
+        L = load_library()
+        h = ctypes.c_void_p()
+        _check(L.fpts_server_create(int(budget_bytes), n_streams, max_batch_points,
+                                    ctypes.byref(h)))
+        self._h = h
+        self._meshes = []
+        self._live = {}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().fpts_server_destroy(self._h)
+        self._h = None
+        self._live = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_mesh(self, mesh, field=None):
+        """Register a resident Mesh with its fields ([n_fields][n_elem][NP]
+        float64 on the device, or None); returns the mesh id."""
+        nf = 0
+        fp = ctypes.c_void_p()
+        if field is not None:
+            if field.dim() == 2:
+                field = field.unsqueeze(0)
+            field = field.contiguous()
+            nf = field.shape[0]
+            fp = _dptr(field)
+        mid = ctypes.c_int()
+        _check(load_library().fpts_server_add_mesh(self._h, mesh._h, nf, fp, ctypes.byref(mid)))
+        self._meshes.append((mesh, field, nf))
+        return mid.value
+
+    def submit(self, mesh_id, pts, precision="fp64"):
+        """Queue find + eval of pts ([dim][n] float64 on the device); returns
+        (request id, output dict)."""
+        import torch
+        mesh, field, nf = self._meshes[mesh_id]
+        pts = pts.contiguous()
+        n = pts.shape[1]
+        dev = pts.device
+        out = dict(code=torch.empty(n, dtype=torch.int32, device=dev),
+                   elem=torch.empty(n, dtype=torch.int32, device=dev),
+                   r=torch.empty((mesh.ref_dim, n), dtype=torch.float64, device=dev),
+                   dist=torch.empty(n, dtype=torch.float64, device=dev),
+                   u=torch.empty((max(nf, 1), n), dtype=torch.float64, device=dev))
+        rid = ctypes.c_int64()
+        _check(load_library().fpts_server_submit(
+            self._h, mesh_id, n, _dptr(pts), _dptr(out["code"]), _dptr(out["elem"]),
+            _dptr(out["r"]), _dptr(out["dist"]), _dptr(out["u"]) if nf else ctypes.c_void_p(),
+            _PREC[precision], ctypes.byref(rid)))
+        self._live[rid.value] = (pts, out)
+        return rid.value, out
+
+    def poll(self, rid):
+        st = ctypes.c_int()
+        t = [ctypes.c_double() for _ in range(3)]
+        _check(load_library().fpts_server_poll(self._h, rid, ctypes.byref(st),
+                                               *[ctypes.byref(x) for x in t]))
+        return st.value, t[0].value, t[1].value, t[2].value
+
+    def wait(self, rid):
+        _check(load_library().fpts_server_wait(self._h, rid))
+
+    def drain(self):
+        _check(load_library().fpts_server_drain(self._h))
+
+    def release(self, rid):
+        self._live.pop(rid, None)
+
+    def stats(self):
+        st = ServerStats()
+        _check(load_library().fpts_server_stats_get(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}

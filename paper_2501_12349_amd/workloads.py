@@ -95,26 +95,43 @@ def poly_coeffs(D, deg, rng):
     return terms
 
 
-def poly_eval(terms, X, chunk=1 << 22):
-    """Evaluate a polynomial given by ``poly_coeffs`` at points X [D][...]."""
+def _poly_chunk(terms, blk, deg):
+    D = blk.shape[0]
+    pw = [[np.ones(blk.shape[1])] for _ in range(D)]
+    for d in range(D):
+        for _ in range(deg):
+            pw[d].append(pw[d][-1] * blk[d])
+    acc = np.zeros(blk.shape[1])
+    for e, c in terms:
+        t = c * pw[0][e[0]]
+        for d in range(1, D):
+            t = t * pw[d][e[d]]
+        acc += t
+    return acc
+
+
+def poly_eval(terms, X, chunk=1 << 20):
+    """Evaluate a polynomial given by ``poly_coeffs`` at points X [D][...]
+    (chunks in a thread pool; numpy releases the GIL on array arithmetic)."""
+    import concurrent.futures as cf
+    import os
     X = np.asarray(X)
     D = X.shape[0]
     flat = X.reshape(D, -1)
     out = np.empty(flat.shape[1])
     deg = max(sum(e) for e, _ in terms)
-    for s in range(0, flat.shape[1], chunk):
-        blk = flat[:, s:s + chunk]
-        pw = [[np.ones(blk.shape[1])] for _ in range(D)]
-        for d in range(D):
-            for _ in range(deg):
-                pw[d].append(pw[d][-1] * blk[d])
-        acc = np.zeros(blk.shape[1])
-        for e, c in terms:
-            t = c * pw[0][e[0]]
-            for d in range(1, D):
-                t = t * pw[d][e[d]]
-            acc += t
-        out[s:s + chunk] = acc
+    starts = list(range(0, flat.shape[1], chunk))
+    nthreads = max(1, min(16, os.cpu_count() or 1, len(starts)))
+
+    def work(s0):
+        out[s0:s0 + chunk] = _poly_chunk(terms, flat[:, s0:s0 + chunk], deg)
+
+    if nthreads == 1:
+        for s0 in starts:
+            work(s0)
+    else:
+        with cf.ThreadPoolExecutor(nthreads) as ex:
+            list(ex.map(work, starts))
     return out.reshape(X.shape[1:])
 
 

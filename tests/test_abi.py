@@ -17,8 +17,8 @@ def _lib():
     return fpts, fpts.load_library()
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "fpts.h")).read()
+def _declared(header="fpts.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(fpts_\w+)\s*\(", src)))
 
@@ -26,11 +26,12 @@ def _declared():
 def test_header_declares_the_binding_exports():
     fpts, _ = _lib()
     assert _declared() == sorted(fpts.EXPORTS)
+    assert _declared("fpts_serve.h") == sorted(fpts.SERVE_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol():
     _, L = _lib()
-    for name in _declared():
+    for name in _declared() + _declared("fpts_serve.h"):
         assert hasattr(L, name), name
 
 
@@ -63,3 +64,14 @@ def test_null_handles_are_rejected():
     assert L.fpts_eval(None, 10, None, None, None, 1, None, None, None, 0, None) == -1
     assert L.fpts_find_workspace_size(None, 10) == 0
     assert L.fpts_destroy(None) == 0
+
+
+@pytest.mark.parametrize("budget,streams,maxb", [(1 << 10, 2, 1000), (1 << 30, 0, 1000),
+                                                 (1 << 30, 17, 1000), (1 << 30, 2, 0)])
+def test_server_rejects_bad_arguments_without_device(budget, streams, maxb):
+    _, L = _lib()
+    h = ctypes.c_void_p()
+    assert L.fpts_server_create(budget, streams, maxb, ctypes.byref(h)) == -1
+    assert not h.value
+    assert L.fpts_server_destroy(None) == 0
+    assert L.fpts_server_submit(None, 0, 10, None, None, None, None, None, None, 0, None) == -1
