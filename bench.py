@@ -110,19 +110,93 @@ def cpu_baseline(wl, sample, log_):
                            0 if wl.get("fields") is None else wl["fields"].shape[0], t, t_setup))
 
 
+def pcie_inclusive(gm, wl, fields, ws_f, ws_e, mode, steps):
+    """Points from pinned host memory to results in pinned host memory:
+    H2D of the points, find + eval, D2H of code/elem/r/dist/u, on one
+    stream."""
+    import torch
+    n = wl["pts"].shape[1]
+    R = wl["ref_dim"]
+    nf = fields.shape[0]
+    dev = fields.device
+    h_pts = torch.from_numpy(wl["pts"]).pin_memory()
+    h_out = dict(code=torch.empty(n, dtype=torch.int32).pin_memory(),
+                 elem=torch.empty(n, dtype=torch.int32).pin_memory(),
+                 r=torch.empty((R, n), dtype=torch.float64).pin_memory(),
+                 dist=torch.empty(n, dtype=torch.float64).pin_memory(),
+                 u=torch.empty((nf, n), dtype=torch.float64).pin_memory())
+    d_pts = torch.empty_like(h_pts, device=dev)
+    d_out = {k: torch.empty_like(v, device=dev) for k, v in h_out.items()}
+
+    def once():
+        d_pts.copy_(h_pts, non_blocking=True)
+        res = {k: d_out[k] for k in ("code", "elem", "r", "dist")}
+        gm.find(d_pts, precision=mode, out=res, ws=ws_f)
+        gm.eval(res, fields, out=d_out["u"], ws=ws_e)
+        for k in h_out:
+            h_out[k].copy_(d_out[k], non_blocking=True)
+
+    once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        once()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    moved = h_pts.numel() * 8 + sum(v.numel() * v.element_size() for v in h_out.values())
+    return dict(value=round(n / dt / 1e6, 3), unit="Mpts/s", ms_per_step=round(dt * 1e3, 3),
+                steps=steps, precision=mode, bytes_over_pcie=int(moved))
+
+
+def serving(n_req, budget):
+    """The request loop over four resident curved hex meshes (p = 3, 5, 7,
+    9; 46^3, 36^3, 27^3, 22^3 elements), Poisson arrivals of find + eval
+    requests with 10^U(3,6) points, mixed precision; p50/p99 latency at
+    0.5 / 0.8 / 1.0 / 1.2 x the saturated request rate."""
+    from paper_2501_12349_amd import fpts
+    from paper_2501_12349_amd import serve as SV
+    t0 = time.perf_counter()
+    meshes = SV.build_meshes(scale=1.0)
+    sizes, mids, pts = SV.make_requests(n_req)
+    log("serving: 4 meshes + %d requests (%d points) ready in %.1f s" % (
+        n_req, int(sizes.sum()), time.perf_counter() - t0))
+    srv = fpts.Server(budget, n_streams=4, max_batch_points=1 << 22)
+    ids = [srv.add_mesh(m, f) for _, m, f in meshes]
+    rep = SV.sweep(srv, ids, sizes, mids, pts)
+    srv.close()
+    for r in rep["loads"]:
+        log("serving load %.1f: %.0f req/s  p50 %.2f ms  p99 %.2f ms  %.1f Mpts/s" % (
+            r["load"], r["rate_req_s"], r["p50_ms"], r["p99_ms"], r["mpts_s"]))
+    rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+    return dict(meshes=[wl["name"] for wl, _, _ in meshes], requests=n_req,
+                points=int(sizes.sum()), precision="mixed", budget_bytes=budget, n_streams=4,
+                saturation=rnd(rep["saturation"]),
+                saturated_rate_req_s=round(rep["saturated_rate_req_s"], 2),
+                loads=[rnd(r) for r in rep["loads"]], batches=rep["batches"],
+                max_batch_requests=rep["max_batch_requests"],
+                max_in_flight=rep["max_in_flight"], peak_bytes=rep["peak_bytes"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="hex48")
-    ap.add_argument("--cpu-sample", type=int, default=60000)
+    ap.add_argument("--cpu-sample", type=int, default=4000000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests per serving run (0: no serving measurement)")
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--pcie-steps", type=int, default=3,
+                    help="steps of the host-to-host measurement (0: skip)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a 1 GiB device copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU: the find/eval path has no "
-              "multi-GPU mode (see DESIGN.md for how it would shard)", file=sys.stderr)
+              "multi-GPU mode (points would shard across GPUs with the mesh replicated)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -156,13 +230,20 @@ def main():
         gm.find(pts, precision=prec, out=out, ws=ws_f)
         gm.eval(out, fields, out=u, ws=ws_e)
 
+    if args.calib_copy:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per byte
+        # scales the counters of the other kernels
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     results = {}
     for mode in args.modes.split(","):
         for _ in range(args.warmup):
             step(mode)
         torch.cuda.synchronize()
-        stats = gm.find_stats(newton_pass=1)
-        stats_all = gm.find_stats()
         gm.profile(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -172,6 +253,9 @@ def main():
         dt = time.perf_counter() - t0
         kt = gm.profile_read()
         gm.profile(False)
+        # counters of the last find (the iteration counts are deterministic)
+        stats = gm.find_stats(newton_pass=1)
+        stats_all = gm.find_stats()
         codes = torch.bincount(out["code"].long(), minlength=3).cpu().tolist()
         ms = dt / args.steps * 1e3
         newton_ms = kt["newton_ms"] / max(kt["find_calls"], 1)
@@ -229,6 +313,15 @@ def main():
                          ("locate", "nearest", "newton", "select") else "eval_calls"], 1), 4)
                          for k in ("locate", "nearest", "newton", "select", "eval_bin", "eval")}
     line["newton_stats"] = {"primary": r0["stats"], "all": r0["stats_all"]}
+    if args.pcie_steps > 0:
+        line["pcie_inclusive"] = pcie_inclusive(gm, wl, fields, ws_f, ws_e, main_mode,
+                                                args.pcie_steps)
+        log("host-to-host (PCIe copies included): %.1f Mpts/s" %
+            line["pcie_inclusive"]["value"])
+    del ws_f, ws_e, out, u, pts
+    torch.cuda.empty_cache()
+    if args.serve_requests > 0:
+        line["serving"] = serving(args.serve_requests, int(args.serve_budget_gb * (1 << 30)))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, n), log)
     print(json.dumps(line), flush=True)

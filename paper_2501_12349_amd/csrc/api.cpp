@@ -37,7 +37,9 @@ T *at(void *base, size_t off)
     return reinterpret_cast<T *>(static_cast<char *>(base) + off);
 }
 
-constexpr int kCounters = 64;   // ints: task counters
+constexpr int kCounters = 64;   // ints: element-queue counters of the Newton passes
+constexpr int kNewtonCounters = 16;   // each Newton pass owns 16 counters from here on
+static_assert(3 * kNewtonCounters <= kCounters, "the two Newton passes need disjoint counters");
 constexpr int kStats = 16;      // unsigned long long: Newton counters per pass
 
 void clear_events(fpts_mesh *m)
@@ -127,6 +129,12 @@ FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
     w.res_r = c.take(sizeof(double) * m->R * w.cap2);
     w.res_dist = c.take(sizeof(double) * w.cap2);
     w.res_code = c.take(I * w.cap2);
+    w.tb_cell = task_bound(n, ncell);
+    w.tb_elem = task_bound(n, m->nel);
+    w.tb_elem2 = task_bound(w.cap2, m->nel);
+    w.task_cell = c.take(I * w.tb_cell);
+    w.task_elem = c.take(I * w.tb_elem);
+    w.task_elem2 = c.take(I * w.tb_elem2);
     w.scan_tmp = c.take(I * w.scan_blocks);
     w.counters = c.take(I * kCounters);
     w.stats = c.take(sizeof(unsigned long long) * 2 * kStats);
@@ -144,7 +152,8 @@ EvalWs eval_ws_layout(const fpts_mesh *m, int64_t n)
     w.chunk_off = c.take(sizeof(int) * (m->nel + 1));
     w.scan_tmp = c.take(sizeof(int) * scan_tmp_blocks(m->nel));
     w.sorted = c.take(sizeof(int) * std::max<int64_t>(n, 1));
-    w.counters = c.take(sizeof(int) * kCounters);
+    w.tb_elem = task_bound(n, m->nel);
+    w.task_elem = c.take(sizeof(int) * w.tb_elem);
     w.total = c.at;
     return w;
 }
@@ -303,6 +312,8 @@ int fpts_find(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     double *res_r = at<double>(d_ws, w.res_r), *res_dist = at<double>(d_ws, w.res_dist);
     int *res_code = at<int>(d_ws, w.res_code), *tmp = at<int>(d_ws, w.scan_tmp);
     int *counters = at<int>(d_ws, w.counters);
+    int *task_cell = at<int>(d_ws, w.task_cell), *task_elem = at<int>(d_ws, w.task_elem);
+    int *task_elem2 = at<int>(d_ws, w.task_elem2);
     unsigned long long *stats = at<unsigned long long>(d_ws, w.stats);
     const int64_t nel = m->nel, ncell = w.ncell, tb = w.scan_blocks;
     hipError_t e = hipSuccess;
@@ -323,17 +334,20 @@ int fpts_find(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
                             primary, d_code, d_elem, d_r, d_dist, s));
         chk(launch_exclusive_scan(cell_cnt, cell_poff, ncell, 1, tmp, tb, s));
         chk(launch_exclusive_scan(cell_cnt, cell_choff, ncell, kChunk, tmp, tb, s));
+        chk(launch_task_map(cell_choff, ncell, task_cell, s));
         chk(launch_cell_bin(m, 1, n, d_pts, cellpt, nullptr, cell_poff, cell_fill, pbin,
                             nullptr, nullptr, d_code, d_elem, d_r, d_dist, s));
-        chk(launch_locate_cells(m, n, d_pts, pbin, cell_poff, cell_choff, ncell, ncand, primary,
-                                elem_cnt, counters + 0, d_code, d_elem, d_r, d_dist, s));
+        chk(launch_locate_cells(m, n, d_pts, pbin, cell_poff, cell_choff, ncell, task_cell,
+                                w.tb_cell, ncand, primary, elem_cnt, d_code, d_elem, d_r, d_dist,
+                                s));
         chk(launch_exclusive_scan(elem_cnt, elem_off, nel, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt, chunk_off, nel, kChunk, tmp, tb, s));
+        chk(launch_task_map(chunk_off, nel, task_elem, s));
         chk(launch_primary_scatter(n, nel, primary, elem_off, elem_fill, sorted, s));
     }
     {   // phase C: Newton on the primary candidates, results straight to the outputs
         NewtonIO io{sorted, elem_off, chunk_off, nullptr, d_code, d_elem, d_r, n, d_dist,
-                    counters + 1, stats};
+                    counters + kNewtonCounters, stats, task_elem, w.tb_elem};
         {
             Span sp(m, 1, s);
             chk(launch_newton(m, precision, n, d_pts, io, 1, s));
@@ -348,10 +362,12 @@ int fpts_find(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         chk(launch_exclusive_scan(off2, off2, n, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt2, elem_off2, nel, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt2, chunk_off2, nel, kChunk, tmp, tb, s));
+        chk(launch_task_map(chunk_off2, nel, task_elem2, s));
         chk(launch_resolve(m, 1, n, d_pts, cellpt, ncand, primary, d_code, d_r, off2, nullptr,
                            elem_off2, elem_fill2, slot_pt, slot_elem, sorted2, s));
         NewtonIO io{sorted2, elem_off2, chunk_off2, slot_pt, res_code, nullptr, res_r, w.cap2,
-                    res_dist, counters + 2, stats + kStats};
+                    res_dist, counters + 2 * kNewtonCounters, stats + kStats, task_elem2,
+                    w.tb_elem2};
         chk(launch_newton(m, precision, n, d_pts, io, 3, s));
         chk(launch_select2(m, n, off2, primary, slot_elem, w.cap2, res_r, res_dist, res_code,
                            d_code, d_elem, d_r, d_dist, s));
@@ -384,7 +400,7 @@ int fpts_eval(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_t *d_e
     int *chunk_off = at<int>(d_ws, w.chunk_off);
     int *tmp = at<int>(d_ws, w.scan_tmp);
     int *sorted = at<int>(d_ws, w.sorted);
-    int *counters = at<int>(d_ws, w.counters);
+    int *task_elem = at<int>(d_ws, w.task_elem);
     const int64_t tb = scan_tmp_blocks(m->nel);
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) {
@@ -394,18 +410,18 @@ int fpts_eval(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_t *d_e
         Span sp(m, 4, s);
         chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
         chk(launch_fill_i32(elem_fill, m->nel, 0, s));
-        chk(launch_fill_i32(counters, kCounters, 0, s));
         chk(launch_eval_bin(m, 0, n, d_code, d_elem, n_fields, d_out, elem_cnt, nullptr, nullptr,
                             nullptr, s));
         chk(launch_exclusive_scan(elem_cnt, elem_off, m->nel, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt, chunk_off, m->nel, kChunk, tmp, tb, s));
+        chk(launch_task_map(chunk_off, m->nel, task_elem, s));
         chk(launch_eval_bin(m, 1, n, d_code, d_elem, n_fields, d_out, nullptr, elem_off,
                             elem_fill, sorted, s));
     }
     {
         Span sp(m, 5, s);
         chk(launch_eval(m, n, d_r, n_fields, d_field, d_out, sorted, elem_off, chunk_off,
-                        counters, s));
+                        task_elem, w.tb_elem, s));
     }
     if (m->profiling) m->prof_eval++;
     return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;

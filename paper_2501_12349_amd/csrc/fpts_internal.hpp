@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <utility>
 #include <vector>
@@ -40,19 +41,50 @@ struct HashView {
 // candidates and picks a primary candidate per point, phase C runs Newton on
 // the primaries, phase D runs the remaining candidates of the points the
 // primary did not settle.
+// Task grids.  Items (points or pairs) bucketed by unit (cell or element)
+// are processed in tasks of up to kChunk items of one unit, one 64-lane
+// workgroup per task.  Workgroups go to the 8 XCDs round-robin, so block b
+// runs task (b mod 8) * (G / 8) + b / 8 of a grid of G blocks (G a multiple
+// of 8): each XCD works through a contiguous range of tasks and the tasks of
+// one unit share its L2; a block continues with tasks t + G, t + 2G, ...
+// Task -> unit comes from a map filled after the task offsets are scanned
+// (launch_task_map).
+constexpr int kXcd = 8;
+
+// Upper bound on the tasks of n items over nunit units.
+inline int64_t task_bound(int64_t n, int64_t nunit)
+{
+    return n / kChunk + std::min<int64_t>(n, nunit) + 1;
+}
+
+// Grid size (blocks) for a task bound: a multiple of the XCD count, at most
+// 64 blocks per CU; blocks loop over tasks t, t + G, ...
+inline int64_t task_grid(int64_t bound, int cus)
+{
+    const int64_t g = std::min<int64_t>(bound, (int64_t)cus * 64);
+    return (std::max<int64_t>(g, 1) + kXcd - 1) / kXcd * kXcd;
+}
+
+__device__ __forceinline__ int task_of_block()
+{
+    const int b = blockIdx.x, G = gridDim.x;
+    return (b % kXcd) * (G / kXcd) + b / kXcd;
+}
+
 struct FindWs {
     size_t cell_cnt, cell_fill, cell_poff, cell_choff, cellpt, pbin, ncand, primary,
         elem_cnt, elem_fill, elem_off, chunk_off, sorted, off2, elem_cnt2, elem_fill2,
         elem_off2, chunk_off2, slot_pt, slot_elem, sorted2, res_r, res_dist, res_code,
-        scan_tmp, counters, stats, total;
+        task_cell, task_elem, task_elem2, scan_tmp, counters, stats, total;
     int64_t cap2;           // capacity for second-pass (point, candidate) pairs
     int64_t scan_blocks;
     int64_t ncell;
+    int64_t tb_cell, tb_elem, tb_elem2;   // task bounds
 };
 
 struct EvalWs {
-    size_t elem_cnt, elem_off, elem_fill, chunk_off, scan_tmp, sorted, counters,
-        total;
+    size_t elem_cnt, elem_off, elem_fill, chunk_off, scan_tmp, sorted, task_elem, total;
+    int64_t tb_elem;
 };
 
 // Where one Newton launch reads its work and writes its results.
@@ -66,8 +98,10 @@ struct NewtonIO {
     double *r;              // [R][ostride]
     int64_t ostride;
     double *dist;           // [item]
-    int *counter;           // task counter (zeroed before the launch)
+    int *counter;           // element-queue counters (zeroed before the launch)
     unsigned long long *stats;
+    const int *task_elem;   // task -> element of the nearest-node task grid
+    int64_t task_bound;     // tasks of that grid at most
 };
 
 }  // namespace fpts
@@ -124,11 +158,13 @@ hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double
                            double *r, double *dist, hipStream_t s);
 // phase B: candidates of each point from its cell's list (one wave per 64
 // points of one cell), primary = deepest inside its OBB
+// task -> unit map of a task grid over nunit units with task offsets chunk_off
+hipError_t launch_task_map(const int *chunk_off, int64_t nunit, int *task_unit, hipStream_t s);
 hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
                                const int *pbin, const int *cell_poff, const int *cell_choff,
-                               int64_t ncell, int *ncand, int *primary, int *elem_cnt,
-                               int *counter, int32_t *code, int32_t *elem, double *r,
-                               double *dist, hipStream_t s);
+                               int64_t ncell, const int *task_cell, int64_t task_bound,
+                               int *ncand, int *primary, int *elem_cnt, int32_t *code,
+                               int32_t *elem, double *r, double *dist, hipStream_t s);
 hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int *primary,
                                   const int *elem_off, int *elem_fill, int *sorted,
                                   hipStream_t s);
@@ -151,8 +187,8 @@ hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_
                            const int *elem_off, int *elem_fill, int *sorted, hipStream_t s);
 hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fields,
                        const double *field, double *out, const int *sorted,
-                       const int *elem_off, const int *chunk_off, int *counter,
-                       hipStream_t s);
+                       const int *elem_off, const int *chunk_off, const int *task_elem,
+                       int64_t task_bound, hipStream_t s);
 hipError_t launch_nodes32(const fpts_mesh *m, hipStream_t s);
 
 // Newton launchers per element kind (kernels_newton_*.hip)

@@ -59,7 +59,7 @@ struct EvalArgs {
     const int *sorted;
     const int *elem_off;
     const int *chunk_off;
-    int *counter;
+    const int *task_elem;   // task -> element (task grid)
     Basis basis;
 };
 
@@ -69,18 +69,8 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
     constexpr int NP = (R == 3) ? N * N * N : N * N;
     const int lane = threadIdx.x;
     const int total = a.chunk_off[a.nel];
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(a.counter, 1);
-        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
-        if (t >= total) break;
-        int lo = 0, hi = a.nel;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (a.chunk_off[mid] <= t) lo = mid;
-            else hi = mid;
-        }
-        const int e = __builtin_amdgcn_readfirstlane(lo);
+    for (int t = task_of_block(); t < total; t += gridDim.x) {
+        const int e = __builtin_amdgcn_readfirstlane(a.task_elem[t]);
         const int beg = a.elem_off[e] + (t - a.chunk_off[e]) * kChunk;
         const int end = min(a.elem_off[e + 1], beg + kChunk);
         const int idx = beg + lane;
@@ -166,7 +156,8 @@ hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_
 
 hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fields,
                        const double *field, double *out, const int *sorted, const int *elem_off,
-                       const int *chunk_off, int *counter, hipStream_t s)
+                       const int *chunk_off, const int *task_elem, int64_t task_bound,
+                       hipStream_t s)
 {
     EvalFn fn = m->R == 3 ? pick_eval<3>(m->N) : pick_eval<2>(m->N);
     if (!fn) return hipErrorInvalidValue;
@@ -180,9 +171,9 @@ hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fie
     a.sorted = sorted;
     a.elem_off = elem_off;
     a.chunk_off = chunk_off;
-    a.counter = counter;
+    a.task_elem = task_elem;
     a.basis = m->basis;
-    hipLaunchKernelGGL(fn, dim3(m->cus * 16), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(fn, dim3(task_grid(task_bound, m->cus)), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

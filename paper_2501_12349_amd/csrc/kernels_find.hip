@@ -184,33 +184,32 @@ __global__ __launch_bounds__(256) void k_cell_bin(HashView h, int pass, int n, i
     }
 }
 
-// Phase B: one wavefront per task of up to 64 points of one cell.  The
-// cell's candidate list and each candidate's box record are wave-uniform and
-// read with scalar loads; every lane tests its own point.  Per point: number
-// of candidates, primary candidate (smallest OBB depth, lowest id on ties),
-// and the primary's bucket count.
+// task -> unit map: the tasks of unit u are chunk_off[u] .. chunk_off[u+1]-1
+__global__ __launch_bounds__(256) void k_task_map(const int *chunk_off, int nunit,
+                                                 int *task_unit)
+{
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= nunit) return;
+    for (int t = chunk_off[u]; t < chunk_off[u + 1]; ++t) task_unit[t] = u;
+}
+
+// Phase B: one wavefront per task of up to 64 points of one cell (task
+// grid).  The cell's candidate list and each candidate's box record are
+// wave-uniform and read with scalar loads; every lane tests its own point.
+// Per point: number of candidates, primary candidate (smallest OBB depth,
+// lowest id on ties), and the primary's bucket count.
 template <int D>
 __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, const double *pts,
                                                     const int *pbin, const int *cell_poff,
                                                     const int *cell_choff, int ncell,
-                                                    int *ncand, int *primary, int *elem_cnt,
-                                                    int *counter, int32_t *code, int32_t *elem,
-                                                    double *r, double *dist)
+                                                    const int *task_cell, int *ncand,
+                                                    int *primary, int *elem_cnt, int32_t *code,
+                                                    int32_t *elem, double *r, double *dist)
 {
     const int lane = threadIdx.x;
     const int total = cell_choff[ncell];
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(counter, 1);
-        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
-        if (t >= total) break;
-        int lo = 0, hi = ncell;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (cell_choff[mid] <= t) lo = mid;
-            else hi = mid;
-        }
-        const int c = __builtin_amdgcn_readfirstlane(lo);
+    for (int t = task_of_block(); t < total; t += gridDim.x) {
+        const int c = __builtin_amdgcn_readfirstlane(task_cell[t]);
         const int beg = cell_poff[c] + (t - cell_choff[c]) * kChunk;
         const int end = min(cell_poff[c + 1], beg + kChunk);
         const bool has = beg + lane < end;
@@ -414,18 +413,26 @@ hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double
     return hipGetLastError();
 }
 
+hipError_t launch_task_map(const int *chunk_off, int64_t nunit, int *task_unit, hipStream_t s)
+{
+    if (nunit <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_task_map, dim3(grid_for(nunit, 256)), dim3(256), 0, s, chunk_off,
+                       (int)nunit, task_unit);
+    return hipGetLastError();
+}
+
 hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
                                const int *pbin, const int *cell_poff, const int *cell_choff,
-                               int64_t ncell, int *ncand, int *primary, int *elem_cnt,
-                               int *counter, int32_t *code, int32_t *elem, double *r,
-                               double *dist, hipStream_t s)
+                               int64_t ncell, const int *task_cell, int64_t task_bound,
+                               int *ncand, int *primary, int *elem_cnt, int32_t *code,
+                               int32_t *elem, double *r, double *dist, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     HashView h = hash_view(m);
     auto k = m->D == 2 ? k_locate_cells<2> : k_locate_cells<3>;
-    hipLaunchKernelGGL(k, dim3(m->cus * 16), dim3(64), 0, s, h, (int)n, m->R, pts, pbin,
-                       cell_poff, cell_choff, (int)ncell, ncand, primary, elem_cnt, counter,
-                       code, elem, r, dist);
+    hipLaunchKernelGGL(k, dim3(task_grid(task_bound, m->cus)), dim3(64), 0, s, h, (int)n, m->R,
+                       pts, pbin, cell_poff, cell_choff, (int)ncell, task_cell, ncand, primary,
+                       elem_cnt, code, elem, r, dist);
     return hipGetLastError();
 }
 

@@ -65,6 +65,16 @@ template <> __device__ __forceinline__ float xor_shfl<float>(float v, int m)
     return __shfl_xor(v, m);
 }
 
+// Orders LDS accesses between the lanes of a wave (every workgroup here is
+// one wave).  The LDS instructions of a wave complete in issue order, so only
+// compiler motion has to be fenced: no wait is emitted.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Sum over the four lanes of a slot (lanes l, l^16, l^32, l^48).
 template <typename T>
 __device__ __forceinline__ T slot_sum(T v)
@@ -122,9 +132,10 @@ __device__ __forceinline__ void basis_at(T x, int i, T &v, T &d, T &dd)
 }
 
 // All N bases of one direction at x (prefix/suffix jets), written to the
-// per-slot LDS table tab[kind][i][slot] (kind 0: phi, 1: phi', 2: phi'').
+// per-slot LDS table tab[kind][i][slot] (kind 0: phi, 1: phi', 2: phi'')
+// when `write` holds.
 template <typename T, int N, bool H2>
-__device__ __forceinline__ void basis_table(T x, T *tab, int slot)
+__device__ __forceinline__ void basis_table(T x, T *tab, int slot, bool write)
 {
     constexpr gll::Table<N> G = gll::Nodes<N>::t;
     T pv[N], pd[N], pdd[N];
@@ -141,11 +152,13 @@ __device__ __forceinline__ void basis_table(T x, T *tab, int slot)
     T sv = T(1), sd = T(0), sdd = T(0);
 #pragma unroll
     for (int i = N - 1; i >= 0; --i) {
-        tab[(0 * N + i) * 16 + slot] = T(G.w[i]) * (pv[i] * sv);
-        tab[(1 * N + i) * 16 + slot] = T(G.w[i]) * (pd[i] * sv + pv[i] * sd);
-        if (H2)
-            tab[(2 * N + i) * 16 + slot] =
-                T(G.w[i]) * (pdd[i] * sv + T(2) * pd[i] * sd + pv[i] * sdd);
+        if (write) {
+            tab[(0 * N + i) * 16 + slot] = T(G.w[i]) * (pv[i] * sv);
+            tab[(1 * N + i) * 16 + slot] = T(G.w[i]) * (pd[i] * sv + pv[i] * sd);
+            if (H2)
+                tab[(2 * N + i) * 16 + slot] =
+                    T(G.w[i]) * (pdd[i] * sv + T(2) * pd[i] * sd + pv[i] * sdd);
+        }
         const T t = x - T(G.z[i]);
         if (H2) sdd = sdd * t + T(2) * sd;
         sd = sd * t + sv;
@@ -153,17 +166,23 @@ __device__ __forceinline__ void basis_table(T x, T *tab, int slot)
     }
 }
 
+// Pairs staged per refill of a wave's slots (coordinates, start and id).
+// 32 keeps the FP64 LDS footprint of hexes with N <= 8 within 20 KB, so that
+// eight waves fit a CU.
+constexpr int kCache = 32;
+
 // LDS layout of one wave: nodes [D][NP] of type T, then the per-slot basis
 // tables of directions 1 and 2 (s, t): [2][3][N][16] of type T.
 template <typename T, int D, int R, int N>
 struct Lds {
     static constexpr int NODES = D * Shape<D, R, N>::NP;
     static constexpr int TAB = 3 * N * 16;
-    // pair cache: 64 x (point coordinates D, start r R) of type T, 64 items
-    static constexpr int CACHE = 64 * (D + R);
+    // pair cache: kCache x (point coordinates D, start r R) of type T, then
+    // kCache item ids
+    static constexpr int CACHE = kCache * (D + R);
     static constexpr size_t bytes()
     {
-        return sizeof(T) * (NODES + 2 * TAB + CACHE) + sizeof(int) * 64;
+        return sizeof(T) * (NODES + 2 * TAB + CACHE) + sizeof(int) * kCache;
     }
 };
 
@@ -175,26 +194,36 @@ __device__ __forceinline__ void sweep1(const T *xl, T *tab, int lane, const T (&
     typedef Shape<D, R, N> S;
     typedef typename V4<T>::type v4;
     const int slot = lane & 15, g = lane >> 4;
+    // per-slot tables [direction][kind][i][slot] (kinds phi, phi'): lane
+    // quarter g builds direction g of its slot, so the R tables of all 16
+    // slots are built at once
+    wave_lds_sync();   // the previous sweep's reads of the tables come first
+    {
+        // q[g] by exact arithmetic selection (one weight is 1, the others
+        // 0), which keeps q in registers
+        const T w0 = T(g != 1 && g != 2), w1 = T(g == 1), w2 = T(R == 3 && g == 2);
+        T x = q[0] * w0;
+        x = fma(q[1], w1, x);
+        if (R == 3) x = fma(q[R == 3 ? 2 : 0], w2, x);
+        basis_table<T, N, false>(x, tab + (g < R ? g : 0) * 2 * N * 16, slot, g < R);
+    }
+    wave_lds_sync();
+    const T *tr = tab, *ts = tab + 2 * N * 16, *tt = tab + 4 * N * 16;
     // B operand: this lane's bases in direction 0 for i = 4 ks + g
     T b0[S::KS], b1[S::KS];
 #pragma unroll
     for (int ks = 0; ks < S::KS; ++ks) {
         const int i = 4 * ks + g;
-        T v, d, dd;
-        basis_at<T, N>(q[0], i, v, d, dd);
-        b0[ks] = i < N ? v : T(0);
-        b1[ks] = i < N ? d : T(0);
+        b0[ks] = i < N ? tr[(0 * N + i) * 16 + slot] : T(0);
+        b1[ks] = i < N ? tr[(1 * N + i) * 16 + slot] : T(0);
     }
-    // per-slot tables of directions 1 (and 2); all four lanes of a slot
-    // write identical values
-    basis_table<T, N, false>(q[1], tab, slot);
-    if (R == 3) basis_table<T, N, false>(q[2], tab + 3 * N * 16, slot);
 #pragma unroll
     for (int c = 0; c < D; ++c) {
         X[c] = T(0);
 #pragma unroll
         for (int a = 0; a < R; ++a) G[c][a] = T(0);
     }
+    constexpr bool kFullA = (N % 4 == 0) && (S::ROWS % 16 == 0);
 #pragma unroll 1
     for (int m = 0; m < S::MT; ++m) {
         v4 acc0[D], acc1[D];
@@ -207,10 +236,13 @@ __device__ __forceinline__ void sweep1(const T *xl, T *tab, int lane, const T (&
 #pragma unroll
         for (int ks = 0; ks < S::KS; ++ks) {
             const int ai = 4 * ks + g;      // A-operand column (node index i)
-            const bool aok = arow < S::ROWS && ai < N;
+            const bool aok = kFullA || (arow < S::ROWS && ai < N);
 #pragma unroll
             for (int c = 0; c < D; ++c) {
-                const T a = xl[aok ? c * S::NP + ai + N * arow : 0] * T(aok ? 1 : 0);
+                // out-of-range A entries meet a zero B entry (ai >= N) or
+                // land in output rows that are dropped (arow >= ROWS); the
+                // clamped address keeps the read inside the node block
+                const T a = xl[aok ? c * S::NP + ai + N * arow : 0];
                 acc0[c] = mfma16(a, b0[ks], acc0[c]);
                 acc1[c] = mfma16(a, b1[ks], acc1[c]);
             }
@@ -219,12 +251,11 @@ __device__ __forceinline__ void sweep1(const T *xl, T *tab, int lane, const T (&
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
             const int row = 16 * m + out_row<T>(g, qq);
-            if (row >= S::ROWS) continue;
+            if (S::ROWS % 16 != 0 && row >= S::ROWS) continue;
             if constexpr (R == 3) {
                 const int j = row % N, k = row / N;
-                const T sv = tab[(0 * N + j) * 16 + slot], sd = tab[(1 * N + j) * 16 + slot];
-                const T tv = tab[3 * N * 16 + (0 * N + k) * 16 + slot];
-                const T td = tab[3 * N * 16 + (1 * N + k) * 16 + slot];
+                const T sv = ts[(0 * N + j) * 16 + slot], sd = ts[(1 * N + j) * 16 + slot];
+                const T tv = tt[(0 * N + k) * 16 + slot], td = tt[(1 * N + k) * 16 + slot];
                 const T w00 = sv * tv, w10 = sd * tv, w01 = sv * td;
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
@@ -235,7 +266,7 @@ __device__ __forceinline__ void sweep1(const T *xl, T *tab, int lane, const T (&
                 }
             } else {
                 const int j = row;
-                const T sv = tab[(0 * N + j) * 16 + slot], sd = tab[(1 * N + j) * 16 + slot];
+                const T sv = ts[(0 * N + j) * 16 + slot], sd = ts[(1 * N + j) * 16 + slot];
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
                     X[c] = fma(acc0[c][qq], sv, X[c]);
@@ -271,8 +302,15 @@ __device__ __forceinline__ void sweep2(const T *xl, T *tab, int lane, const T (&
         b1[ks] = i < N ? d : T(0);
         b2[ks] = i < N ? dd : T(0);
     }
-    basis_table<T, N, true>(q[1], tab, slot);
-    if (R == 3) basis_table<T, N, true>(q[2], tab + 3 * N * 16, slot);
+    // per-slot tables [direction - 1][kind][i][slot] (phi, phi', phi'') of
+    // directions 1 (lane quarter 1) and 2 (lane quarter 2)
+    wave_lds_sync();
+    {
+        const T x = (R == 3 && g == 2) ? q[R == 3 ? 2 : 0] : q[1];
+        const bool w = g == 1 || (R == 3 && g == 2);
+        basis_table<T, N, true>(x, tab + (g == 2 ? 3 * N * 16 : 0), slot, w);
+    }
+    wave_lds_sync();
     T Sa[kSym<R>];
 #pragma unroll
     for (int a = 0; a < kSym<R>; ++a) Sa[a] = T(0);
@@ -285,10 +323,10 @@ __device__ __forceinline__ void sweep2(const T *xl, T *tab, int lane, const T (&
 #pragma unroll
         for (int ks = 0; ks < S::KS; ++ks) {
             const int ai = 4 * ks + g;
-            const bool aok = arow < S::ROWS && ai < N;
+            const bool aok = ((N % 4 == 0) && (S::ROWS % 16 == 0)) || (arow < S::ROWS && ai < N);
 #pragma unroll
             for (int c = 0; c < D; ++c) {
-                const T a = xl[aok ? c * S::NP + ai + N * arow : 0] * T(aok ? 1 : 0);
+                const T a = xl[aok ? c * S::NP + ai + N * arow : 0];
                 acc0 = mfma16(a, dx[c] * b0[ks], acc0);
                 acc1 = mfma16(a, dx[c] * b1[ks], acc1);
                 acc2 = mfma16(a, dx[c] * b2[ks], acc2);
@@ -297,7 +335,7 @@ __device__ __forceinline__ void sweep2(const T *xl, T *tab, int lane, const T (&
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
             const int row = 16 * m + out_row<T>(g, qq);
-            if (row >= S::ROWS) continue;
+            if (S::ROWS % 16 != 0 && row >= S::ROWS) continue;
             const T C0 = acc0[qq], C1 = acc1[qq], C2 = acc2[qq];
             if constexpr (R == 3) {
                 const int j = row % N, k = row / N;
@@ -479,57 +517,81 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
     for (int k = 0; k < kSym<R>; ++k) cur.Hgn[k] = T(0);
     bool hb_ok = false;
     int head = q0, cstart = q0, cend = q0;
-    const int guard = (q1 - q0 + 16) * (2 * max_iter + 4);
-    for (int trip = 0; trip < guard; ++trip) {
-        // refill free slots from the element's queue, through a cache of
-        // the next 64 pairs (one coalesced load per 64 pairs)
+    // Refill free slots from the element's queue, through a cache of the
+    // next kCache pairs (one coalesced load per kCache pairs).  Wave-uniform.
+    auto refill = [&]() {
         const unsigned long long freem = __ballot(leader && state == S_FREE);
         const int nfree = __popcll(freem);
-        if (nfree && head < q1) {
-            if (head >= cend) {
-                cstart = head;
-                cend = min(q1, head + 64);
-                const int idx = cstart + lane;
-                if (idx < cend) {
-                    const int it = io.list[idx];
-                    const int p = io.slot_pt ? io.slot_pt[it] : it;
-                    citem[lane] = it;
+        if (!nfree || head >= q1) return;
+        if (head >= cend) {
+            wave_lds_sync();   // earlier reads of the cache come first
+            cstart = head;
+            cend = min(q1, head + kCache);
+            const int idx = cstart + lane;
+            if (lane < kCache && idx < cend) {
+                const int it = io.list[idx];
+                const int p = io.slot_pt ? io.slot_pt[it] : it;
+                citem[lane] = it;
 #pragma unroll
-                    for (int c = 0; c < D; ++c)
-                        cache[c * 64 + lane] =
-                            T(a.pts[(size_t)c * a.n + p] - (shift ? shift[c] : 0.0));
-                    // agent-scope loads: in mixed mode the FP32 phase of this
-                    // wave stored these values moments ago
+                for (int c = 0; c < D; ++c)
+                    cache[c * kCache + lane] =
+                        T(a.pts[(size_t)c * a.n + p] - (shift ? shift[c] : 0.0));
+                // agent-scope loads: in mixed mode the FP32 phase of this
+                // wave stored these values moments ago
 #pragma unroll
-                    for (int k = 0; k < R; ++k)
-                        cache[(D + k) * 64 + lane] = T(__hip_atomic_load(
-                            io.r + (size_t)k * io.ostride + it, __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT));
-                }
+                for (int k = 0; k < R; ++k)
+                    cache[(D + k) * kCache + lane] = T(__hip_atomic_load(
+                        io.r + (size_t)k * io.ostride + it, __ATOMIC_RELAXED,
+                        __HIP_MEMORY_SCOPE_AGENT));
             }
-            if (state == S_FREE) {
-                const int rank = __popcll(freem & ((1ull << slot) - 1));
-                const int idx = head + rank;
-                if (idx < cend) {
-                    const int c0 = idx - cstart;
-                    item = citem[c0];
-#pragma unroll
-                    for (int c = 0; c < D; ++c) xs[c] = cache[c * 64 + c0];
-#pragma unroll
-                    for (int k = 0; k < R; ++k) r[k] = cache[(D + k) * 64 + c0];
-                    T xn = T(0);
-#pragma unroll
-                    for (int c = 0; c < D; ++c) xn = fma(xs[c], xs[c], xn);
-                    xnorm = sqrt(xn);
-                    state = S_INIT;
-                    pass = 0;
-                    alpha = T(1);
-                    hb_ok = false;
-                    if (leader && FINAL) cn.pairs++;
-                }
-            }
-            head = min(head + nfree, cend);
+            wave_lds_sync();
         }
+        if (state == S_FREE) {
+            const int rank = __popcll(freem & ((1ull << slot) - 1));
+            const int idx = head + rank;
+            if (idx < cend) {
+                const int c0 = idx - cstart;
+                item = citem[c0];
+#pragma unroll
+                for (int c = 0; c < D; ++c) xs[c] = cache[c * kCache + c0];
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    r[k] = cache[(D + k) * kCache + c0];
+                    q[k] = r[k];
+                }
+                T xn = T(0);
+#pragma unroll
+                for (int c = 0; c < D; ++c) xn = fma(xs[c], xs[c], xn);
+                xnorm = sqrt(xn);
+                state = S_INIT;
+                pass = 0;
+                alpha = T(1);
+                hb_ok = false;
+                if (leader && FINAL) cn.pairs++;
+            }
+        }
+        head = min(head + nfree, cend);
+    };
+    // A pair is done: results out, slot free.
+    auto finish = [&]() {
+        if (leader) {
+            if (FINAL) {
+                bool inside = true;
+#pragma unroll
+                for (int k = 0; k < R; ++k) inside = inside && (fabs(r[k]) < T(1));
+                if (R < D) inside = inside && (cur.f < T(a.eps_d));
+                io.code[item] = inside ? FPTS_INTERIOR : FPTS_BORDER;
+                if (io.elem) io.elem[item] = e;
+                io.dist[item] = sqrt((double)cur.f);
+            }
+#pragma unroll
+            for (int k = 0; k < R; ++k) io.r[(size_t)k * io.ostride + item] = (double)r[k];
+        }
+        state = S_FREE;
+    };
+    const int guard = (q1 - q0 + 16) * (2 * max_iter + 4);
+    for (int trip = 0; trip < guard; ++trip) {
+        refill();
         const unsigned long long waitm = __ballot(leader && state == S_WAIT);
         const unsigned long long stepm = __ballot(leader && (state == S_STEP || state == S_INIT));
         if (!waitm && !stepm) break;
@@ -551,11 +613,9 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
             if (leader && FINAL && state != S_FREE) cn.evals_h2_exec++;
             continue;
         }
-        // query points: start points (INIT) or trial points (STEP)
-        if (state == S_INIT) {
-#pragma unroll
-            for (int k = 0; k < R; ++k) q[k] = r[k];
-        } else if (state == S_STEP) {
+        // trial points of the stepping slots
+        bool ended = false;
+        if (state == S_STEP) {
             const bool beta = (pass > 0) && on_face(r);
             if (beta && !hb_ok) {
                 // a face pass needs second derivatives at r: dx at r is
@@ -596,12 +656,29 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                     for (int b = 0; b < R; ++b) dHd = fma(dr[k] * H[sym<R>(k, b)], dr[b], dHd);
                 }
                 pred = T(2) * gd - dHd;
+                if (dmax < tol) {
+                    // converged: the step is taken without evaluating the
+                    // map at q; the squared residual there is the model's,
+                    // f - pred, whose error is third order in the step
+                    ++pass;
+                    if (leader) {
+                        if (FINAL) cn.passes++;
+                        else cn.passes32++;
+                    }
+#pragma unroll
+                    for (int k = 0; k < R; ++k) r[k] = q[k];
+                    cur.f = fmax(cur.f - pred, T(0));
+                    finish();
+                    ended = true;
+                }
             }
         }
+        if (__ballot(leader && ended)) refill();
         if (state != S_INIT && state != S_STEP) {
 #pragma unroll
             for (int k = 0; k < R; ++k) q[k] = r[k];
         }
+        if (!__ballot(leader && (state == S_INIT || state == S_STEP))) continue;
         T X[D], Gm[D][R], dxn[D];
         sweep1<T, D, R, N>(xl, tab, lane, q, X, Gm);
         if (lane == 0) {
@@ -631,25 +708,21 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                     cn.passes32++;
                 }
             }
-            bool accept, stop = false;
-            if (dmax < tol) {
+            // trust-region test (the step is at least the tolerance here)
+            bool accept;
+            const T decr = cur.f - nw.f;
+            const T sf = sqrt(cur.f);
+            const T noise = T(64) * eps_of<T>() * sf * (xnorm + sf);
+            if (pred > T(0) && pred <= noise) {
                 accept = true;
-                stop = true;
+            } else if (pred > T(0) && decr >= T(0.9) * pred) {
+                accept = true;
+                alpha *= T(2);
+            } else if (pred > T(0) && decr >= T(0.01) * pred) {
+                accept = true;
             } else {
-                const T decr = cur.f - nw.f;
-                const T sf = sqrt(cur.f);
-                const T noise = T(64) * eps_of<T>() * sf * (xnorm + sf);
-                if (pred > T(0) && pred <= noise) {
-                    accept = true;
-                } else if (pred > T(0) && decr >= T(0.9) * pred) {
-                    accept = true;
-                    alpha *= T(2);
-                } else if (pred > T(0) && decr >= T(0.01) * pred) {
-                    accept = true;
-                } else {
-                    accept = false;
-                    alpha *= T(0.25);
-                }
+                accept = false;
+                alpha *= T(0.25);
             }
             if (accept) {
 #pragma unroll
@@ -659,136 +732,200 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                 for (int c = 0; c < D; ++c) dx[c] = dxn[c];
                 hb_ok = false;
             }
-            if (stop || pass >= max_iter) {
-                // pair done: results out, slot free
-                if (leader) {
-                    if (FINAL) {
-                        bool inside = true;
-#pragma unroll
-                        for (int k = 0; k < R; ++k) inside = inside && (fabs(r[k]) < T(1));
-                        if (R < D) inside = inside && (cur.f < T(a.eps_d));
-                        io.code[item] = inside ? FPTS_INTERIOR : FPTS_BORDER;
-                        if (io.elem) io.elem[item] = e;
-                        io.dist[item] = sqrt((double)cur.f);
-                    }
-#pragma unroll
-                    for (int k = 0; k < R; ++k) io.r[(size_t)k * io.ostride + item] = (double)r[k];
-                }
-                state = S_FREE;
-            } else if (accept && on_face(r)) {
-                // the next pass uses beta = 1 here: wait for sweep 2
-                state = S_WAIT;
-            }
+            if (pass >= max_iter) finish();
+            else if (accept && on_face(r)) state = S_WAIT;   // next pass: beta = 1
         }
     }
 }
 
-// Nearest element node of each pair (Euclidean; lowest node index on
-// ties), as the start of Newton (Section 3.2.1); written to io.r.  One wave
-// per task of up to 64 pairs of one element, nodes staged in LDS.
-template <typename T>
-__device__ __forceinline__ void stage(T *lds, const T *src, int count, int lane)
+// Copies COUNT values of an element block from global memory to LDS (one
+// wave), issuing every load before the first store, then waits for the
+// workgroup.
+template <typename T, int COUNT>
+__device__ __forceinline__ void stage(T *lds, const T *src, int lane)
 {
     typedef __attribute__((ext_vector_type(4))) unsigned int u4;
-    const int words = count * (int)sizeof(T) / 16;
+    constexpr int WORDS = COUNT * (int)sizeof(T) / 16;
+    constexpr int PER = (WORDS + kWave - 1) / kWave;
+    constexpr int BATCH = 4;   // 16-byte loads in flight per lane
     const u4 *s = reinterpret_cast<const u4 *>(src);
     u4 *d = reinterpret_cast<u4 *>(lds);
-    for (int k = lane; k < words; k += kWave) d[k] = s[k];
-    const int rest = count * (int)sizeof(T) - words * 16;   // 0, 4, 8 or 12 bytes
+#pragma unroll 1
+    for (int k0 = 0; k0 < PER; k0 += BATCH) {
+        u4 v[BATCH];
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) {
+            const int w = (k0 + k) * kWave + lane;
+            if (w < WORDS) v[k] = s[w];
+        }
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) {
+            const int w = (k0 + k) * kWave + lane;
+            if (w < WORDS) d[w] = v[k];
+        }
+    }
+    constexpr int REST = COUNT * (int)sizeof(T) - WORDS * 16;   // 0, 4, 8 or 12 bytes
     const unsigned *s4 = reinterpret_cast<const unsigned *>(src);
     unsigned *d4 = reinterpret_cast<unsigned *>(lds);
-    if (lane < rest / 4) d4[words * 4 + lane] = s4[words * 4 + lane];
+    if (lane < REST / 4) d4[WORDS * 4 + lane] = s4[WORDS * 4 + lane];
     __syncthreads();
 }
 
+// LDS of the nearest-node kernel: B operand rows [4][NPAD] (-2 x_j, -2 y_j,
+// -2 z_j, |x_j|^2 of every node j, element-local; padding columns score a
+// large constant), A operand rows [4][64] (x, y, z, 1 of each pair), item ids.
+template <typename T, int D, int R, int N>
+struct NearLds {
+    static constexpr int NPAD = (Shape<D, R, N>::NP + 31) / 32 * 32;   // even tile count
+    static constexpr size_t bytes() { return sizeof(T) * 4 * (NPAD + 64) + sizeof(int) * 64; }
+};
+
+// Nearest element node of up to 64 pairs of one element (Euclidean; among
+// equal scores the lowest node index), the start of Newton (Section 3.2.1).
+// The squared distance |x - x_j|^2 = |x|^2 - 2 x.x_j + |x_j|^2 has the same
+// minimiser as the score |x_j|^2 - 2 x.x_j, a K = 4 contraction of
+// (x, y, z, 1) with (-2 x_j, -2 y_j, -2 z_j, |x_j|^2): one 16 x 16 x 4 MFMA
+// scores 16 pairs against 16 nodes.  Coordinates are element-local (node
+// block minus the element centre) to keep the cancellation small.
 template <int D, int R, int N, bool MIXED>
 __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
 {
     typedef Shape<D, R, N> S;
-    constexpr gll::Table<N> GT = gll::Nodes<N>::t;
-    extern __shared__ double lds_raw[];
+    typedef NearLds<typename std::conditional<MIXED, float, double>::type, D, R, N> L;
     typedef typename std::conditional<MIXED, float, double>::type T;
-    T *xl = reinterpret_cast<T *>(lds_raw);
-    const int lane = threadIdx.x;
+    typedef typename V4<T>::type v4;
+    constexpr gll::Table<N> GT = gll::Nodes<N>::t;
+    constexpr int NT = L::NPAD / 16;
+    const T kBig = MIXED ? T(1e30f) : T(1e300);
+    extern __shared__ double lds_raw[];
+    T *Bt = reinterpret_cast<T *>(lds_raw);            // [4][NPAD]
+    T *Pt = Bt + 4 * L::NPAD;                          // [4][64]
+    int *items = reinterpret_cast<int *>(Pt + 4 * 64); // [64]
+    const int lane = threadIdx.x, col = lane & 15, g = lane >> 4;
     const NewtonIO &io = a.io;
     const int total = io.chunk_off[a.nel];
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(io.counter, 1);
-        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
-        if (t >= total) break;
-        int lo = 0, hi = a.nel;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (io.chunk_off[mid] <= t) lo = mid;
-            else hi = mid;
-        }
-        const int e = __builtin_amdgcn_readfirstlane(lo);
+    for (int t = task_of_block(); t < total; t += gridDim.x) {
+        const int e = __builtin_amdgcn_readfirstlane(io.task_elem[t]);
         const int beg = io.elem_off[e] + (t - io.chunk_off[e]) * kChunk;
-        const int end = min(io.elem_off[e + 1], beg + kChunk);
-        const bool has = beg + lane < end;
-        const int item = has ? io.list[beg + lane] : 0;
-        const int p = has ? (io.slot_pt ? io.slot_pt[item] : item) : 0;
-        __syncthreads();
-        if (MIXED) stage<T>(xl, (const T *)(a.nodes32 + (size_t)e * D * S::NP), D * S::NP, lane);
-        else stage<T>(xl, (const T *)(a.nodes + (size_t)e * D * S::NP), D * S::NP, lane);
-        T xs[D];
+        const int cnt = min(io.elem_off[e + 1] - beg, kChunk);
+        double xc[D];
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-            const double x = has ? a.pts[(size_t)c * a.n + p] : 0.0;
-            xs[c] = MIXED ? T(x - a.xc[(size_t)e * D + c]) : T(x);
-        }
-        T best = T(__builtin_huge_valf());
-        int bi = 0;
+        for (int c = 0; c < D; ++c) xc[c] = a.xc[(size_t)e * D + c];
+        wave_lds_sync();   // the previous task's reads come first
+        // B rows of the element's nodes
 #pragma unroll 1
-        for (int row = 0; row < S::ROWS; ++row) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const int idx = row * N + i;
-                T d2 = T(0);
+        for (int j = lane; j < L::NPAD; j += kWave) {
+            T b[4] = {T(0), T(0), T(0), T(0)};
+            if (j < S::NP) {
+                T n2 = T(0);
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
-                    const T u = xs[c] - xl[c * S::NP + idx];
-                    d2 = fma(u, u, d2);
+                    const T v = MIXED ? T(a.nodes32[((size_t)e * D + c) * S::NP + j])
+                                      : T(a.nodes[((size_t)e * D + c) * S::NP + j] - xc[c]);
+                    b[c] = T(-2) * v;
+                    n2 = fma(v, v, n2);
                 }
-                if (d2 < best) {
-                    best = d2;
-                    bi = idx;
+                b[D] = n2;
+            } else {
+                b[D] = kBig;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Bt[k * L::NPAD + j] = b[k];
+        }
+        // A rows of the pairs
+        {
+            const bool has = lane < cnt;
+            const int item = has ? io.list[beg + lane] : 0;
+            const int p = has ? (io.slot_pt ? io.slot_pt[item] : item) : 0;
+            items[lane] = item;
+            T pa[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+                pa[c] = has ? T(a.pts[(size_t)c * a.n + p] - xc[c]) : T(0);
+            pa[D] = T(1);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) Pt[k * 64 + lane] = pa[k];
+        }
+        wave_lds_sync();
+        const int ntile = (cnt + 15) >> 4;   // pair tiles of this task
+#pragma unroll 1
+        for (int pt = 0; pt < ntile; ++pt) {
+            const T av = Pt[g * 64 + 16 * pt + col];
+            T best[4];
+            int bix[4];
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                best[qq] = T(__builtin_huge_valf());
+                bix[qq] = 0;
+            }
+#pragma unroll 2
+            for (int nt = 0; nt < NT; ++nt) {
+                const T bv = Bt[g * L::NPAD + 16 * nt + col];
+                const v4 d = mfma16(av, bv, v4{0, 0, 0, 0});
+                const int node = 16 * nt + col;
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq) {
+                    const bool lt = d[qq] < best[qq];
+                    bix[qq] = lt ? node : bix[qq];
+                    best[qq] = lt ? d[qq] : best[qq];
                 }
             }
-        }
-        if (has) {
-            const int ii[3] = {bi % N, (bi / N) % N, bi / (N * N)};
+            // lexicographic (score, node) minimum over the 16 lanes of a row
 #pragma unroll
-            for (int k = 0; k < R; ++k) {
-                double v = GT.z[0];
+            for (int o = 1; o < 16; o <<= 1) {
 #pragma unroll
-                for (int m = 1; m < N; ++m)
-                    if (ii[k] == m) v = GT.z[m];
-                io.r[(size_t)k * io.ostride + item] = v;
+                for (int qq = 0; qq < 4; ++qq) {
+                    const T so = __shfl_xor(best[qq], o);
+                    const int io2 = __shfl_xor(bix[qq], o);
+                    const bool take = so < best[qq] || (so == best[qq] && io2 < bix[qq]);
+                    bix[qq] = take ? io2 : bix[qq];
+                    best[qq] = take ? so : best[qq];
+                }
+            }
+            // lane `col` < 4 writes the pair of its row group held in item qq = col
+            int bi = bix[0] * (col == 0) + bix[1] * (col == 1) + bix[2] * (col == 2) +
+                     bix[3] * (col == 3);
+            const int pl = 16 * pt + (MIXED ? 4 * g + col : g + 4 * col);
+            if (col < 4 && pl < cnt) {
+                const int item = items[pl];
+                const int ii[3] = {bi % N, (bi / N) % N, bi / (N * N)};
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    double v = GT.z[0];
+#pragma unroll
+                    for (int m = 1; m < N; ++m)
+                        if (ii[k] == m) v = GT.z[m];
+                    io.r[(size_t)k * io.ostride + item] = v;
+                }
             }
         }
     }
 }
 
-// Newton over the element queue: one wave per element (task counter over
-// elements that have pairs).
-template <int D, int R, int N, bool MIXED>
+// Newton over the element queue in precision T: one wave per element (task
+// counter io.counter[8] for the FP64 kernel, [9] for the FP32 phase of mixed
+// mode), over the elements that have pairs.  The start of every pair is
+// read from io.r: the nearest node, or the FP32 result in mixed mode.
+template <typename T, int D, int R, int N>
 __device__ __forceinline__ void newton_body(const NewtonArgs &a)
 {
     typedef Shape<D, R, N> S;
+    constexpr bool FINAL = std::is_same<T, double>::value;
     extern __shared__ double lds_raw[];
     int *citem = reinterpret_cast<int *>(reinterpret_cast<char *>(lds_raw) +
-                                         Lds<double, D, R, N>::bytes() - sizeof(int) * 64);
+                                         Lds<T, D, R, N>::bytes() - sizeof(int) * kCache);
     const int lane = threadIdx.x;
     const NewtonIO &io = a.io;
+    T *xl = reinterpret_cast<T *>(lds_raw);
+    T *tab = xl + Lds<T, D, R, N>::NODES;
+    T *cache = tab + 2 * Lds<T, D, R, N>::TAB;
     Counters cn;
     for (;;) {
         int e = 0;
         if (lane == 0) {
             // next element with a non-empty queue
             for (;;) {
-                e = atomicAdd(io.counter + 8, 1);
+                e = atomicAdd(io.counter + (FINAL ? 8 : 9), 1);
                 if (e >= a.nel || io.elem_off[e + 1] > io.elem_off[e]) break;
             }
         }
@@ -796,22 +933,15 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &a)
         if (e >= a.nel) break;
         const int q0 = io.elem_off[e], q1 = io.elem_off[e + 1];
         __syncthreads();
-        if constexpr (MIXED) {
-            float *xl32 = reinterpret_cast<float *>(lds_raw);
-            float *tab32 = xl32 + Lds<float, D, R, N>::NODES;
-            float *cache32 = tab32 + 2 * Lds<float, D, R, N>::TAB;
-            stage<float>(xl32, a.nodes32 + (size_t)e * D * S::NP, D * S::NP, lane);
-            run_element<float, D, R, N, false>(a, e, q0, q1, xl32, tab32, cache32, citem, lane,
+        if constexpr (FINAL) {
+            stage<double, D * S::NP>(xl, a.nodes + (size_t)e * D * S::NP, lane);
+            run_element<double, D, R, N, true>(a, e, q0, q1, xl, tab, cache, citem, lane,
+                                               a.max_iter, a.tol, nullptr, cn);
+        } else {
+            stage<float, D * S::NP>(xl, a.nodes32 + (size_t)e * D * S::NP, lane);
+            run_element<float, D, R, N, false>(a, e, q0, q1, xl, tab, cache, citem, lane,
                                                a.max_iter32, a.tol32, a.xc + (size_t)e * D, cn);
-            __threadfence();   // the FP32 results are stored before they are reloaded
-            __syncthreads();
         }
-        double *xl = lds_raw;
-        double *tab = xl + Lds<double, D, R, N>::NODES;
-        double *cache = tab + 2 * Lds<double, D, R, N>::TAB;
-        stage<double>(xl, a.nodes + (size_t)e * D * S::NP, D * S::NP, lane);
-        run_element<double, D, R, N, true>(a, e, q0, q1, xl, tab, cache, citem, lane, a.max_iter,
-                                           a.tol, nullptr, cn);
     }
     unsigned long long v[10] = {cn.pairs,  cn.passes,        cn.evals,  cn.evals_h2,
                                 cn.passes32, cn.evals32,     cn.evals_h2_exec,
@@ -838,30 +968,50 @@ __global__ __launch_bounds__(64) void k_nearest_resolve(NewtonArgs a)
 {
     nearest_body<D, R, N, MIXED>(a);
 }
-template <int D, int R, int N, bool MIXED>
+template <int D, int R, int N>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_newton(NewtonArgs a)
 {
-    newton_body<D, R, N, MIXED>(a);
+    newton_body<double, D, R, N>(a);
 }
-template <int D, int R, int N, bool MIXED>
+template <int D, int R, int N>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 k_newton_resolve(NewtonArgs a)
 {
-    newton_body<D, R, N, MIXED>(a);
+    newton_body<double, D, R, N>(a);
+}
+template <int D, int R, int N>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
+k_newton32(NewtonArgs a)
+{
+    newton_body<float, D, R, N>(a);
+}
+template <int D, int R, int N>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
+k_newton32_resolve(NewtonArgs a)
+{
+    newton_body<float, D, R, N>(a);
 }
 
 typedef void (*KernelFn)(NewtonArgs);
 
+struct Kernels {
+    KernelFn nearest = nullptr, newton32 = nullptr, newton = nullptr;
+    size_t lds_nearest = 0, lds_newton32 = 0, lds_newton = 0;
+};
+
 template <int D, int R, bool MIXED>
-void pick_kernels(int N, bool resolve, KernelFn &nn, KernelFn &nt, size_t &lds_nn,
-                  size_t &lds_nt)
+Kernels pick_kernels(int N, bool resolve)
 {
+    typedef typename std::conditional<MIXED, float, double>::type TN;
+    Kernels k;
 #define FPTS_CASE(NN)                                                                       \
     case NN:                                                                                \
-        nn = resolve ? k_nearest_resolve<D, R, NN, MIXED> : k_nearest<D, R, NN, MIXED>;     \
-        nt = resolve ? k_newton_resolve<D, R, NN, MIXED> : k_newton<D, R, NN, MIXED>;       \
-        lds_nn = sizeof(double) * D * Shape<D, R, NN>::NP;                                  \
-        lds_nt = Lds<double, D, R, NN>::bytes();                                            \
+        k.nearest = resolve ? k_nearest_resolve<D, R, NN, MIXED> : k_nearest<D, R, NN, MIXED>; \
+        k.newton = resolve ? k_newton_resolve<D, R, NN> : k_newton<D, R, NN>;               \
+        if (MIXED) k.newton32 = resolve ? k_newton32_resolve<D, R, NN> : k_newton32<D, R, NN>; \
+        k.lds_nearest = NearLds<TN, D, R, NN>::bytes();                                     \
+        k.lds_newton32 = Lds<float, D, R, NN>::bytes();                                     \
+        k.lds_newton = Lds<double, D, R, NN>::bytes();                                      \
         break;
     switch (N) {
         FPTS_CASE(2)
@@ -874,26 +1024,25 @@ void pick_kernels(int N, bool resolve, KernelFn &nn, KernelFn &nt, size_t &lds_n
         FPTS_CASE(9)
         FPTS_CASE(10)
     default:
-        nn = nt = nullptr;
-        lds_nn = lds_nt = 0;
+        break;
     }
 #undef FPTS_CASE
+    return k;
 }
 
-// Launches on the caller's stream: nearest nodes (which & 1; 64-pair tasks
-// over io.chunk_off, counter io.counter[0]), then Newton (which & 2; element
-// tasks, counter io.counter[8]).  io.counter[0..15] must be zero.  A list
+// Launches on the caller's stream: nearest nodes (which & 1; task grid of
+// 64-pair tasks over io.chunk_off, io.task_elem), then Newton (which & 2; element
+// tasks: in mixed mode the FP32 phase, counter io.counter[9], then the FP64
+// kernel, counter io.counter[8]).  io.counter[0..15] must be zero.  A list
 // with io.slot_pt set (other candidates) selects the *_resolve kernels.
 template <int D, int R>
 hipError_t launch_newton_kind(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
                               const NewtonIO &io, int which, hipStream_t s)
 {
-    KernelFn nn, nt;
-    size_t lds_nn, lds_nt;
     const bool resolve = io.slot_pt != nullptr;
-    if (mixed) pick_kernels<D, R, true>(m->N, resolve, nn, nt, lds_nn, lds_nt);
-    else pick_kernels<D, R, false>(m->N, resolve, nn, nt, lds_nn, lds_nt);
-    if (!nn) return hipErrorInvalidValue;
+    const Kernels k = mixed ? pick_kernels<D, R, true>(m->N, resolve)
+                            : pick_kernels<D, R, false>(m->N, resolve);
+    if (!k.nearest || !k.newton) return hipErrorInvalidValue;
     NewtonArgs a;
     a.nodes = m->d_nodes;
     a.nodes32 = m->d_nodes32;
@@ -908,12 +1057,18 @@ hipError_t launch_newton_kind(const fpts_mesh *m, bool mixed, int64_t n, const d
     a.max_iter32 = 10;
     a.tol32 = 1e-6f;
     if (which & 1) {
-        hipLaunchKernelGGL(nn, dim3(m->cus * 16), dim3(64), lds_nn, s, a);
+        hipLaunchKernelGGL(k.nearest, dim3(task_grid(io.task_bound, m->cus)), dim3(64),
+                           k.lds_nearest, s, a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (which & 2) {
-        hipLaunchKernelGGL(nt, dim3(m->cus * 8), dim3(64), lds_nt, s, a);
+        if (k.newton32) {
+            hipLaunchKernelGGL(k.newton32, dim3(m->cus * 8), dim3(64), k.lds_newton32, s, a);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k.newton, dim3(m->cus * 8), dim3(64), k.lds_newton, s, a);
         return hipGetLastError();
     }
     return hipSuccess;

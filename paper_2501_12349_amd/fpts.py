@@ -312,19 +312,25 @@ class Server:
         self._meshes.append((mesh, field, nf))
         return mid.value
 
-    def submit(self, mesh_id, pts, precision="fp64"):
-        """Queue find + eval of pts ([dim][n] float64 on the device); returns
-        (request id, output dict)."""
+    def outputs(self, mesh_id, n, device="cuda"):
+        """Output tensors for a request of n points against mesh_id."""
         import torch
+        mesh, field, nf = self._meshes[mesh_id]
+        return dict(code=torch.empty(n, dtype=torch.int32, device=device),
+                    elem=torch.empty(n, dtype=torch.int32, device=device),
+                    r=torch.empty((mesh.ref_dim, n), dtype=torch.float64, device=device),
+                    dist=torch.empty(n, dtype=torch.float64, device=device),
+                    u=torch.empty((max(nf, 1), n), dtype=torch.float64, device=device))
+
+    def submit(self, mesh_id, pts, precision="fp64", out=None):
+        """Queue find + eval of pts ([dim][n] float64 on the device) into out
+        (from outputs(); allocated here when None); returns (request id,
+        output dict)."""
         mesh, field, nf = self._meshes[mesh_id]
         pts = pts.contiguous()
         n = pts.shape[1]
-        dev = pts.device
-        out = dict(code=torch.empty(n, dtype=torch.int32, device=dev),
-                   elem=torch.empty(n, dtype=torch.int32, device=dev),
-                   r=torch.empty((mesh.ref_dim, n), dtype=torch.float64, device=dev),
-                   dist=torch.empty(n, dtype=torch.float64, device=dev),
-                   u=torch.empty((max(nf, 1), n), dtype=torch.float64, device=dev))
+        if out is None:
+            out = self.outputs(mesh_id, n, pts.device)
         rid = ctypes.c_int64()
         _check(load_library().fpts_server_submit(
             self._h, mesh_id, n, _dptr(pts), _dptr(out["code"]), _dptr(out["elem"]),

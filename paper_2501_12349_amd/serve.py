@@ -45,17 +45,21 @@ def make_requests(n_req, seed=1004, lo=3.0, hi=6.0, n_mesh=4, dim=3):
 def run(server, mesh_ids, sizes, meshes, pts, rate, precision="mixed", seed=7):
     """Submit the requests with exponential inter-arrival times of mean
     1/rate seconds (rate = inf: all at once), wait for all, and return the
-    latency and throughput summary."""
+    latency and throughput summary.  Output buffers are allocated before
+    the first arrival."""
+    import torch
     rng = np.random.default_rng(seed)
     n = len(sizes)
     gaps = np.zeros(n) if not np.isfinite(rate) else rng.exponential(1.0 / rate, size=n)
     arrive = np.cumsum(gaps)
+    outs = [server.outputs(mesh_ids[meshes[i]], int(sizes[i])) for i in range(n)]
+    torch.cuda.synchronize()
     rids = []
     t0 = time.perf_counter()
     for i in range(n):
         while time.perf_counter() - t0 < arrive[i]:
             pass
-        rid, _ = server.submit(mesh_ids[meshes[i]], pts[i], precision=precision)
+        rid, _ = server.submit(mesh_ids[meshes[i]], pts[i], precision=precision, out=outs[i])
         rids.append(rid)
     server.drain()
     lat, t_sub, t_done = [], [], []
@@ -73,3 +77,21 @@ def run(server, mesh_ids, sizes, meshes, pts, rate, precision="mixed", seed=7):
                 p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                 mean_ms=float(lat.mean()), makespan_s=float(span),
                 mpts_s=float(pts_total / span / 1e6))
+
+
+def sweep(server, mesh_ids, sizes, meshes, pts, loads=(0.5, 0.8, 1.0, 1.2), precision="mixed"):
+    """Saturation run (all requests at once) and Poisson runs at the given
+    fractions of the saturated request rate."""
+    run(server, mesh_ids, sizes[:8], meshes[:8], pts[:8], float("inf"), precision)   # warm-up
+    sat = run(server, mesh_ids, sizes, meshes, pts, float("inf"), precision)
+    rate_sat = sat["requests"] / sat["makespan_s"]
+    out = []
+    for k, ld in enumerate(loads):
+        rep = run(server, mesh_ids, sizes, meshes, pts, ld * rate_sat, precision, seed=100 + k)
+        rep["load"] = ld
+        out.append(rep)
+    st = server.stats()
+    return dict(saturation=sat, saturated_rate_req_s=rate_sat, loads=out,
+                batches=st["batches"], max_batch_requests=st["max_batch_requests"],
+                max_in_flight=st["max_in_flight"], peak_bytes=st["peak_bytes"],
+                budget_bytes=st["budget_bytes"])
