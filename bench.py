@@ -26,6 +26,7 @@ if ROOT not in sys.path:
 
 FP64_VALU_PEAK_TFLOPS = 78.6    # 256 CUs x 2.4 GHz x 128 FP64 flop/clk
 FP32_VALU_PEAK_TFLOPS = 157.3
+TRAFFIC_SUMMARY = "k_newton_hex48_p7_fp64_traffic.md"
 
 
 def log(*a):
@@ -196,7 +197,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU: the find/eval path has no "
-              "multi-GPU mode (points would shard across GPUs with the mesh replicated)", file=sys.stderr)
+              "multi-GPU mode (points would shard across GPUs with the mesh replicated)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -275,6 +277,13 @@ def main():
     main_mode = "fp64" if "fp64" in results else list(results)[0]
     r0 = results[main_mode]
     achieved = r0["flops"] / (r0["newton_ms"] * 1e-3) / 1e12
+    # HBM bytes per k_newton launch from the committed counter summary of this
+    # workload (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated); None when
+    # the Newton sources changed since the counters were taken
+    traffic = None
+    if args.workload == "hex48" and main_mode == "fp64":
+        from paper_2501_12349_amd import prof
+        traffic = prof.read_newton_traffic(os.path.join(ROOT, "profiles", TRAFFIC_SUMMARY))
     line = {
         "metric": "located+interpolated points/s (Mpts/s) FP64 vs mixed; p50/p99 request latency",
         "value": round(r0["mpts"], 3),
@@ -294,7 +303,7 @@ def main():
                    "step": "find + eval of all fields, inputs resident in HBM"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": traffic,
                      "kernel": "k_newton (FP64 trust-region Newton, primary candidates)",
                      "kernel_ms": round(r0["newton_ms"], 4),
                      "flops_per_launch": r0["flops"],

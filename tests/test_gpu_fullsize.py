@@ -1,0 +1,99 @@
+"""Full-size workloads in the launch configuration bench.py times.
+
+The GPU finds and interpolates every point of the workload with the same
+Mesh.find / Mesh.eval calls as bench.py; the oracle checks all of them where
+it finishes in seconds (16^3 hexes, 1.02M points) and a seeded random sample
+otherwise (48^3 hexes with 2^24 points; the cubed sphere with 2^22 points),
+point by point, to the same bars as the small parity tests."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_12349_amd import workloads as W
+from tests.parity import compare_eval, compare_find, to_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu_all(wl, precision):
+    from paper_2501_12349_amd import fpts
+    gm = fpts.Mesh(wl["nodes"], wl["N"], dim=wl["dim"], ref_dim=wl["ref_dim"])
+    tp = torch.from_numpy(np.ascontiguousarray(wl["pts"])).cuda()
+    res = gm.find(tp, precision=precision)
+    u = None
+    if wl.get("fields") is not None:
+        u = gm.eval(res, torch.from_numpy(wl["fields"]).cuda())
+    torch.cuda.synchronize()
+    out = to_np(res)
+    return out, (u.cpu().numpy() if u is not None else None)
+
+
+def _subset(gpu, u, idx):
+    g = {k: (v[:, idx] if v.ndim == 2 else v[idx]) for k, v in gpu.items()}
+    return g, (u[:, idx] if u is not None else None)
+
+
+def _check_sample(wl, om, precision, idx, surface=False):
+    print("full-size %s %s: %d points on the GPU, %d checked" % (
+        wl["name"], precision, wl["pts"].shape[1], len(idx)), flush=True)
+    sys.stdout.flush()
+    gpu, u = _gpu_all(wl, precision)
+    g, us = _subset(gpu, u, idx)
+    pts = np.ascontiguousarray(wl["pts"][:, idx])
+    orc = om.find(pts)
+    rep = compare_find(om, pts, orc, g, wl["h"], surface=surface)
+    if us is not None:
+        uo = om.eval(orc, wl["fields"])
+        same = g["elem"] == orc["elem"]
+        rep["eval_rel"] = compare_eval(uo[:, same], us[:, same], orc["code"][same])
+    # every point of the full run is accounted for
+    assert np.all(np.isin(gpu["code"], [oracle.INTERIOR, oracle.BORDER, oracle.NOT_FOUND]))
+    print(wl["name"], precision, rep, flush=True)
+    return rep
+
+
+@pytest.fixture(scope="module")
+def hex16():
+    wl = W.hex16()
+    return wl, oracle.Mesh(wl["nodes"], wl["dim"], wl["ref_dim"], wl["N"])
+
+
+@pytest.fixture(scope="module")
+def hex48():
+    wl = W.hex48()
+    return wl, oracle.Mesh(wl["nodes"], wl["dim"], wl["ref_dim"], wl["N"])
+
+
+@pytest.fixture(scope="module")
+def sphere():
+    wl = W.sphere()
+    return wl, oracle.Mesh(wl["nodes"], wl["dim"], wl["ref_dim"], wl["N"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_hex16_every_point(hex16, precision):
+    wl, om = hex16
+    rep = _check_sample(wl, om, precision, np.arange(wl["pts"].shape[1]))
+    assert rep["n"] == 1020000
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_hex48_sampled(hex48, precision):
+    wl, om = hex48
+    n = wl["pts"].shape[1]
+    idx = np.sort(np.random.default_rng(77).choice(n, size=6000, replace=False))
+    # plus the first and last points of the batch
+    idx = np.unique(np.concatenate([idx, [0, 1, n - 2, n - 1]]))
+    _check_sample(wl, om, precision, idx)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sphere_sampled(sphere, precision):
+    wl, om = sphere
+    n = wl["pts"].shape[1]
+    idx = np.sort(np.random.default_rng(78).choice(n, size=40000, replace=False))
+    _check_sample(wl, om, precision, idx, surface=True)
