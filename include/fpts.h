@@ -53,9 +53,12 @@ enum {
 /* Newton precision of fpts_find. */
 enum {
     FPTS_FP64 = 0,       /* every Newton pass in FP64 (the method as given) */
-    FPTS_MIXED = 1       /* FP32 passes in element-local coordinates, then
-                            FP64 passes from the FP32 result; boxes, codes,
-                            distances and the final residual are FP64 */
+    FPTS_MIXED = 1       /* primary candidates: FP32 passes in element-local
+                            coordinates, then FP64 passes from the FP32
+                            result; the second search over the other
+                            candidates of unsettled points is FP64; boxes,
+                            codes, distances and the final residual are
+                            FP64 */
 };
 
 /* Setup parameters (Section 3.1).  Zero-initialise, then set fields;
@@ -74,6 +77,14 @@ typedef struct fpts_params {
                            (Section 4.4 default 1e-10) */
     int max_iter;       /* Newton passes per candidate (Section 3.2.1: 50) */
     double newton_tol;  /* stop when ||dr||_inf < newton_tol (1e-10) */
+    int mixed_max_iter; /* FPTS_MIXED: FP32 passes per candidate at most */
+    double mixed_tol;   /* FPTS_MIXED: the FP32 phase ends when
+                           ||dr||_inf < mixed_tol (default 1e-3); the FP64
+                           phase then runs the full iteration to newton_tol,
+                           so this trades FP32 passes against FP64 passes
+                           only.  At 1e-3 the FP32 phase takes about two
+                           evaluations and the FP64 phase two (quadratic
+                           convergence from ~1e-6) */
 } fpts_params;
 
 typedef struct fpts_mesh fpts_mesh;

@@ -184,6 +184,8 @@ void fpts_params_default(fpts_params *p, int dim, int ref_dim, int nodes_1d, int
     p->surf_eps_d = 1e-10;
     p->max_iter = 50;
     p->newton_tol = 1e-10;
+    p->mixed_max_iter = 10;
+    p->mixed_tol = 1e-3;
 }
 
 const char *fpts_status_string(int s)
@@ -208,7 +210,8 @@ int fpts_setup(const fpts_params *p, const double *h_nodes, void *stream, fpts_m
     if (p->nodes_1d < 2 || p->nodes_1d > kMaxN) return FPTS_EINVAL;
     if (p->n_elem < 1 || p->n_elem > INT32_MAX / 2) return FPTS_EINVAL;
     if (!(p->bbox_tol >= 0.0) || !(p->newton_tol > 0.0) || p->max_iter < 1 ||
-        p->max_iter > 1000 || !(p->surf_eps_d >= 0.0) || p->hash_n < 0)
+        p->max_iter > 1000 || !(p->surf_eps_d >= 0.0) || p->hash_n < 0 ||
+        p->mixed_max_iter < 1 || p->mixed_max_iter > 1000 || !(p->mixed_tol > 0.0))
         return FPTS_EINVAL;
     if (sticky_error()) return FPTS_EDEVICE;
     fpts_mesh *m = new (std::nothrow) fpts_mesh();
@@ -368,7 +371,9 @@ int fpts_find(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         NewtonIO io{sorted2, elem_off2, chunk_off2, slot_pt, res_code, nullptr, res_r, w.cap2,
                     res_dist, counters + 2 * kNewtonCounters, stats + kStats, task_elem2,
                     w.tb_elem2};
-        chk(launch_newton(m, precision, n, d_pts, io, 3, s));
+        // the other candidates are few and near element faces: plain FP64
+        // in both modes (an FP32 phase would not pay for its launches)
+        chk(launch_newton(m, FPTS_FP64, n, d_pts, io, 3, s));
         chk(launch_select2(m, n, off2, primary, slot_elem, w.cap2, res_r, res_dist, res_code,
                            d_code, d_elem, d_r, d_dist, s));
     }

@@ -1054,8 +1054,8 @@ hipError_t launch_newton_kind(const fpts_mesh *m, bool mixed, int64_t n, const d
     a.max_iter = m->p.max_iter;
     a.tol = m->p.newton_tol;
     a.eps_d = m->p.surf_eps_d;
-    a.max_iter32 = 10;
-    a.tol32 = 1e-6f;
+    a.max_iter32 = m->p.mixed_max_iter;
+    a.tol32 = (float)m->p.mixed_tol;
     if (which & 1) {
         hipLaunchKernelGGL(k.nearest, dim3(task_grid(io.task_bound, m->cus)), dim3(64),
                            k.lds_nearest, s, a);

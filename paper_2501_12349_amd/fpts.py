@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
                 ("nodes_1d", ctypes.c_int), ("hash_n", ctypes.c_int),
                 ("n_elem", ctypes.c_int64), ("bbox_tol", ctypes.c_double),
                 ("surf_eps_d", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("newton_tol", ctypes.c_double)]
+                ("newton_tol", ctypes.c_double), ("mixed_max_iter", ctypes.c_int),
+                ("mixed_tol", ctypes.c_double)]
 
 
 class FindStats(ctypes.Structure):
@@ -130,7 +131,8 @@ class Mesh:
     shape; pass ref_dim=2 with dim=3 for surface quads."""
 
     def __init__(self, nodes, nodes_1d, dim=None, ref_dim=None, bbox_tol=0.1, hash_n=0,
-                 surf_eps_d=1e-10, max_iter=50, newton_tol=1e-10, stream=None):
+                 surf_eps_d=1e-10, max_iter=50, newton_tol=1e-10, mixed_tol=None,
+                 mixed_max_iter=None, stream=None):
         import torch
         if not torch.cuda.is_available():
             raise FptsError("no HIP device visible")
@@ -144,6 +146,10 @@ class Mesh:
         L.fpts_params_default(ctypes.byref(p), dim, ref_dim, nodes_1d, nel)
         p.bbox_tol, p.hash_n, p.surf_eps_d = bbox_tol, hash_n, surf_eps_d
         p.max_iter, p.newton_tol = max_iter, newton_tol
+        if mixed_tol is not None:
+            p.mixed_tol = mixed_tol
+        if mixed_max_iter is not None:
+            p.mixed_max_iter = mixed_max_iter
         if NP != nodes_1d ** ref_dim or D != dim:
             raise FptsError("nodes shape %s does not match dim/ref_dim/nodes_1d" %
                             (nodes.shape,))

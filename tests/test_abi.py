@@ -41,6 +41,7 @@ def test_defaults_and_status_strings():
     L.fpts_params_default(ctypes.byref(p), 3, 3, 8, 1000)
     assert (p.dim, p.ref_dim, p.nodes_1d, p.n_elem) == (3, 3, 8, 1000)
     assert p.bbox_tol == 0.1 and p.max_iter == 50 and p.newton_tol == 1e-10
+    assert p.mixed_max_iter == 10 and p.mixed_tol == 1e-3
     assert p.surf_eps_d == 1e-10 and p.hash_n == 0
     assert L.fpts_status_string(0) == b"ok"
     assert L.fpts_status_string(-1) == b"invalid argument"
