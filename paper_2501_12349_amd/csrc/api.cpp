@@ -84,6 +84,7 @@ void free_mesh(fpts_mesh *m)
     clear_events(m);
     (void)hipFree(m->d_nodes);
     (void)hipFree(m->d_nodes32);
+    (void)hipFree(m->d_near);
     (void)hipFree(m->d_xc);
     (void)hipFree(m->d_box);
     (void)hipFree(m->d_cell_off);
@@ -241,8 +242,11 @@ int fpts_setup(const fpts_params *p, const double *h_nodes, void *stream, fpts_m
     hipStream_t s = (hipStream_t)stream;
     const size_t nn = (size_t)m->nel * m->D * m->NP;
     const size_t nb = m->box.size(), nx = m->xc.size();
+    m->near_npad = (m->NP + 31) / 32 * 32;
+    const size_t nr = (size_t)m->nel * 4 * m->near_npad;
     bool ok = hipMalloc(&m->d_nodes, sizeof(double) * nn) == hipSuccess &&
               hipMalloc(&m->d_nodes32, sizeof(float) * nn) == hipSuccess &&
+              hipMalloc(&m->d_near, sizeof(double) * nr) == hipSuccess &&
               hipMalloc(&m->d_xc, sizeof(double) * nx) == hipSuccess &&
               hipMalloc(&m->d_box, sizeof(double) * nb) == hipSuccess &&
               hipMalloc(&m->d_cell_off, sizeof(int) * m->cell_off.size()) == hipSuccess &&
@@ -262,7 +266,8 @@ int fpts_setup(const fpts_params *p, const double *h_nodes, void *stream, fpts_m
                         hipMemcpyHostToDevice, s) == hipSuccess &&
          hipMemcpyAsync(m->d_cell_el, m->cell_el.data(), sizeof(int) * m->cell_el.size(),
                         hipMemcpyHostToDevice, s) == hipSuccess &&
-         launch_nodes32(m, s) == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
+         launch_nodes32(m, s) == hipSuccess && launch_near_rows(m, s) == hipSuccess &&
+         hipStreamSynchronize(s) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         free_mesh(m);

@@ -131,6 +131,8 @@ struct fpts_mesh {
     // device copies
     double *d_nodes = nullptr;    // [nel][D][NP]
     float *d_nodes32 = nullptr;   // [nel][D][NP] x - x_c in FP32 (mixed mode)
+    double *d_near = nullptr;     // [nel][4][near_npad] nearest-node score rows (FP64)
+    int near_npad = 0;
     double *d_xc = nullptr;       // [nel][D]
     double *d_box = nullptr;
     int *d_cell_off = nullptr, *d_cell_el = nullptr;
@@ -190,6 +192,10 @@ hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fie
                        const int *elem_off, const int *chunk_off, const int *task_elem,
                        int64_t task_bound, hipStream_t s);
 hipError_t launch_nodes32(const fpts_mesh *m, hipStream_t s);
+// score rows of the nearest-node contraction: per element and node j,
+// (-2 x_j, -2 y_j, -2 z_j, |x_j|^2) element-local (D = 2: (-2x, -2y, |x|^2, 0)),
+// padding columns j >= N^R score 1e300
+hipError_t launch_near_rows(const fpts_mesh *m, hipStream_t s);
 
 // Newton launchers per element kind (kernels_newton_*.hip)
 hipError_t launch_newton_hex(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,

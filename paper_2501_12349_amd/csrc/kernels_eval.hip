@@ -122,6 +122,30 @@ __global__ void k_nodes32(const double *nodes, const double *xc, float *out, int
     }
 }
 
+__global__ void k_near_rows(const double *nodes, const double *xc, double *rows, int64_t nel,
+                            int D, int NP, int npad)
+{
+    const int64_t total = nel * npad;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = i / npad;
+        const int j = (int)(i % npad);
+        double b[4] = {0.0, 0.0, 0.0, 0.0};
+        if (j < NP) {
+            double n2 = 0.0;
+            for (int c = 0; c < D; ++c) {
+                const double v = nodes[(e * D + c) * NP + j] - xc[e * D + c];
+                b[c] = -2.0 * v;
+                n2 = fma(v, v, n2);
+            }
+            b[D] = n2;
+        } else {
+            b[D] = 1e300;
+        }
+        for (int k = 0; k < 4; ++k) rows[(e * 4 + k) * npad + j] = b[k];
+    }
+}
+
 typedef void (*EvalFn)(EvalArgs);
 
 template <int R>
@@ -174,6 +198,15 @@ hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fie
     a.task_elem = task_elem;
     a.basis = m->basis;
     hipLaunchKernelGGL(fn, dim3(task_grid(task_bound, m->cus)), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_near_rows(const fpts_mesh *m, hipStream_t s)
+{
+    const int64_t total = m->nel * m->near_npad;
+    const int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_near_rows, dim3(grid), dim3(256), 0, s, m->d_nodes, m->d_xc, m->d_near,
+                       (int64_t)m->nel, m->D, m->NP, m->near_npad);
     return hipGetLastError();
 }
 

@@ -458,6 +458,7 @@ __device__ __forceinline__ bool on_face(const T (&r)[R])
 struct NewtonArgs {
     const double *nodes;     // [nel][D][NP]
     const float *nodes32;    // [nel][D][NP] x - x_c (mixed mode)
+    const double *near;      // [nel][4][NearLds NPAD] nearest-node score rows (FP64)
     const double *xc;        // [nel][D]     (mixed mode)
     const double *pts;       // [D][n]
     int n;
@@ -771,13 +772,19 @@ __device__ __forceinline__ void stage(T *lds, const T *src, int lane)
     __syncthreads();
 }
 
-// LDS of the nearest-node kernel: B operand rows [4][NPAD] (-2 x_j, -2 y_j,
+// Nearest-node contraction operands: B rows [4][NPAD] (-2 x_j, -2 y_j,
 // -2 z_j, |x_j|^2 of every node j, element-local; padding columns score a
-// large constant), A operand rows [4][64] (x, y, z, 1 of each pair), item ids.
+// large constant) and A rows [4][64] (x, y, z, 1 of each pair).  FP64 reads
+// B from rows precomputed at setup (L2-resident per element), so its LDS
+// holds only A and the item ids; FP32 builds B in LDS from the FP32 nodes.
 template <typename T, int D, int R, int N>
 struct NearLds {
     static constexpr int NPAD = (Shape<D, R, N>::NP + 31) / 32 * 32;   // even tile count
-    static constexpr size_t bytes() { return sizeof(T) * 4 * (NPAD + 64) + sizeof(int) * 64; }
+    static constexpr bool B_IN_LDS = std::is_same<T, float>::value;
+    static constexpr size_t bytes()
+    {
+        return sizeof(T) * 4 * ((B_IN_LDS ? NPAD : 0) + 64) + sizeof(int) * 64;
+    }
 };
 
 // Nearest element node of up to 64 pairs of one element (Euclidean; among
@@ -798,9 +805,9 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
     constexpr int NT = L::NPAD / 16;
     const T kBig = MIXED ? T(1e30f) : T(1e300);
     extern __shared__ double lds_raw[];
-    T *Bt = reinterpret_cast<T *>(lds_raw);            // [4][NPAD]
-    T *Pt = Bt + 4 * L::NPAD;                          // [4][64]
-    int *items = reinterpret_cast<int *>(Pt + 4 * 64); // [64]
+    T *Bt = reinterpret_cast<T *>(lds_raw);                  // [4][NPAD] (FP32)
+    T *Pt = Bt + (L::B_IN_LDS ? 4 * L::NPAD : 0);            // [4][64]
+    int *items = reinterpret_cast<int *>(Pt + 4 * 64);       // [64]
     const int lane = threadIdx.x, col = lane & 15, g = lane >> 4;
     const NewtonIO &io = a.io;
     const int total = io.chunk_off[a.nel];
@@ -812,9 +819,9 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
 #pragma unroll
         for (int c = 0; c < D; ++c) xc[c] = a.xc[(size_t)e * D + c];
         wave_lds_sync();   // the previous task's reads come first
-        // B rows of the element's nodes
+        // B rows of the element's nodes (FP32; FP64 reads the setup rows)
 #pragma unroll 1
-        for (int j = lane; j < L::NPAD; j += kWave) {
+        for (int j = lane; L::B_IN_LDS && j < L::NPAD; j += kWave) {
             T b[4] = {T(0), T(0), T(0), T(0)};
             if (j < S::NP) {
                 T n2 = T(0);
@@ -860,7 +867,9 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
             }
 #pragma unroll 2
             for (int nt = 0; nt < NT; ++nt) {
-                const T bv = Bt[g * L::NPAD + 16 * nt + col];
+                const T bv = L::B_IN_LDS
+                                 ? Bt[g * L::NPAD + 16 * nt + col]
+                                 : T(a.near[((size_t)e * 4 + g) * L::NPAD + 16 * nt + col]);
                 const v4 d = mfma16(av, bv, v4{0, 0, 0, 0});
                 const int node = 16 * nt + col;
 #pragma unroll
@@ -1046,6 +1055,8 @@ hipError_t launch_newton_kind(const fpts_mesh *m, bool mixed, int64_t n, const d
     NewtonArgs a;
     a.nodes = m->d_nodes;
     a.nodes32 = m->d_nodes32;
+    a.near = m->d_near;
+    if (m->near_npad != (m->NP + 31) / 32 * 32) return hipErrorInvalidValue;
     a.xc = m->d_xc;
     a.pts = pts;
     a.n = (int)n;
