@@ -108,6 +108,20 @@ int fpts_setup(const fpts_params *p, const double *h_nodes, void *stream,
  * device first).  NULL is accepted. */
 int fpts_destroy(fpts_mesh *m);
 
+/* Move the mesh: d_nodes [n_elem][dim][nodes_1d^ref_dim] (device memory,
+ * the layout of fpts_setup; may be the caller's or any buffer) become the
+ * mesh's nodes, and everything fpts_setup derives from them -- element
+ * AABB and OBB (Sections 3.1.1, 3.1.2, 4.1, 4.2), centres and the local
+ * map (Section 3.1.3) -- is recomputed on the device, for meshes that move
+ * between searches (the r-adaptivity and tangential-relaxation uses of
+ * Section 6).  Element count, nodes_1d, parameters and the map resolution
+ * N_L stay.  The results equal those of fpts_setup on the same nodes bit
+ * for bit.  Synchronises `stream` (the map size is read back); workspace
+ * sizes may grow, so query them again.  FPTS_EINVAL (null arguments, or
+ * nodes whose boxes are not finite), FPTS_ENOMEM, FPTS_EDEVICE; after an
+ * error the mesh must be destroyed. */
+int fpts_update_nodes(fpts_mesh *m, const double *d_nodes, void *stream);
+
 /* Bytes of device workspace fpts_find needs for n points (an upper bound
  * that assumes every point hits the largest cell of the local map), or 0
  * when n is out of range. */

@@ -24,14 +24,17 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 SOURCES = ["kernels_newton_hex.hip", "kernels_newton_surf.hip", "kernels_newton_quad.hip",
-           "kernels_find.hip", "kernels_eval.hip", "api.cpp", "setup.cpp", "serve.cpp"]
+           "kernels_find.hip", "kernels_eval.hip", "setup_device.hip", "api.cpp", "setup.cpp",
+           "serve.cpp"]
+# the device setup reproduces the host setup's rounding: no contraction
+EXTRA = {"setup_device.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src):
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src + ".o")
     lang = ["-x", "hip"]
-    cmd = [HIPCC] + COMMON + lang + ["-c", path, "-o", obj]
+    cmd = [HIPCC] + COMMON + EXTRA.get(src, []) + lang + ["-c", path, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))

@@ -498,6 +498,24 @@ int fpts_profile_read(fpts_mesh *m, fpts_kernel_times *out)
     return FPTS_OK;
 }
 
+int fpts_update_nodes(fpts_mesh *m, const double *d_nodes, void *stream)
+{
+    if (!m || !d_nodes) return FPTS_EINVAL;
+    if (sticky_error()) return FPTS_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nn = (size_t)m->nel * m->D * m->NP;
+    if (d_nodes != m->d_nodes &&
+        hipMemcpyAsync(m->d_nodes, d_nodes, sizeof(double) * nn, hipMemcpyDeviceToDevice, s) !=
+            hipSuccess)
+        return FPTS_EDEVICE;
+    const int st = device_setup(m, s);
+    if (st != FPTS_OK) return st;
+    if (launch_nodes32(m, s) != hipSuccess || launch_near_rows(m, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return FPTS_EDEVICE;
+    return FPTS_OK;
+}
+
 int fpts_get_boxes(const fpts_mesh *m, double *h_aabb, double *h_obb_A, double *h_obb_c)
 {
     if (!m) return FPTS_EINVAL;

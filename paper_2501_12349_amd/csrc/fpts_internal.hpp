@@ -143,6 +143,24 @@ namespace fpts {
 // host setup (setup.cpp)
 int host_setup(fpts_mesh *m, const double *h_nodes);
 
+// Basis-bound tables of Section 3.1.1 (built on the host, M = 2N Chebyshev
+// points), the Legendre moments of the bases and the bases at r = 0, as the
+// device setup reads them.
+struct BoundTables {
+    int N, M;
+    double eta[2 * kMaxN];
+    double vlo[kMaxN * 2 * kMaxN], vhi[kMaxN * 2 * kMaxN];   // [N][M]
+    double mom0[kMaxN], mom1[kMaxN];
+    double z[kMaxN];
+    double v0[kMaxN], d0[kMaxN];
+};
+void bound_tables(const fpts_mesh *m, BoundTables *t);
+
+// Device setup (setup_device.hip): boxes and centres of every element from
+// m->d_nodes into m->d_box / m->d_xc, then the local map, with the same
+// arithmetic in the same order as host_setup; updates the host copies.
+int device_setup(fpts_mesh *m, hipStream_t s);
+
 // workspace layouts (api.cpp)
 FindWs find_ws_layout(const fpts_mesh *m, int64_t n);
 EvalWs eval_ws_layout(const fpts_mesh *m, int64_t n);

@@ -424,6 +424,27 @@ int cell_coord(const fpts_mesh *m, int d, double x)
 
 }  // namespace
 
+void bound_tables(const fpts_mesh *m, BoundTables *t)
+{
+    const int N = m->N;
+    Tables T;
+    make_tables(m->basis, N, T);
+    std::memset(t, 0, sizeof(*t));
+    t->N = N;
+    t->M = T.M;
+    for (int j = 0; j < T.M; ++j) t->eta[j] = T.eta[j];
+    for (int a = 0; a < N * T.M; ++a) {
+        t->vlo[a] = T.vlo[a];
+        t->vhi[a] = T.vhi[a];
+    }
+    for (int i = 0; i < N; ++i) {
+        t->mom0[i] = T.mom0[i];
+        t->mom1[i] = T.mom1[i];
+        t->z[i] = m->basis.z[i];
+    }
+    basis_eval(m->basis, N, 0.0, t->v0, t->d0);
+}
+
 int host_setup(fpts_mesh *m, const double *h_nodes)
 {
     const int D = m->D, N = m->N, W = box_words(D);

@@ -15,7 +15,7 @@ FP64, MIXED = 0, 1
 _PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
 
 # Entry points declared in include/fpts.h.
-EXPORTS = ("fpts_params_default", "fpts_setup", "fpts_destroy",
+EXPORTS = ("fpts_params_default", "fpts_setup", "fpts_destroy", "fpts_update_nodes",
            "fpts_find_workspace_size", "fpts_find", "fpts_eval_workspace_size",
            "fpts_eval", "fpts_find_stats_get", "fpts_profile", "fpts_profile_read",
            "fpts_get_boxes", "fpts_get_hash", "fpts_status_string")
@@ -79,6 +79,7 @@ def load_library(path=LIB_PATH):
     L.fpts_params_default.restype = None
     L.fpts_setup.argtypes = [ctypes.POINTER(Params), vp, vp, ctypes.POINTER(vp)]
     L.fpts_destroy.argtypes = [vp]
+    L.fpts_update_nodes.argtypes = [vp, vp, vp]
     L.fpts_find_workspace_size.argtypes = [vp, i64]
     L.fpts_find_workspace_size.restype = ctypes.c_size_t
     L.fpts_find.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, vp, ctypes.c_size_t, vp]
@@ -172,6 +173,21 @@ class Mesh:
             pass
 
     # -- workspaces
+    def update_nodes(self, nodes, stream=None):
+        """Move the mesh (fpts_update_nodes): nodes [n_elem][dim][NP] float64,
+        a device tensor or a host array (copied to the device first); boxes,
+        centres and the local map are recomputed on the device."""
+        import torch
+        if not isinstance(nodes, torch.Tensor):
+            nodes = torch.from_numpy(np.ascontiguousarray(nodes, dtype=np.float64)).cuda()
+        if nodes.dtype != torch.float64 or not nodes.is_cuda or \
+                tuple(nodes.shape) != (self.n_elem, self.dim, self.NP):
+            raise FptsError("nodes must be a float64 device tensor [%d][%d][%d]" % (
+                self.n_elem, self.dim, self.NP))
+        nodes = nodes.contiguous()
+        _check(load_library().fpts_update_nodes(self._h, _dptr(nodes), _stream_ptr(stream)))
+        self._ws = None
+
     def find_workspace_bytes(self, n):
         return load_library().fpts_find_workspace_size(self._h, n)
 
