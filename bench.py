@@ -5,7 +5,9 @@ selection) + fpts_eval of all fields, over one batch of device-resident
 points.  Default workload: 48^3 curved hexes, p = 7 (N = 8 GLL nodes per
 direction), 2^24 points uniform in the cube, 3 fields.  Both Newton
 precisions are timed (FP64, and FP32 passes + FP64 polish); `value` is the
-FP64 path, the mixed result sits beside it.
+FP64 path, the mixed result sits beside it.  Beside them: the particle
+tracking loop of the paper's channel case (fpts_lpt_step), device-side
+setup, host-to-host throughput, the serving loop and the oracle on the CPU.
 
 Prints one JSON line (see the driver contract) with a roofline object for
 the dominant kernel (trust-region Newton, measured with HIP events on the
@@ -178,6 +180,71 @@ def serving(n_req, budget):
                 max_in_flight=rep["max_in_flight"], peak_bytes=rep["peak_bytes"])
 
 
+def particle_tracking(ratios, steps, warmup, precision):
+    """The particle-tracking loop of the paper's channel case: 36 x 24 x 36
+    hexes with p = 7 (15.9M computational points), a frozen synthetic
+    fluid velocity, tau = 5, dt = 1e-3, particles on a 2:1:1 lattice with
+    `ratio` particles per computational point.  One step = Interpolate +
+    particle update + Find of every particle (fpts_lpt_step); the time of
+    each part comes from HIP events on the stream."""
+    import torch
+    from paper_2501_12349_amd import fpts
+    from paper_2501_12349_amd import workloads as W
+    t0 = time.perf_counter()
+    wl = W.channel(ratio=ratios[0])
+    gm = fpts.Mesh(wl["nodes"], wl["N"])
+    field = torch.from_numpy(wl["fields"]).cuda()
+    log("particle tracking: %s (%d elements) ready in %.1f s" % (
+        wl["name"], wl["nodes"].shape[0], time.perf_counter() - t0))
+    out = []
+    for ratio in ratios:
+        n_y = W.lattice_n_y(ratio, wl["n_comp"])
+        pts = W.particle_lattice(n_y)
+        v0 = W.channel_velocity(pts, wl["modes"])
+        n = pts.shape[1]
+        P = fpts.Particles(torch.from_numpy(pts).cuda(), torch.from_numpy(v0).cuda(), wl["tau"],
+                           wl["dt"], wl["lo"], wl["hi"], wl["periodic"]).start(gm, precision)
+        del pts, v0
+        ws = torch.empty(gm.lpt_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+        for k in range(warmup):
+            gm.lpt_step(P, field, first=(k == 0), precision=precision, ws=ws)
+        torch.cuda.synchronize()
+        gm.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            gm.lpt_step(P, field, first=(warmup == 0 and k == 0), precision=precision, ws=ws)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        kt = gm.profile_read()
+        gm.profile(False)
+        lost = int((P.find["code"] == fpts.NOT_FOUND).sum().item())
+        c = max(kt["lpt_calls"], 1)
+        find_ms = (kt["locate_ms"] + kt["nearest_ms"] + kt["newton_ms"] + kt["select_ms"]) / c
+        interp_ms = (kt["eval_bin_ms"] + kt["eval_ms"]) / c
+        adv_ms = kt["advance_ms"] / c
+        tot = find_ms + interp_ms + adv_ms
+        rep = dict(ratio=ratio, particles=n, ms_per_step=round(dt * 1e3, 4),
+                   mparticle_steps_per_s=round(n / dt / 1e6, 3),
+                   find_ms=round(find_ms, 4), interpolate_ms=round(interp_ms, 4),
+                   advance_ms=round(adv_ms, 4),
+                   fractions=dict(find=round(find_ms / tot, 4),
+                                  interpolate=round(interp_ms / tot, 4),
+                                  advance=round(adv_ms / tot, 4)),
+                   not_found=lost)
+        log("particle tracking %.2f particles/point (%d): %.3f ms/step  %.1f M particle-steps/s  "
+            "find %.3f interpolate %.3f advance %.3f ms  lost %d" % (
+                ratio, n, dt * 1e3, n / dt / 1e6, find_ms, interp_ms, adv_ms, lost))
+        out.append(rep)
+        del P, ws
+        torch.cuda.empty_cache()
+    return dict(workload="%s_%dhex_tau%g_dt%g" % (wl["name"], wl["nodes"].shape[0], wl["tau"],
+                                                   wl["dt"]),
+                n_comp=wl["n_comp"], precision=precision, steps=steps, warmup=warmup,
+                step="interpolate (3 fields) + drag/AB2/boundary + find, fpts_lpt_step",
+                runs=out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,7 +260,15 @@ def main():
     ap.add_argument("--pcie-steps", type=int, default=3,
                     help="steps of the host-to-host measurement (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="run a 1 GiB device copy first (HBM counter calibration)")
+                    help="run a 1 GiB device copy first (HBM counter calibration); "
+                         "implies --no-setup-device, whose node copy is larger")
+    ap.add_argument("--no-setup-device", action="store_true",
+                    help="skip timing the device-side setup (fpts_update_nodes)")
+    ap.add_argument("--lpt-ratios", default="1.02",
+                    help="particles per computational point of the particle-tracking runs "
+                         "(comma list; empty: skip)")
+    ap.add_argument("--lpt-steps", type=int, default=10,
+                    help="timed steps per particle-tracking run (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU: the find/eval path has no "
@@ -218,14 +293,17 @@ def main():
     log("setup %.2f s (host boxes + map, upload)" % t_setup)
     # setup on the device from nodes already there (fpts_update_nodes, the
     # moving-mesh path), timed after a first call
-    d_nodes = torch.from_numpy(wl["nodes"]).to(dev)
-    gm.update_nodes(d_nodes)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    gm.update_nodes(d_nodes)
-    t_setup_dev = time.perf_counter() - t0
-    del d_nodes
-    log("device setup %.1f ms (boxes, centres, local map from device nodes)" % (t_setup_dev * 1e3))
+    t_setup_dev = None
+    if not (args.no_setup_device or args.calib_copy):
+        d_nodes = torch.from_numpy(wl["nodes"]).to(dev)
+        gm.update_nodes(d_nodes)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gm.update_nodes(d_nodes)
+        t_setup_dev = time.perf_counter() - t0
+        del d_nodes
+        log("device setup %.1f ms (boxes, centres, local map from device nodes)"
+            % (t_setup_dev * 1e3))
     pts = torch.from_numpy(wl["pts"]).to(dev)
     fields = torch.from_numpy(wl["fields"]).to(dev)
     nf = fields.shape[0]
@@ -319,7 +397,7 @@ def main():
                      "flops_per_launch": r0["flops"],
                      "slot_use": slot_use(r0["stats"])},
         "setup_s": round(t_setup, 3),
-        "setup_device_s": round(t_setup_dev, 4),
+        "setup_device_s": round(t_setup_dev, 4) if t_setup_dev is not None else None,
         "codes": dict(zip(("interior", "border", "not_found"), r0["codes"])),
     }
     if "mixed" in results and main_mode != "mixed":
@@ -340,6 +418,9 @@ def main():
             line["pcie_inclusive"]["value"])
     del ws_f, ws_e, out, u, pts
     torch.cuda.empty_cache()
+    if args.lpt_ratios and args.lpt_steps > 0:
+        line["particle_tracking"] = particle_tracking(
+            [float(r) for r in args.lpt_ratios.split(",")], args.lpt_steps, 2, main_mode)
     if args.serve_requests > 0:
         line["serving"] = serving(args.serve_requests, int(args.serve_budget_gb * (1 << 30)))
     if not args.no_cpu:

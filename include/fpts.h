@@ -191,9 +191,9 @@ int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws,
  * candidate search and the scans), nearest (the nearest-node start of the
  * primary pass), newton (the trust-region Newton kernel of the primary pass
  * alone), select (start, Newton and selection over the other candidates of
- * unsettled points), eval_bin and eval (point binning and interpolation).
- * Sums over the calls since profiling was enabled.  Meant for one stream at
- * a time. */
+ * unsettled points), eval_bin and eval (point binning and interpolation),
+ * advance (the particle update of fpts_lpt_step, fpts_lpt.h).  Sums over
+ * the calls since profiling was enabled.  Meant for one stream at a time. */
 typedef struct fpts_kernel_times {
     double locate_ms;
     double nearest_ms;
@@ -201,8 +201,10 @@ typedef struct fpts_kernel_times {
     double select_ms;
     double eval_bin_ms;
     double eval_ms;
+    double advance_ms;
     int64_t find_calls;
     int64_t eval_calls;
+    int64_t lpt_calls;
 } fpts_kernel_times;
 
 /* enable != 0 starts recording (clearing earlier records); 0 stops. */

@@ -24,10 +24,11 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 SOURCES = ["kernels_newton_hex.hip", "kernels_newton_surf.hip", "kernels_newton_quad.hip",
-           "kernels_find.hip", "kernels_eval.hip", "setup_device.hip", "api.cpp", "setup.cpp",
+           "kernels_find.hip", "kernels_eval.hip", "setup_device.hip", "lpt.hip", "api.cpp", "setup.cpp",
            "serve.cpp"]
-# the device setup reproduces the host setup's rounding: no contraction
-EXTRA = {"setup_device.hip": ["-ffp-contract=off"]}
+# the device setup reproduces the host setup's rounding and the particle
+# update rounds operation by operation: no contraction
+EXTRA = {"setup_device.hip": ["-ffp-contract=off"], "lpt.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src):

@@ -8,6 +8,7 @@
 #include <new>
 
 #include "fpts_internal.hpp"
+#include "fpts_lpt.h"
 
 using namespace fpts;
 
@@ -51,7 +52,7 @@ void clear_events(fpts_mesh *m)
         }
         v.clear();
     }
-    m->prof_find = m->prof_eval = 0;
+    m->prof_find = m->prof_eval = m->prof_lpt = 0;
 }
 
 // Records an event pair around a kernel group when profiling is on.
@@ -490,8 +491,10 @@ int fpts_profile_read(fpts_mesh *m, fpts_kernel_times *out)
     out->select_ms = ms[3];
     out->eval_bin_ms = ms[4];
     out->eval_ms = ms[5];
+    out->advance_ms = ms[6];
     out->find_calls = m->prof_find;
     out->eval_calls = m->prof_eval;
+    out->lpt_calls = m->prof_lpt;
     const bool on = m->profiling;
     clear_events(m);
     m->profiling = on;
@@ -548,6 +551,71 @@ int fpts_get_hash(const fpts_mesh *m, double *h_lo, double *h_hi, double *h_delt
     if (nnz) *nnz = (int64_t)m->cell_off.back();
     if (max_cell) *max_cell = m->max_cell;
     return FPTS_OK;
+}
+
+
+size_t fpts_lpt_workspace_size(const fpts_mesh *m, int64_t n)
+{
+    if (!m || n < 0 || n > INT32_MAX - 1) return 0;
+    const size_t fw = fpts_find_workspace_size(m, n);
+    if (fw == 0) return 0;
+    const size_t ew = eval_ws_layout(m, n).total;
+    return align_up(sizeof(double) * (size_t)m->D * (size_t)std::max<int64_t>(n, 1)) +
+           std::max(fw, ew);
+}
+
+int fpts_lpt_step(fpts_mesh *m, const fpts_lpt_params *p, int64_t n, int first, double *d_x,
+                  double *d_v, double *d_hist, const double *d_field, int32_t *d_code,
+                  int32_t *d_elem, double *d_r, double *d_dist, int precision, void *d_ws,
+                  size_t ws_bytes, void *stream)
+{
+    if (!m || !p || n < 0 || n > INT32_MAX - 1 || m->R != m->D) return FPTS_EINVAL;
+    if (!(std::isfinite(p->tau) && p->tau > 0) || !(std::isfinite(p->dt) && p->dt > 0))
+        return FPTS_EINVAL;
+    for (int d = 0; d < m->D; ++d)
+        if (!(std::isfinite(p->lo[d]) && std::isfinite(p->hi[d]) && p->lo[d] < p->hi[d]) ||
+            (p->periodic[d] != 0 && p->periodic[d] != 1))
+            return FPTS_EINVAL;
+    if (precision != FPTS_FP64 && precision != FPTS_MIXED) return FPTS_EINVAL;
+    if (n == 0) return FPTS_OK;
+    if (!d_x || !d_v || !d_hist || !d_field || !d_code || !d_elem || !d_r || !d_dist || !d_ws)
+        return FPTS_EINVAL;
+    if (((uintptr_t)d_ws & 255) != 0) return FPTS_EINVAL;
+    const size_t need = fpts_lpt_workspace_size(m, n);
+    if (need == 0 || ws_bytes < need) return FPTS_EINVAL;
+    if (sticky_error()) return FPTS_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    // [D][n] interpolated fluid velocity, then the Find / Interpolate space
+    const size_t u_bytes = align_up(sizeof(double) * (size_t)m->D * (size_t)n);
+    double *u = static_cast<double *>(d_ws);
+    void *sub = static_cast<char *>(d_ws) + u_bytes;
+    const size_t sub_bytes = ws_bytes - u_bytes;
+    int st = fpts_eval(m, n, d_code, d_elem, d_r, m->D, d_field, u, sub, sub_bytes, stream);
+    if (st != FPTS_OK) return st;
+    LptArgs a;
+    a.x = d_x;
+    a.v = d_v;
+    a.hist_v = d_hist;
+    a.hist_a = d_hist + (size_t)m->D * (size_t)n;
+    a.u = u;
+    a.code = d_code;
+    a.n = n;
+    a.tau = p->tau;
+    a.dt = p->dt;
+    for (int d = 0; d < 3; ++d) {
+        a.lo[d] = d < m->D ? p->lo[d] : 0.0;
+        a.hi[d] = d < m->D ? p->hi[d] : 1.0;
+        a.periodic[d] = d < m->D ? p->periodic[d] : 0;
+    }
+    a.first = first != 0;
+    hipError_t e;
+    {
+        Span sp(m, 6, s);
+        e = launch_lpt_advance(m, a, s);
+    }
+    if (e != hipSuccess) return FPTS_EDEVICE;
+    if (m->profiling) m->prof_lpt++;
+    return fpts_find(m, n, d_x, d_code, d_elem, d_r, d_dist, precision, sub, sub_bytes, stream);
 }
 
 }  // extern "C"

@@ -108,7 +108,7 @@ struct NewtonIO {
 
 // profiling spans: locate, nearest-node start, Newton (primary pass), select
 // (other candidates + selection), eval binning, eval
-constexpr int kSpans = 6;
+constexpr int kSpans = 7;
 
 struct fpts_mesh {
     fpts_params p;
@@ -127,7 +127,7 @@ struct fpts_mesh {
     // profiling: event pairs per kernel group
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kSpans];
-    int64_t prof_find = 0, prof_eval = 0;
+    int64_t prof_find = 0, prof_eval = 0, prof_lpt = 0;
     // device copies
     double *d_nodes = nullptr;    // [nel][D][NP]
     float *d_nodes32 = nullptr;   // [nel][D][NP] x - x_c in FP32 (mixed mode)
@@ -222,5 +222,19 @@ hipError_t launch_newton_quad(const fpts_mesh *m, bool mixed, int64_t n, const d
                               const NewtonIO &io, int which, hipStream_t s);
 hipError_t launch_newton_surf(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
                               const NewtonIO &io, int which, hipStream_t s);
+
+// particle transport step (lpt.hip): drag, Adams-Bashforth 2 / Euler, box
+// boundary; all arrays [D][n]
+struct LptArgs {
+    double *x, *v, *hist_v, *hist_a;
+    const double *u;
+    const int32_t *code;
+    int64_t n;
+    double tau, dt;
+    double lo[3], hi[3];
+    int periodic[3];
+    int first;
+};
+hipError_t launch_lpt_advance(const fpts_mesh *m, const LptArgs &a, hipStream_t s);
 
 }  // namespace fpts

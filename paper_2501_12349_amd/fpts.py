@@ -20,6 +20,9 @@ EXPORTS = ("fpts_params_default", "fpts_setup", "fpts_destroy", "fpts_update_nod
            "fpts_eval", "fpts_find_stats_get", "fpts_profile", "fpts_profile_read",
            "fpts_get_boxes", "fpts_get_hash", "fpts_status_string")
 
+# Entry points declared in include/fpts_lpt.h.
+LPT_EXPORTS = ("fpts_lpt_workspace_size", "fpts_lpt_step")
+
 # Entry points declared in include/fpts_serve.h.
 SERVE_EXPORTS = ("fpts_server_create", "fpts_server_destroy", "fpts_server_add_mesh",
                  "fpts_server_submit", "fpts_server_poll", "fpts_server_wait",
@@ -51,8 +54,15 @@ class KernelTimes(ctypes.Structure):
     _fields_ = [("locate_ms", ctypes.c_double), ("nearest_ms", ctypes.c_double),
                 ("newton_ms", ctypes.c_double),
                 ("select_ms", ctypes.c_double), ("eval_bin_ms", ctypes.c_double),
-                ("eval_ms", ctypes.c_double), ("find_calls", ctypes.c_int64),
-                ("eval_calls", ctypes.c_int64)]
+                ("eval_ms", ctypes.c_double), ("advance_ms", ctypes.c_double),
+                ("find_calls", ctypes.c_int64), ("eval_calls", ctypes.c_int64),
+                ("lpt_calls", ctypes.c_int64)]
+
+
+class LptParams(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("dt", ctypes.c_double),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("periodic", ctypes.c_int * 3)]
 
 
 class ServerStats(ctypes.Structure):
@@ -92,6 +102,10 @@ def load_library(path=LIB_PATH):
     L.fpts_get_boxes.argtypes = [vp, vp, vp, vp]
     L.fpts_get_hash.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i32),
                                 ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    L.fpts_lpt_workspace_size.argtypes = [vp, i64]
+    L.fpts_lpt_workspace_size.restype = ctypes.c_size_t
+    L.fpts_lpt_step.argtypes = [vp, ctypes.POINTER(LptParams), i64, i32, vp, vp, vp, vp, vp,
+                                vp, vp, vp, i32, vp, ctypes.c_size_t, vp]
     L.fpts_status_string.argtypes = [i32]
     L.fpts_status_string.restype = ctypes.c_char_p
     L.fpts_server_create.argtypes = [ctypes.c_size_t, i32, i64, ctypes.POINTER(vp)]
@@ -259,6 +273,29 @@ class Mesh:
                            _dptr(wsb), wsb.numel(), _stream_ptr(stream)))
         return out
 
+    # -- particle transport (include/fpts_lpt.h)
+    def lpt_workspace_bytes(self, n):
+        return load_library().fpts_lpt_workspace_size(self._h, n)
+
+    def lpt_step(self, particles, field, first=False, precision="fp64", ws=None, stream=None):
+        """One time step of a Particles set through this mesh's fluid
+        velocity ``field`` [dim][n_elem][NP] (float64, device)."""
+        import torch
+        P = particles
+        if field.dtype != torch.float64 or not field.is_cuda or \
+                tuple(field.shape) != (self.dim, self.n_elem, self.NP):
+            raise FptsError("field must be float64 [dim][n_elem][NP] on the device")
+        need = self.lpt_workspace_bytes(P.n)
+        if need == 0:
+            raise FptsError("too many particles for one step")
+        wsb = ws if ws is not None else self.workspace(need)
+        f = P.find
+        _check(load_library().fpts_lpt_step(
+            self._h, ctypes.byref(P.params), P.n, 1 if first else 0, _dptr(P.x), _dptr(P.v),
+            _dptr(P.hist), _dptr(field.contiguous()), _dptr(f["code"]), _dptr(f["elem"]),
+            _dptr(f["r"]), _dptr(f["dist"]), _PREC[precision], _dptr(wsb), wsb.numel(),
+            _stream_ptr(stream)))
+
     # -- kernel timing (HIP events on the call's stream)
     def profile(self, enable=True):
         _check(load_library().fpts_profile(self._h, 1 if enable else 0))
@@ -287,6 +324,34 @@ class Mesh:
                                             de.ctypes.data, ctypes.byref(nl),
                                             ctypes.byref(nnz), ctypes.byref(mc)))
         return dict(NL=nl.value, lo=lo, hi=hi, delta=de, nnz=nnz.value, max_cell=mc.value)
+
+
+class Particles:
+    """Device state of n particles for Mesh.lpt_step: positions x and
+    velocities v [dim][n], the Adams-Bashforth history [2][dim][n] and the
+    Find result of x.  ``start(mesh)`` runs the initial Find."""
+
+    def __init__(self, x, v, tau, dt, lo, hi, periodic):
+        import torch
+        if x.dtype != torch.float64 or not x.is_cuda or x.dim() != 2 or \
+                tuple(v.shape) != tuple(x.shape) or v.dtype != torch.float64 or not v.is_cuda:
+            raise FptsError("x and v must be float64 device tensors [dim][n]")
+        D, n = x.shape
+        self.x = x.contiguous().clone()
+        self.v = v.contiguous().clone()
+        self.hist = torch.zeros((2, D, n), dtype=torch.float64, device=x.device)
+        self.n = n
+        self.params = LptParams()
+        self.params.tau, self.params.dt = float(tau), float(dt)
+        for d in range(3):
+            self.params.lo[d] = float(lo[d]) if d < D else 0.0
+            self.params.hi[d] = float(hi[d]) if d < D else 1.0
+            self.params.periodic[d] = int(periodic[d]) if d < D else 0
+        self.find = None
+
+    def start(self, mesh, precision="fp64", stream=None):
+        self.find = mesh.find(self.x, precision=precision, stream=stream)
+        return self
 
 
 class Server:

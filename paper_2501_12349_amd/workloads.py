@@ -340,3 +340,119 @@ def sphere(n_pts=1 << 22, seed=1005, ne=32, N=7, amp=0.05, far_frac=0.01,
     return dict(name="sphere_6x%dx%d_p%d" % (ne, ne, N - 1), dim=3, ref_dim=2, N=N,
                 nodes=nodes, pts=pts, fields=fields,
                 terms=[terms, [((1, 0, 0), 1.0)]], h=(np.pi / 2) / ne)
+
+
+# --------------------------------------------------------------------------
+# Channel flow for particle tracking.
+# --------------------------------------------------------------------------
+
+CHANNEL_L = (2.0 * math.pi, 2.0, math.pi)     # Lx, height (y in [-1, 1]), Lz
+
+
+def channel_mesh(n_el, N, beta=1.5, L=CHANNEL_L):
+    """Channel [0,Lx] x [-1,1] (x [0,Lz]) with n_el = (nx, ny[, nz]) elements,
+    N GLL nodes per direction, uniform in x and z and graded towards the
+    walls in y by y = tanh(beta eta) / tanh(beta) applied node by node (so
+    the element maps are curved in y).  Element id = a + nx*(b + ny*c);
+    nodes shared by two elements are bit-identical."""
+    D = len(n_el)
+    t = 0.5 * (gll_points(N) + 1.0)
+    s = [(np.arange(n)[:, None] + t[None, :]) / n for n in n_el]     # [n][N] in [0, 1]
+    cx = L[0] * s[0]
+    eta = 2.0 * s[1] - 1.0
+    cy = np.sign(eta) * np.tanh(beta * np.abs(eta)) / np.tanh(beta)
+    if D == 2:
+        nx, ny = n_el
+        X = np.broadcast_to(cx[None, :, None, :], (ny, nx, N, N))    # [b][a][j][i]
+        Y = np.broadcast_to(cy[:, None, :, None], (ny, nx, N, N))
+        nodes = np.stack([X, Y], axis=2)
+        return np.ascontiguousarray(nodes.reshape(nx * ny, 2, N * N))
+    nx, ny, nz = n_el
+    cz = L[2] * s[2]
+    shp = (nz, ny, nx, N, N, N)                                       # [c][b][a][k][j][i]
+    X = np.broadcast_to(cx[None, None, :, None, None, :], shp)
+    Y = np.broadcast_to(cy[None, :, None, None, :, None], shp)
+    Z = np.broadcast_to(cz[:, None, None, :, None, None], shp)
+    nodes = np.stack([X, Y, Z], axis=3)
+    return np.ascontiguousarray(nodes.reshape(nx * ny * nz, 3, N ** 3))
+
+
+def channel_modes(rng, n_modes=4, L=CHANNEL_L):
+    """Random perturbation modes (kx, kz, A, B, phase_x, phase_z, phase_w),
+    periodic in x and z."""
+    modes = []
+    for _ in range(n_modes):
+        kx = 2.0 * math.pi * rng.integers(1, 4) / L[0]
+        kz = 2.0 * math.pi * rng.integers(0, 3) / L[2]
+        modes.append((kx, kz, rng.uniform(0.02, 0.08), rng.uniform(0.02, 0.08),
+                      rng.uniform(0, 2 * math.pi), rng.uniform(0, 2 * math.pi),
+                      rng.uniform(0, 2 * math.pi)))
+    return modes
+
+
+def channel_velocity(X, modes):
+    """Analytic fluid velocity at X [D][...]: the laminar profile
+    1.5 (1 - y^2) (bulk velocity 1 along x) plus, per mode, the curl of the
+    stream function A (1-y^2)^2 sin(kx x + px) cos(kz z + pz) in the x-y
+    plane and (3D) a spanwise B (1-y^2) sin(kx x + pw).  Divergence-free,
+    zero at the walls y = +-1, periodic in x and z."""
+    X = np.asarray(X, dtype=np.float64)
+    D = X.shape[0]
+    y = X[1]
+    w = 1.0 - y * y
+    out = np.zeros_like(X)
+    out[0] = 1.5 * w
+    for kx, kz, A, B, px, pz, pw in modes:
+        cz = np.cos(kz * X[2] + pz) if D == 3 else 1.0
+        out[0] += A * 2.0 * w * (-2.0 * y) * np.sin(kx * X[0] + px) * cz
+        out[1] -= A * w * w * kx * np.cos(kx * X[0] + px) * cz
+        if D == 3:
+            out[2] += B * w * np.sin(kx * X[0] + pw)
+    return out
+
+
+def particle_lattice(n_y, D=3, L=CHANNEL_L):
+    """n_x : n_y (: n_z) = 2 : 1 (: 1) particles at the centres of a uniform
+    lattice of the channel; particle id = i + n_x*(j + n_y*k)."""
+    n_x = 2 * n_y
+    gx = (np.arange(n_x) + 0.5) / n_x * L[0]
+    gy = -1.0 + (np.arange(n_y) + 0.5) / n_y * 2.0
+    if D == 2:
+        Y, X = np.meshgrid(gy, gx, indexing="ij")
+        return np.ascontiguousarray(np.stack([X.ravel(), Y.ravel()]))
+    gz = (np.arange(n_y) + 0.5) / n_y * L[2]
+    Z, Y, X = np.meshgrid(gz, gy, gx, indexing="ij")
+    return np.ascontiguousarray(np.stack([X.ravel(), Y.ravel(), Z.ravel()]))
+
+
+def lattice_n_y(ratio, n_comp):
+    """n_y = n_z = ceil((ratio n_comp / 2)^(1/3)) for ratio = particles per
+    computational point (Section 6.7)."""
+    n = int(math.ceil((0.5 * ratio * n_comp) ** (1.0 / 3.0) - 1e-9))
+    return max(n, 1)
+
+
+def channel(n_el=(36, 24, 36), N=8, ratio=1.02, seed=1007, n_y=None, tau=5.0, dt=1e-3):
+    """Particle-tracking workload: the channel mesh (31104 hexes, p=7 by
+    default: 15.9M computational points), the fluid velocity at its nodes
+    ([D][nel][NP], three fields), the particle lattice for ``ratio``
+    particles per computational point, their initial velocity (the fluid's,
+    analytic), Stokes time tau = 5 and dt = 1e-3 as in the paper."""
+    rng = np.random.default_rng(seed)
+    D = len(n_el)
+    nodes = channel_mesh(n_el, N)
+    modes = channel_modes(rng)
+    fields = np.ascontiguousarray(channel_velocity(np.moveaxis(nodes, 1, 0), modes))
+    n_comp = nodes.shape[0] * N ** D
+    if n_y is None:
+        n_y = lattice_n_y(ratio, n_comp)
+    pts = particle_lattice(n_y, D)
+    v0 = np.ascontiguousarray(channel_velocity(pts, modes))
+    L = CHANNEL_L
+    lo = (0.0, -1.0, 0.0)[:D]
+    hi = (L[0], 1.0, L[2])[:D]
+    periodic = (1, 0, 1)[:D]
+    name = "channel_%s_p%d" % ("x".join(str(n) for n in n_el), N - 1)
+    return dict(name=name, dim=D, ref_dim=D, N=N, nodes=nodes, fields=fields, pts=pts, v0=v0,
+                modes=modes, lo=lo, hi=hi, periodic=periodic, tau=tau, dt=dt, n_y=n_y,
+                n_comp=n_comp, h=min(L[0] / n_el[0], 2.0 / n_el[1]))

@@ -27,11 +27,12 @@ def test_header_declares_the_binding_exports():
     fpts, _ = _lib()
     assert _declared() == sorted(fpts.EXPORTS)
     assert _declared("fpts_serve.h") == sorted(fpts.SERVE_EXPORTS)
+    assert _declared("fpts_lpt.h") == sorted(fpts.LPT_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol():
     _, L = _lib()
-    for name in _declared() + _declared("fpts_serve.h"):
+    for name in _declared() + _declared("fpts_serve.h") + _declared("fpts_lpt.h"):
         assert hasattr(L, name), name
 
 
@@ -76,3 +77,13 @@ def test_server_rejects_bad_arguments_without_device(budget, streams, maxb):
     assert not h.value
     assert L.fpts_server_destroy(None) == 0
     assert L.fpts_server_submit(None, 0, 10, None, None, None, None, None, None, 0, None) == -1
+
+
+def test_lpt_rejects_bad_arguments_without_device():
+    fpts, L = _lib()
+    p = fpts.LptParams()
+    p.tau, p.dt = 5.0, 1e-3
+    assert L.fpts_lpt_workspace_size(None, 10) == 0
+    args = [1, None, None, None, None, None, None, None, None, 0, None, 0, None]
+    assert L.fpts_lpt_step(None, ctypes.byref(p), 10, *args) == -1
+    assert L.fpts_lpt_step(None, None, 10, *args) == -1
