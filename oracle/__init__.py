@@ -66,6 +66,9 @@ def lib():
                                D, I, I, ctypes.c_int]
         L.orc_eval.argtypes = [P, ctypes.c_longlong, I, I, D, ctypes.c_int, D, D,
                                ctypes.c_int]
+        L.orc_eval_order.restype = ctypes.c_int
+        L.orc_eval_order.argtypes = [P, ctypes.c_longlong, I, I, D, ctypes.c_int, ctypes.c_int,
+                                     D, D, ctypes.c_int]
         L.orc_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -208,17 +211,21 @@ class Mesh:
         return dict(code=code, elem=elem, r=r, dist=dist, margin=margin,
                     iters=iters, ncand=ncand)
 
-    def eval(self, res, field, nthreads=0):
-        """field: [nf][nel][NP] -> [nf][n] (NaN where NOT_FOUND)."""
+    def eval(self, res, field, nthreads=0, field_nodes_1d=None):
+        """field: [nf][nel][Nf^R] -> [nf][n] (NaN where NOT_FOUND).  Nf
+        (field_nodes_1d) defaults to the geometry's N."""
         field = np.ascontiguousarray(field, dtype=np.float64)
         if field.ndim == 2:
             field = field[None]
         nf = field.shape[0]
+        Nf = self.N if field_nodes_1d is None else int(field_nodes_1d)
+        assert field.shape[1:] == (self.nel, Nf ** self.R), field.shape
         code = np.ascontiguousarray(res["code"], dtype=np.int32)
         elem = np.ascontiguousarray(res["elem"], dtype=np.int32)
         r = np.ascontiguousarray(res["r"], dtype=np.float64)
         n = code.shape[0]
         out = np.zeros((nf, n))
-        lib().orc_eval(self._h, n, _i(code), _i(elem), _d(r), nf, _d(field), _d(out),
-                       nthreads)
+        if lib().orc_eval_order(self._h, n, _i(code), _i(elem), _d(r), nf, Nf, _d(field),
+                                _d(out), nthreads) != 0:
+            raise ValueError("field order out of range")
         return out

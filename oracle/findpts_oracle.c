@@ -1058,13 +1058,25 @@ void orc_find(const orc_mesh *m, long long n, const double *pts, int mode, int32
     }
 }
 
-/* Section 3.3: u_f(r*) = sum over nodes of u_f,e(node) * prod of Lagrange
- * bases at r* (eq. eq_u_tensor with the same N as the geometry), for each
- * of nf fields laid out [nf][nel][NP]; NaN for NOT_FOUND points. */
-void orc_eval(const orc_mesh *m, long long n, const int32_t *code, const int32_t *elem,
-              const double *r, int nf, const double *field, double *out, int nthreads)
+/* Section 3.3: u_f(r*) = sum over the field's nodes of u_f,e(node) times
+ * the product of Lagrange bases at r* (eq. eq_u_tensor).  The field has its
+ * own order: Nf GLL nodes per direction (Nf = N-tilde, which need not equal
+ * the geometry's N), laid out [nf][nel][Nf^R] with the first reference index
+ * fastest.  NaN for NOT_FOUND points.  Returns -1 for Nf out of range. */
+int orc_eval_order(const orc_mesh *m, long long n, const int32_t *code, const int32_t *elem,
+                   const double *r, int nf, int Nf, const double *field, double *out,
+                   int nthreads)
 {
-    const int R = m->R, N = m->N, NP = m->NP;
+    const int R = m->R;
+    if (Nf < 2 || Nf > ORC_MAXN) return -1;
+    int NPf = Nf;
+    for (int a = 1; a < R; ++a) NPf *= Nf;
+    double zf[ORC_MAXN], wf[ORC_MAXN];
+    if (Nf == m->N) {
+        for (int i = 0; i < Nf; ++i) zf[i] = m->z[i];
+    } else if (orc_gll(Nf, zf, wf) != 0) {
+        return -1;
+    }
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
 #endif
@@ -1076,18 +1088,27 @@ void orc_eval(const orc_mesh *m, long long n, const int32_t *code, const int32_t
             continue;
         }
         double ph[3][ORC_MAXN];
-        for (int a = 0; a < R; ++a) orc_lagrange(N, m->z, r[(size_t)a * n + p], ph[a], NULL, NULL);
+        for (int a = 0; a < R; ++a) orc_lagrange(Nf, zf, r[(size_t)a * n + p], ph[a], NULL, NULL);
         for (int f = 0; f < nf; ++f) {
-            const double *u = field + ((size_t)f * m->nel + elem[p]) * NP;
+            const double *u = field + ((size_t)f * m->nel + elem[p]) * NPf;
             double s = 0.0;
-            for (int idx = 0; idx < NP; ++idx) {
-                double b = ph[0][idx % N] * ph[1][(idx / N) % N];
-                if (R == 3) b *= ph[2][idx / (N * N)];
+            for (int idx = 0; idx < NPf; ++idx) {
+                double b = ph[0][idx % Nf];
+                if (R >= 2) b *= ph[1][(idx / Nf) % Nf];
+                if (R == 3) b *= ph[2][idx / (Nf * Nf)];
                 s += u[idx] * b;
             }
             out[(size_t)f * n + p] = s;
         }
     }
+    return 0;
+}
+
+/* Interpolation of fields with the geometry's order (Nf = N). */
+void orc_eval(const orc_mesh *m, long long n, const int32_t *code, const int32_t *elem,
+              const double *r, int nf, const double *field, double *out, int nthreads)
+{
+    (void)orc_eval_order(m, n, code, elem, r, nf, m->N, field, out, nthreads);
 }
 
 /* Threads an OpenMP region of this library uses by default. */
