@@ -162,6 +162,19 @@ int fpts_eval(fpts_mesh *m, int64_t n, const int32_t *d_code,
               const double *d_field, double *d_out, void *d_ws,
               size_t ws_bytes, void *stream);
 
+/* Interpolate a field whose order differs from the geometry's (Section 2,
+ * eq. eq_u_tensor, where the field has its own N-tilde nodes per direction):
+ * as fpts_eval, with d_field [n_fields][n_elem][field_nodes_1d^ref_dim] of
+ * nodal values at the field_nodes_1d GLL nodes per reference direction
+ * (first index fastest), 2 <= field_nodes_1d <= 10.  The reference
+ * coordinates r* from fpts_find are the same for every field order.
+ * fpts_eval is this call with field_nodes_1d = nodes_1d.  Workspace:
+ * fpts_eval_workspace_size.  FPTS_EINVAL as fpts_eval, and for
+ * field_nodes_1d out of range. */
+int fpts_eval_order(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_t *d_elem,
+                    const double *d_r, int n_fields, int field_nodes_1d, const double *d_field,
+                    double *d_out, void *d_ws, size_t ws_bytes, void *stream);
+
 /* Counters of the last fpts_find that used workspace d_ws (read back with a
  * device-to-host copy on `stream`, which is synchronised) for one Newton
  * pass: pass 1 = primary candidates, 2 = the other candidates of points the

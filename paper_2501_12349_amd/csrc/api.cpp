@@ -397,7 +397,17 @@ int fpts_eval(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_t *d_e
               const double *d_r, int n_fields, const double *d_field, double *d_out, void *d_ws,
               size_t ws_bytes, void *stream)
 {
+    if (!m) return FPTS_EINVAL;
+    return fpts_eval_order(m, n, d_code, d_elem, d_r, n_fields, m->N, d_field, d_out, d_ws,
+                           ws_bytes, stream);
+}
+
+int fpts_eval_order(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_t *d_elem,
+                    const double *d_r, int n_fields, int field_nodes_1d, const double *d_field,
+                    double *d_out, void *d_ws, size_t ws_bytes, void *stream)
+{
     if (!m || n < 0 || n > INT32_MAX - 1 || n_fields < 1) return FPTS_EINVAL;
+    if (field_nodes_1d < 2 || field_nodes_1d > kMaxN) return FPTS_EINVAL;
     if (n == 0) return FPTS_OK;
     if (!d_code || !d_elem || !d_r || !d_field || !d_out || !d_ws) return FPTS_EINVAL;
     if (((uintptr_t)d_ws & 255) != 0) return FPTS_EINVAL;
@@ -431,8 +441,8 @@ int fpts_eval(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_t *d_e
     }
     {
         Span sp(m, 5, s);
-        chk(launch_eval(m, n, d_r, n_fields, d_field, d_out, sorted, elem_off, chunk_off,
-                        task_elem, w.tb_elem, s));
+        chk(launch_eval(m, n, d_r, n_fields, field_nodes_1d, d_field, d_out, sorted, elem_off,
+                        chunk_off, task_elem, w.tb_elem, s));
     }
     if (m->profiling) m->prof_eval++;
     return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;

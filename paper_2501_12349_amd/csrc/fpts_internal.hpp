@@ -205,7 +205,8 @@ hipError_t launch_newton(const fpts_mesh *m, int precision, int64_t n, const dou
 hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
                            const int32_t *elem, int n_fields, double *out, int *elem_cnt,
                            const int *elem_off, int *elem_fill, int *sorted, hipStream_t s);
-hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fields,
+// field_n: GLL nodes per direction of the field (its own order, 2..kMaxN)
+hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fields, int field_n,
                        const double *field, double *out, const int *sorted,
                        const int *elem_off, const int *chunk_off, const int *task_elem,
                        int64_t task_bound, hipStream_t s);

@@ -8,6 +8,7 @@
 // contracts them sum-factorised: N^3 + N^2 + N FMAs per field and point.
 // Also: the FP32 element-local node copy used by mixed-precision Newton.
 #include "fpts_internal.hpp"
+#include "gll_table.hpp"
 
 namespace fpts {
 namespace {
@@ -178,12 +179,12 @@ hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_
     return hipGetLastError();
 }
 
-hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fields,
+hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fields, int field_n,
                        const double *field, double *out, const int *sorted, const int *elem_off,
                        const int *chunk_off, const int *task_elem, int64_t task_bound,
                        hipStream_t s)
 {
-    EvalFn fn = m->R == 3 ? pick_eval<3>(m->N) : pick_eval<2>(m->N);
+    EvalFn fn = m->R == 3 ? pick_eval<3>(field_n) : pick_eval<2>(field_n);
     if (!fn) return hipErrorInvalidValue;
     EvalArgs a;
     a.r = r;
@@ -196,7 +197,8 @@ hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fie
     a.elem_off = elem_off;
     a.chunk_off = chunk_off;
     a.task_elem = task_elem;
-    a.basis = m->basis;
+    if (field_n == m->N) a.basis = m->basis;
+    else gll::fill(field_n, a.basis.z, a.basis.w);
     hipLaunchKernelGGL(fn, dim3(task_grid(task_bound, m->cus)), dim3(64), 0, s, a);
     return hipGetLastError();
 }

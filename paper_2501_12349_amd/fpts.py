@@ -17,7 +17,7 @@ _PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
 # Entry points declared in include/fpts.h.
 EXPORTS = ("fpts_params_default", "fpts_setup", "fpts_destroy", "fpts_update_nodes",
            "fpts_find_workspace_size", "fpts_find", "fpts_eval_workspace_size",
-           "fpts_eval", "fpts_find_stats_get", "fpts_profile", "fpts_profile_read",
+           "fpts_eval", "fpts_eval_order", "fpts_find_stats_get", "fpts_profile", "fpts_profile_read",
            "fpts_get_boxes", "fpts_get_hash", "fpts_status_string")
 
 # Entry points declared in include/fpts_lpt.h.
@@ -96,6 +96,8 @@ def load_library(path=LIB_PATH):
     L.fpts_eval_workspace_size.argtypes = [vp, i64]
     L.fpts_eval_workspace_size.restype = ctypes.c_size_t
     L.fpts_eval.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
+    L.fpts_eval_order.argtypes = [vp, i64, vp, vp, vp, i32, i32, vp, vp, vp, ctypes.c_size_t,
+                                  vp]
     L.fpts_find_stats_get.argtypes = [vp, i64, vp, i32, ctypes.POINTER(FindStats), vp]
     L.fpts_profile.argtypes = [vp, i32]
     L.fpts_profile_read.argtypes = [vp, ctypes.POINTER(KernelTimes)]
@@ -251,16 +253,18 @@ class Mesh:
         return {k: getattr(st, k) for k, _ in FindStats._fields_}
 
     # -- Interpolate
-    def eval(self, res, field, out=None, ws=None, stream=None):
-        """field: float64 device tensor [n_fields][n_elem][NP] (or
-        [n_elem][NP]) -> [n_fields][n]."""
+    def eval(self, res, field, out=None, ws=None, stream=None, field_nodes_1d=None):
+        """field: float64 device tensor [n_fields][n_elem][Nf^ref_dim] (or
+        [n_elem][Nf^ref_dim]) -> [n_fields][n].  Nf = field_nodes_1d, the
+        field's own GLL nodes per direction, defaults to the geometry's."""
         import torch
         L = load_library()
+        Nf = self.N if field_nodes_1d is None else int(field_nodes_1d)
         if field.dim() == 2:
             field = field.unsqueeze(0)
         if field.dtype != torch.float64 or not field.is_cuda or \
-                tuple(field.shape[1:]) != (self.n_elem, self.NP):
-            raise FptsError("field must be float64 [n_fields][n_elem][NP] on the device")
+                tuple(field.shape[1:]) != (self.n_elem, Nf ** self.ref_dim):
+            raise FptsError("field must be float64 [n_fields][n_elem][Nf^ref_dim] on the device")
         field = field.contiguous()
         n = res["code"].shape[0]
         nf = field.shape[0]
@@ -268,9 +272,9 @@ class Mesh:
             out = torch.empty((nf, n), dtype=torch.float64, device=field.device)
         need = self.eval_workspace_bytes(n)
         wsb = ws if ws is not None else self.workspace(need)
-        _check(L.fpts_eval(self._h, n, _dptr(res["code"]), _dptr(res["elem"]),
-                           _dptr(res["r"].contiguous()), nf, _dptr(field), _dptr(out),
-                           _dptr(wsb), wsb.numel(), _stream_ptr(stream)))
+        _check(L.fpts_eval_order(self._h, n, _dptr(res["code"]), _dptr(res["elem"]),
+                                 _dptr(res["r"].contiguous()), nf, Nf, _dptr(field), _dptr(out),
+                                 _dptr(wsb), wsb.numel(), _stream_ptr(stream)))
         return out
 
     # -- particle transport (include/fpts_lpt.h)
