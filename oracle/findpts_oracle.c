@@ -445,8 +445,10 @@ static void bound_coord(const orc_mesh *m, const double *f, double *lo, double *
             if (a < mn) mn = a;
             if (b > mx) mx = b;
         }
-    } else { /* surface quad in 3D */
+    } else if (m->R == 2) { /* surface quad in 3D */
         orc_bound_2d(N, M, f, &mn, &mx);
+    } else { /* line element: the whole curve's coordinate function */
+        orc_bound_1d(N, M, f, &mn, &mx);
     }
     *lo = mn;
     *hi = mx;
@@ -455,7 +457,10 @@ static void bound_coord(const orc_mesh *m, const double *f, double *lo, double *
 /* Thin-extent rule for manifold elements (Section 4.1): a (near) zero extent
  * is raised to tol times the smallest other extent, about its centre.
  * Reading: applied to every direction of surface elements (a no-op unless the
- * extent is below that value); not applied to volume elements.  Then the
+ * extent is below that value); not applied to volume elements.  For line
+ * elements the reference is the largest other extent: in 2D that is the one
+ * other extent, as printed; in 3D a straight line has two zero extents and
+ * the smallest other one would be zero.  Then the
  * box is expanded by tol of its extent in total, half on each side (Section
  * 3.1.1, "expanded by a nominal percentage"). */
 static void finish_box(const orc_mesh *m, double *lo, double *hi, const double *scale)
@@ -467,9 +472,9 @@ static void finish_box(const orc_mesh *m, double *lo, double *hi, const double *
         double Lp[3];
         for (int d = 0; d < D; ++d) Lp[d] = L[d] * (scale ? scale[d] : 1.0);
         for (int d = 0; d < D; ++d) {
-            double mo = INFINITY;
+            double mo = m->R == 1 ? 0.0 : INFINITY;
             for (int q = 0; q < D; ++q)
-                if (q != d && Lp[q] < mo) mo = Lp[q];
+                if (q != d && (m->R == 1 ? Lp[q] > mo : Lp[q] < mo)) mo = Lp[q];
             double need = m->tol * mo / (scale ? scale[d] : 1.0);
             if (L[d] < need) {
                 double c = 0.5 * (lo[d] + hi[d]);
@@ -537,6 +542,35 @@ static void element_boxes(orc_mesh *m, long long e)
     double scale[3] = {1, 1, 1};
     if (R == D) {
         for (int i = 0; i < D * D; ++i) Jc[i] = G[i];
+    } else if (R == 1) {
+        /* line (Section 4.2): Rodrigues' rotation Q about k = u x e1 by the
+         * angle between the unit tangent u = t/|t| and e1 takes u to e1,
+         * Q = I + sin(th) K + (1 - cos(th)) K^2 with K v = k x v.  x~ =
+         * Q (x - x_c) is in physical length, so J_c = Q^T.  u = -e1: the
+         * half turn about e3.  A zero tangent leaves the OBB off. */
+        double t[3] = {G[0], G[1], D == 3 ? G[2] : 0.0};
+        double tn = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+        double Q[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+        if (tn > 0) {
+            double u[3] = {t[0] / tn, t[1] / tn, t[2] / tn};
+            double k[3] = {0.0, u[2], -u[1]};          /* u x e1 */
+            double sn = sqrt(k[1] * k[1] + k[2] * k[2]), cs = u[0];
+            if (sn > 0) {
+                for (int i = 0; i < 3; ++i) k[i] /= sn;
+                double K[9] = {0, -k[2], k[1], k[2], 0, -k[0], -k[1], k[0], 0};
+                for (int i = 0; i < 3; ++i)
+                    for (int j = 0; j < 3; ++j) {
+                        double k2 = 0.0;
+                        for (int q = 0; q < 3; ++q) k2 += K[i * 3 + q] * K[q * 3 + j];
+                        Q[i * 3 + j] = (i == j ? 1.0 : 0.0) + sn * K[i * 3 + j] + (1.0 - cs) * k2;
+                    }
+            } else if (cs < 0) {
+                Q[0] = -1.0;
+                Q[4] = -1.0;
+            }
+            for (int c = 0; c < D; ++c)
+                for (int q = 0; q < D; ++q) Jc[c * D + q] = Q[q * 3 + c];
+        }
     } else { /* surface: columns t1, t2, n/|n| ; G[c*2 + a] */
         double t1[3] = {G[0], G[2], G[4]}, t2[3] = {G[1], G[3], G[5]};
         double n[3] = {t1[1] * t2[2] - t1[2] * t2[1], t1[2] * t2[0] - t1[0] * t2[2],
@@ -665,12 +699,12 @@ void orc_free(orc_mesh *m)
 orc_mesh *orc_setup(int D, int R, int N, long long nel, const double *x, double tol,
                     int hash_n, double eps_d, int max_iter, double newton_tol)
 {
-    if (!(D == 2 || D == 3) || !(R == D || (R == 2 && D == 3))) return NULL;
+    if (!(D == 2 || D == 3) || !(R == D || R == 1 || (R == 2 && D == 3))) return NULL;
     if (N < 2 || N > ORC_MAXN || nel < 1 || !x) return NULL;
     orc_mesh *m = calloc(1, sizeof(orc_mesh));
     if (!m) return NULL;
     m->D = D; m->R = R; m->N = N; m->nel = nel; m->x = x;
-    m->NP = (R == 3) ? N * N * N : N * N;
+    m->NP = (R == 3) ? N * N * N : (R == 2) ? N * N : N;
     m->tol = tol; m->eps_d = eps_d; m->max_iter = max_iter; m->newton_tol = newton_tol;
     m->M = 2 * N;
     orc_gll(N, m->z, NULL);

@@ -456,3 +456,87 @@ def channel(n_el=(36, 24, 36), N=8, ratio=1.02, seed=1007, n_y=None, tau=5.0, dt
     return dict(name=name, dim=D, ref_dim=D, N=N, nodes=nodes, fields=fields, pts=pts, v0=v0,
                 modes=modes, lo=lo, hi=hi, periodic=periodic, tau=tau, dt=dt, n_y=n_y,
                 n_comp=n_comp, h=min(L[0] / n_el[0], 2.0 / n_el[1]))
+
+
+# --------------------------------------------------------------------------
+# Line meshes (D_r = 1) in 2D and 3D.
+# --------------------------------------------------------------------------
+
+def _line_pieces_2d():
+    """Curve pieces of the 2D line workload: the boundary of [0,7] x [0,3]
+    (straight) and two curved interfaces meeting it and each other at
+    element ends, 84 elements at level 0.  Each piece: (function of the
+    parameter s in [0, 1] -> (x, y), elements at level 0)."""
+    def seg(p, q):
+        return lambda s: (p[0] + s * (q[0] - p[0]), p[1] + s * (q[1] - p[1]))
+    iface1 = lambda s: (1.0 + 0.08 * np.sin(2.0 * np.pi * s), 3.0 * s)
+    iface2 = lambda s: (1.0 + 6.0 * s, 1.5 + 0.3 * np.sin(np.pi * s))
+    return [(seg((0, 0), (7, 0)), 21), (seg((7, 0), (7, 3)), 6), (seg((7, 3), (0, 3)), 21),
+            (seg((0, 3), (0, 0)), 6), (iface1, 6), (iface2, 24)]
+
+
+def _trefoil(s):
+    t = 2.0 * np.pi * s
+    return (np.sin(t) + 2.0 * np.sin(2.0 * t), np.cos(t) - 2.0 * np.cos(2.0 * t),
+            -np.sin(3.0 * t))
+
+
+def line_mesh(pieces, N, level):
+    """Nodes [nel][D][N] of curve pieces split into 2^level times their
+    level-0 element count, uniform in the curve parameter; nodes at the GLL
+    points of each element's parameter interval.  Also the parameter
+    interval of every element, for sampling points on the curves."""
+    t = 0.5 * (gll_points(N) + 1.0)
+    nodes, spans = [], []
+    for f, m0 in pieces:
+        m = m0 * 2 ** level
+        a = np.arange(m) / m
+        S = (a[:, None] + t[None, :] / m)             # [m][N]
+        S[:, -1] = (np.arange(m) + 1) / m              # shared ends bit-identical
+        X = np.stack([np.asarray(c, dtype=np.float64) for c in f(S)], axis=1)   # [m][D][N]
+        nodes.append(X)
+        spans.append((f, a, 1.0 / m))
+    return np.ascontiguousarray(np.concatenate(nodes)), spans
+
+
+def line_points_on_curves(spans, per_elem, rng, offset=0.0):
+    """per_elem points per element at uniform random curve parameters of its
+    interval, on the analytic curve (not on the element's polynomial), plus,
+    with offset > 0, a random displacement of length U(0, offset) in a random
+    direction."""
+    out = []
+    for f, a, h in spans:
+        s = (a[:, None] + h * rng.uniform(0, 1, (a.size, per_elem))).ravel()
+        out.append(np.stack([np.asarray(c, dtype=np.float64) for c in f(s)]))
+    P = np.concatenate(out, axis=1)
+    if offset > 0:
+        u = rng.standard_normal(P.shape)
+        u /= np.linalg.norm(u, axis=0)
+        P = P + u * rng.uniform(0, offset, P.shape[1])
+    return np.ascontiguousarray(P)
+
+
+def line2d(level=8, per_elem=1000, N=4, seed=1008):
+    """Cubic line mesh in 2D standing in for the paper's cubic surface mesh
+    of the 2D triple-point problem (Section 6.3): 84 elements at level 0, 84
+    x 2^level after uniform refinement (21 504 at level 8), per_elem points
+    per element on the curves, a cubic field of (x, y)."""
+    rng = np.random.default_rng(seed)
+    nodes, spans = line_mesh(_line_pieces_2d(), N, level)
+    pts = line_points_on_curves(spans, per_elem, rng)
+    terms = poly_coeffs(2, 3, rng)
+    fields = nodal_field(nodes, terms)[None]
+    return dict(name="line2d_%del_p%d" % (nodes.shape[0], N - 1), dim=2, ref_dim=1, N=N,
+                nodes=nodes, pts=pts, fields=fields, terms=[terms], h=3.0 / 6 / 2 ** level)
+
+
+def line3d(n_elem=64, per_elem=200, N=5, seed=1009, offset=1e-3):
+    """A trefoil knot in 3D with n_elem curved elements of N nodes; points
+    near the curve (random offsets up to `offset`) and a degree N-1 field."""
+    rng = np.random.default_rng(seed)
+    nodes, spans = line_mesh([(_trefoil, n_elem)], N, 0)
+    pts = line_points_on_curves(spans, per_elem, rng, offset)
+    terms = poly_coeffs(3, N - 1, rng)
+    fields = nodal_field(nodes, terms)[None]
+    return dict(name="line3d_trefoil_%del_p%d" % (n_elem, N - 1), dim=3, ref_dim=1, N=N,
+                nodes=nodes, pts=pts, fields=fields, terms=[terms], h=10.0 / n_elem)
