@@ -6,8 +6,9 @@ points.  Default workload: 48^3 curved hexes, p = 7 (N = 8 GLL nodes per
 direction), 2^24 points uniform in the cube, 3 fields.  Both Newton
 precisions are timed (FP64, and FP32 passes + FP64 polish); `value` is the
 FP64 path, the mixed result sits beside it.  Beside them: the particle
-tracking loop of the paper's channel case (fpts_lpt_step), device-side
-setup, host-to-host throughput, the serving loop and the oracle on the CPU.
+tracking loop of the paper's channel case (fpts_lpt_step), a 2D line mesh
+of the paper's surface-mesh size, device-side setup, host-to-host
+throughput, the serving loop and the oracle on the CPU.
 
 Prints one JSON line (see the driver contract) with a roofline object for
 the dominant kernel (trust-region Newton, measured with HIP events on the
@@ -245,6 +246,61 @@ def particle_tracking(ratios, steps, warmup, precision):
                 runs=out)
 
 
+def line_surface(level, steps, warmup):
+    """Find + Interpolate on the cubic 2D line mesh that stands in for the
+    paper's surface-mesh case (84 x 2^level elements, 1000 points per
+    element on the curves, one cubic field), FP64."""
+    import torch
+    from paper_2501_12349_amd import fpts
+    from paper_2501_12349_amd import workloads as W
+    t0 = time.perf_counter()
+    wl = W.line2d(level=level)
+    gm = fpts.Mesh(wl["nodes"], wl["N"], dim=2, ref_dim=1)
+    t_setup = time.perf_counter() - t0
+    n = wl["pts"].shape[1]
+    pts = torch.from_numpy(wl["pts"]).cuda()
+    field = torch.from_numpy(wl["fields"]).cuda()
+    out = dict(code=torch.empty(n, dtype=torch.int32, device="cuda"),
+               elem=torch.empty(n, dtype=torch.int32, device="cuda"),
+               r=torch.empty((1, n), dtype=torch.float64, device="cuda"),
+               dist=torch.empty(n, dtype=torch.float64, device="cuda"))
+    u = torch.empty((1, n), dtype=torch.float64, device="cuda")
+    ws = torch.empty(max(gm.find_workspace_bytes(n), gm.eval_workspace_bytes(n)),
+                     dtype=torch.uint8, device="cuda")
+    for _ in range(warmup):
+        gm.find(pts, out=out, ws=ws)
+        gm.eval(out, field, out=u, ws=ws)
+    torch.cuda.synchronize()
+    gm.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gm.find(pts, out=out, ws=ws)
+        gm.eval(out, field, out=u, ws=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    kt = gm.profile_read()
+    gm.profile(False)
+    stats = gm.find_stats()
+    c = max(kt["find_calls"], 1)
+    find_ms = (kt["locate_ms"] + kt["nearest_ms"] + kt["newton_ms"] + kt["select_ms"]) / c
+    eval_ms = (kt["eval_bin_ms"] + kt["eval_ms"]) / max(kt["eval_calls"], 1)
+    codes = torch.bincount(out["code"].long(), minlength=3).cpu().tolist()
+    log("line2d %d elements, %d points: %.3f ms/step  %.1f Mpts/s  find %.3f eval %.3f ms  "
+        "newton %.3f ms  codes %s  evals/pair %.2f" % (
+            wl["nodes"].shape[0], n, dt * 1e3, n / dt / 1e6, find_ms, eval_ms,
+            kt["newton_ms"] / c, codes, stats["evals"] / max(stats["pairs"], 1)))
+    return dict(workload="%s_%dpts_1field" % (wl["name"], n), n_elem=int(wl["nodes"].shape[0]),
+                n_points=n, precision="fp64", steps=steps, ms_per_step=round(dt * 1e3, 4),
+                mpts_s=round(n / dt / 1e6, 3), find_ms=round(find_ms, 4),
+                eval_ms=round(eval_ms, 4), newton_ms=round(kt["newton_ms"] / c, 4),
+                setup_s=round(t_setup, 3),
+                codes=dict(zip(("interior", "border", "not_found"), codes)),
+                evals_per_pair=round(stats["evals"] / max(stats["pairs"], 1), 3),
+                paper_context="same element and point counts: Find 8.6 s, Interpolate 2.4 s "
+                              "on one node with 4 V100 GPUs")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +325,9 @@ def main():
                          "(comma list; empty: skip)")
     ap.add_argument("--lpt-steps", type=int, default=10,
                     help="timed steps per particle-tracking run (0: skip)")
+    ap.add_argument("--line-level", type=int, default=8,
+                    help="refinement level of the 2D line-mesh run (84 x 2^level elements; "
+                         "-1: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU: the find/eval path has no "
@@ -421,6 +480,8 @@ def main():
     if args.lpt_ratios and args.lpt_steps > 0:
         line["particle_tracking"] = particle_tracking(
             [float(r) for r in args.lpt_ratios.split(",")], args.lpt_steps, 2, main_mode)
+    if args.line_level >= 0:
+        line["line_mesh_2d"] = line_surface(args.line_level, 5, 1)
     if args.serve_requests > 0:
         line["serving"] = serving(args.serve_requests, int(args.serve_budget_gb * (1 << 30)))
     if not args.no_cpu:

@@ -58,23 +58,26 @@ enum {
                             result; the second search over the other
                             candidates of unsettled points is FP64; boxes,
                             codes, distances and the final residual are
-                            FP64 */
+                            FP64.  Line elements run FP64 throughout (their
+                            map evaluation is a few dozen FLOPs) */
 };
 
 /* Setup parameters (Section 3.1).  Zero-initialise, then set fields;
  * fpts_params_default fills the paper's defaults. */
 typedef struct fpts_params {
     int dim;            /* D, space dimension: 2 or 3 */
-    int ref_dim;        /* D_r: dim (quad/hex mesh) or 2 with dim 3 (surface
-                           quads) */
+    int ref_dim;        /* D_r: dim (quad/hex mesh), 2 with dim 3 (surface
+                           quads) or 1 with dim 2 or 3 (line elements,
+                           Section 2 eq. eq_x_tensor_surf; OBB frame by
+                           Rodrigues' rotation, Section 4.2) */
     int nodes_1d;       /* N = p + 1 GLL nodes per direction, 2..10 */
     int hash_n;         /* N_L cells per direction of the local map; 0 picks
                            the smallest n with n^D >= n_elem (Section 3.1.3) */
     int64_t n_elem;     /* number of elements, >= 1 */
     double bbox_tol;    /* box expansion, fraction of the extent added in
                            total (Section 3.1.1 default 0.1) */
-    double surf_eps_d;  /* surface INTERIOR threshold on the squared distance
-                           (Section 4.4 default 1e-10) */
+    double surf_eps_d;  /* manifold (surface and line) INTERIOR threshold on
+                           the squared distance (Section 4.4 default 1e-10) */
     int max_iter;       /* Newton passes per candidate (Section 3.2.1: 50) */
     double newton_tol;  /* stop when ||dr||_inf < newton_tol (1e-10) */
     int mixed_max_iter; /* FPTS_MIXED: FP32 passes per candidate at most */
@@ -118,8 +121,10 @@ int fpts_destroy(fpts_mesh *m);
  * N_L stay.  The results equal those of fpts_setup on the same nodes bit
  * for bit.  Synchronises `stream` (the map size is read back); workspace
  * sizes may grow, so query them again.  FPTS_EINVAL (null arguments, or
- * nodes whose boxes are not finite), FPTS_ENOMEM, FPTS_EDEVICE; after an
- * error the mesh must be destroyed. */
+ * nodes whose boxes are not finite), FPTS_EUNSUPPORTED for line elements
+ * (no device kernels for their boxes; the mesh is left unchanged),
+ * FPTS_ENOMEM, FPTS_EDEVICE; after another error the mesh must be
+ * destroyed. */
 int fpts_update_nodes(fpts_mesh *m, const double *d_nodes, void *stream);
 
 /* Bytes of device workspace fpts_find needs for n points (an upper bound

@@ -166,6 +166,7 @@ hipError_t launch_newton(const fpts_mesh *m, int precision, int64_t n, const dou
     const bool mixed = precision == FPTS_MIXED;
     if (m->D == 3 && m->R == 3) return launch_newton_hex(m, mixed, n, pts, io, which, s);
     if (m->D == 2 && m->R == 2) return launch_newton_quad(m, mixed, n, pts, io, which, s);
+    if (m->R == 1) return launch_newton_line(m, n, pts, io, which, s);
     return launch_newton_surf(m, mixed, n, pts, io, which, s);
 }
 
@@ -208,7 +209,8 @@ int fpts_setup(const fpts_params *p, const double *h_nodes, void *stream, fpts_m
     *out = nullptr;
     const bool vol = p->ref_dim == p->dim && (p->dim == 2 || p->dim == 3);
     const bool surf = p->dim == 3 && p->ref_dim == 2;
-    if (!(vol || surf)) return FPTS_EINVAL;
+    const bool line = p->ref_dim == 1 && (p->dim == 2 || p->dim == 3);
+    if (!(vol || surf || line)) return FPTS_EINVAL;
     if (p->nodes_1d < 2 || p->nodes_1d > kMaxN) return FPTS_EINVAL;
     if (p->n_elem < 1 || p->n_elem > INT32_MAX / 2) return FPTS_EINVAL;
     if (!(p->bbox_tol >= 0.0) || !(p->newton_tol > 0.0) || p->max_iter < 1 ||
@@ -222,7 +224,7 @@ int fpts_setup(const fpts_params *p, const double *h_nodes, void *stream, fpts_m
     m->D = p->dim;
     m->R = p->ref_dim;
     m->N = p->nodes_1d;
-    m->NP = m->R == 3 ? m->N * m->N * m->N : m->N * m->N;
+    m->NP = m->R == 3 ? m->N * m->N * m->N : m->R == 2 ? m->N * m->N : m->N;
     m->nel = p->n_elem;
     if (hipGetDevice(&m->device) != hipSuccess ||
         hipDeviceGetAttribute(&m->cus, hipDeviceAttributeMultiprocessorCount, m->device) !=
@@ -514,6 +516,7 @@ int fpts_profile_read(fpts_mesh *m, fpts_kernel_times *out)
 int fpts_update_nodes(fpts_mesh *m, const double *d_nodes, void *stream)
 {
     if (!m || !d_nodes) return FPTS_EINVAL;
+    if (m->R == 1) return FPTS_EUNSUPPORTED;   // the device setup has no line kernels
     if (sticky_error()) return FPTS_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
     const size_t nn = (size_t)m->nel * m->D * m->NP;

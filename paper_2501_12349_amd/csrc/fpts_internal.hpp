@@ -223,6 +223,9 @@ hipError_t launch_newton_quad(const fpts_mesh *m, bool mixed, int64_t n, const d
                               const NewtonIO &io, int which, hipStream_t s);
 hipError_t launch_newton_surf(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
                               const NewtonIO &io, int which, hipStream_t s);
+// line elements (kernels_newton_line.hip): FP64 in every mode
+hipError_t launch_newton_line(const fpts_mesh *m, int64_t n, const double *pts,
+                              const NewtonIO &io, int which, hipStream_t s);
 
 // particle transport step (lpt.hip): drag, Adams-Bashforth 2 / Euler, box
 // boundary; all arrays [D][n]

@@ -67,7 +67,7 @@ struct EvalArgs {
 template <int R, int N>
 __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
 {
-    constexpr int NP = (R == 3) ? N * N * N : N * N;
+    constexpr int NP = (R == 3) ? N * N * N : (R == 2) ? N * N : N;
     const int lane = threadIdx.x;
     const int total = a.chunk_off[a.nel];
     for (int t = task_of_block(); t < total; t += gridDim.x) {
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
         const int p = has ? a.sorted[idx] : 0;
         double v0[N], v1[N], v2[N];
         basis_v<N>(has ? a.r[p] : 0.0, a.basis.z, a.basis.w, v0);
-        basis_v<N>(has ? a.r[(size_t)a.n + p] : 0.0, a.basis.z, a.basis.w, v1);
+        if (R >= 2) basis_v<N>(has ? a.r[(size_t)a.n + p] : 0.0, a.basis.z, a.basis.w, v1);
         if (R == 3) basis_v<N>(has ? a.r[(size_t)2 * a.n + p] : 0.0, a.basis.z, a.basis.w, v2);
         for (int f = 0; f < a.n_fields; ++f) {
             cdouble *u = (cdouble *)(a.field + ((size_t)f * a.nel + e) * NP);
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
                     }
                     acc = fma(B, v2[k], acc);
                 }
-            } else {
+            } else if constexpr (R == 2) {
 #pragma unroll
                 for (int j = 0; j < N; ++j) {
                     double A = 0.0;
@@ -105,6 +105,9 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
                     for (int i = 0; i < N; ++i) A = fma(u[i + N * j], v0[i], A);
                     acc = fma(A, v1[j], acc);
                 }
+            } else {
+#pragma unroll
+                for (int i = 0; i < N; ++i) acc = fma(u[i], v0[i], acc);
             }
             if (has) a.out[(size_t)f * a.n + p] = acc;
         }
@@ -184,7 +187,8 @@ hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fie
                        const int *chunk_off, const int *task_elem, int64_t task_bound,
                        hipStream_t s)
 {
-    EvalFn fn = m->R == 3 ? pick_eval<3>(field_n) : pick_eval<2>(field_n);
+    EvalFn fn = m->R == 3 ? pick_eval<3>(field_n)
+                : m->R == 2 ? pick_eval<2>(field_n) : pick_eval<1>(field_n);
     if (!fn) return hipErrorInvalidValue;
     EvalArgs a;
     a.r = r;

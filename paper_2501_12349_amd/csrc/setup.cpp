@@ -216,7 +216,8 @@ void bound2(const Tables &T, const Basis &B, const double *u, double &lo, double
 }
 
 // Bound of one coordinate function f[NP] of an element: edges of a quad,
-// faces of a hex, the whole patch of a surface quad.
+// faces of a hex, the whole patch of a surface quad, the whole curve of a
+// line element.
 void bound_fun(const fpts_mesh *m, const Tables &T, const double *f, double &lo, double &hi)
 {
     const int N = m->N;
@@ -250,14 +251,19 @@ void bound_fun(const fpts_mesh *m, const Tables &T, const double *f, double &lo,
             bound2(T, m->basis, buf, a, b);
             take(a, b);
         }
-    } else {
+    } else if (m->R == 2) {
         bound2(T, m->basis, f, a, b);
+        take(a, b);
+    } else {
+        bound1(T, m->basis, f, a, b);
         take(a, b);
     }
 }
 
-// Thin-extent rule (surfaces only, Section 4.1) and expansion by tol of the
+// Thin-extent rule (manifolds only, Section 4.1) and expansion by tol of the
 // extent in total (Section 3.1.1).  `len` scales extents to physical length.
+// The rule's reference is the smallest other extent for surface quads and
+// the largest for lines (a straight line in 3D has two zero extents).
 void finish(const fpts_mesh *m, double *lo, double *hi, const double *len)
 {
     const int D = m->D;
@@ -268,10 +274,10 @@ void finish(const fpts_mesh *m, double *lo, double *hi, const double *len)
         double P[3];
         for (int d = 0; d < D; ++d) P[d] = L[d] * len[d];
         for (int d = 0; d < D; ++d) {
-            double small = INFINITY;
+            double ref = m->R == 1 ? 0.0 : INFINITY;
             for (int q = 0; q < D; ++q)
-                if (q != d) small = std::min(small, P[q]);
-            double need = tol * small / len[d];
+                if (q != d) ref = m->R == 1 ? std::max(ref, P[q]) : std::min(ref, P[q]);
+            double need = tol * ref / len[d];
             if (L[d] < need) {
                 double c = 0.5 * (lo[d] + hi[d]);
                 lo[d] = c - 0.5 * need;
@@ -314,6 +320,32 @@ bool invert(int D, const double *A, double *I)
     return true;
 }
 
+// J_c = Q^T for a line element with centre tangent t (see element_setup);
+// left all zero when t = 0.
+void rodrigues_frame(int D, double tx, double ty, double tz, double *Jc)
+{
+    const double tn = std::sqrt(tx * tx + ty * ty + tz * tz);
+    if (!(tn > 0.0)) return;
+    const double u[3] = {tx / tn, ty / tn, tz / tn};
+    double Q[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    const double sn = std::sqrt(u[1] * u[1] + u[2] * u[2]), cs = u[0];
+    if (sn > 0.0) {
+        const double k[3] = {0.0, u[2] / sn, -u[1] / sn};
+        const double K[3][3] = {{0.0, -k[2], k[1]}, {k[2], 0.0, -k[0]}, {-k[1], k[0], 0.0}};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double kk = 0.0;
+                for (int q = 0; q < 3; ++q) kk += K[i][q] * K[q][j];
+                Q[i][j] = (i == j ? 1.0 : 0.0) + sn * K[i][j] + (1.0 - cs) * kk;
+            }
+    } else if (cs < 0.0) {
+        Q[0][0] = -1.0;
+        Q[1][1] = -1.0;
+    }
+    for (int c = 0; c < D; ++c)
+        for (int q = 0; q < D; ++q) Jc[c * D + q] = Q[q][c];
+}
+
 // AABB and OBB of element e (Section 3.1.1, 3.1.2, 4.1, 4.2).
 void element_setup(fpts_mesh *m, const Tables &T, const double *x, int64_t e)
 {
@@ -334,6 +366,11 @@ void element_setup(fpts_mesh *m, const Tables &T, const double *x, int64_t e)
     for (int idx = 0; idx < NP; ++idx) {
         int ii = idx % N, jj = (idx / N) % N, kk = idx / (N * N);
         double b0 = v[ii] * v[jj], br = d[ii] * v[jj], bs = v[ii] * d[jj], bt = 0.0;
+        if (R == 1) {
+            b0 = v[ii];
+            br = d[ii];
+            bs = 0.0;
+        }
         if (R == 3) {
             bt = b0 * d[kk];
             b0 *= v[kk];
@@ -353,6 +390,13 @@ void element_setup(fpts_mesh *m, const Tables &T, const double *x, int64_t e)
     if (R == D) {
         for (int a = 0; a < D; ++a)
             for (int b = 0; b < D; ++b) Jc[a * D + b] = G[a][b];
+    } else if (R == 1) {
+        // Section 4.2, line elements: the rotation Q that takes the unit
+        // tangent u at the centre to e1, by Rodrigues' formula about
+        // k = u x e1 with cos = u.e1, sin = |u x e1|; x~ = Q (x - x_c) keeps
+        // physical length, so J_c = Q^T.  u = -e1 takes the half turn about
+        // e3; a zero tangent leaves J_c singular (OBB off).
+        rodrigues_frame(D, G[0][0], G[1][0], D == 3 ? G[2][0] : 0.0, Jc);
     } else {
         double t1[3] = {G[0][0], G[1][0], G[2][0]}, t2[3] = {G[0][1], G[1][1], G[2][1]};
         double n[3] = {t1[1] * t2[2] - t1[2] * t2[1], t1[2] * t2[0] - t1[0] * t2[2],

@@ -158,7 +158,7 @@ class Mesh:
         nel, D, NP = nodes.shape
         dim = D if dim is None else dim
         if ref_dim is None:
-            ref_dim = dim if NP == nodes_1d ** dim else dim - 1
+            ref_dim = next((k for k in (dim, dim - 1, 1) if NP == nodes_1d ** k), dim)
         p = Params()
         L.fpts_params_default(ctypes.byref(p), dim, ref_dim, nodes_1d, nel)
         p.bbox_tol, p.hash_n, p.surf_eps_d = bbox_tol, hash_n, surf_eps_d

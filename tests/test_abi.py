@@ -48,7 +48,7 @@ def test_defaults_and_status_strings():
     assert L.fpts_status_string(-1) == b"invalid argument"
 
 
-@pytest.mark.parametrize("dim,ref_dim,N,nel", [(1, 1, 4, 10), (3, 1, 4, 10), (2, 3, 4, 10),
+@pytest.mark.parametrize("dim,ref_dim,N,nel", [(1, 1, 4, 10), (3, 4, 4, 10), (2, 3, 4, 10),
                                                (3, 3, 1, 10), (3, 3, 11, 10), (3, 3, 4, 0)])
 def test_setup_rejects_bad_params_without_device(dim, ref_dim, N, nel):
     fpts, L = _lib()
