@@ -71,6 +71,35 @@ __device__ __forceinline__ int task_of_block()
     return (b % kXcd) * (G / kXcd) + b / kXcd;
 }
 
+// ctr[key]++ for every active lane, returning the lane's old value, with one
+// atomic per group of lanes that share a key: the group of the lowest pending
+// lane is peeled off with a ballot and takes a block of consecutive values.
+// Points that arrive clustered (along a curve, in a lattice, element by
+// element) otherwise pile thousands of atomics onto one address, and
+// device-scope atomics on one address serialise.  Peeling stops once a group
+// has fewer than 4 lanes (scattered keys); the rest use one atomic each.
+// Every lane of the wavefront must call it (it ballots).
+__device__ __forceinline__ int wave_inc(int *ctr, int key, bool active)
+{
+    const int lane = __lane_id();
+    const unsigned long long bit = 1ull << lane;
+    unsigned long long pend = __ballot(active);
+    int out = 0;
+    for (int round = 0; round < 16 && pend; ++round) {
+        const int leader = __builtin_ctzll(pend);
+        const int k = __shfl(key, leader, 64);
+        const unsigned long long grp = __ballot(key == k) & pend;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&ctr[k], __popcll(grp));
+        base = __shfl(base, leader, 64);
+        if (grp & bit) out = base + __popcll(grp & (bit - 1));
+        pend &= ~grp;
+        if (__popcll(grp) < 4) break;
+    }
+    if (pend & bit) out = atomicAdd(&ctr[key], 1);
+    return out;
+}
+
 struct FindWs {
     size_t cell_cnt, cell_fill, cell_poff, cell_choff, cellpt, pbin, ncand, primary,
         elem_cnt, elem_fill, elem_off, chunk_off, sorted, off2, elem_cnt2, elem_fill2,

@@ -22,16 +22,18 @@ __global__ __launch_bounds__(256) void k_eval_bin(int pass, int n, int nel, cons
                                                  int *elem_cnt, const int *elem_off,
                                                  int *elem_fill, int *sorted)
 {
+    // no early exit: wave_inc needs every lane
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int e = elem[p];
-    const bool found = code[p] != FPTS_NOT_FOUND && e >= 0 && e < nel;
+    const bool in = p < n;
+    const int e = in ? elem[p] : -1;
+    const bool found = in && code[p] != FPTS_NOT_FOUND && e >= 0 && e < nel;
     if (pass == 0) {
-        if (found) atomicAdd(&elem_cnt[e], 1);
-        else
+        (void)wave_inc(elem_cnt, e, found);
+        if (in && !found)
             for (int f = 0; f < n_fields; ++f) out[(size_t)f * n + p] = __builtin_nan("");
-    } else if (found) {
-        sorted[elem_off[e] + atomicAdd(&elem_fill[e], 1)] = p;
+    } else {
+        const int k = wave_inc(elem_fill, e, found);
+        if (found) sorted[elem_off[e] + k] = p;
     }
 }
 

@@ -165,22 +165,27 @@ __global__ __launch_bounds__(256) void k_cell_bin(HashView h, int pass, int n, i
                                                  int32_t *code, int32_t *elem, double *r,
                                                  double *dist)
 {
+    // no early exit: wave_inc needs every lane
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    const bool in = p < n;
     if (pass == 0) {
-        double x[D];
+        int c = -1;
+        if (in) {
+            double x[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) x[d] = pts[(size_t)d * n + p];
-        const int c = cell_of<D>(h, x);
-        cellpt[p] = c;
-        // every point gets defined candidate data, also those no cell holds
-        ncand[p] = 0;
-        primary[p] = -1;
-        if (c < 0) write_not_found(p, n, R, code, elem, r, dist);
-        else atomicAdd(&cell_cnt[c], 1);
+            for (int d = 0; d < D; ++d) x[d] = pts[(size_t)d * n + p];
+            c = cell_of<D>(h, x);
+            cellpt[p] = c;
+            // every point gets defined candidate data, also those no cell holds
+            ncand[p] = 0;
+            primary[p] = -1;
+            if (c < 0) write_not_found(p, n, R, code, elem, r, dist);
+        }
+        (void)wave_inc(cell_cnt, c, c >= 0);
     } else {
-        const int c = cellpt[p];
-        if (c >= 0) pbin[cell_poff[c] + atomicAdd(&cell_fill[c], 1)] = p;
+        const int c = in ? cellpt[p] : -1;
+        const int k = wave_inc(cell_fill, c, c >= 0);
+        if (c >= 0) pbin[cell_poff[c] + k] = p;
     }
 }
 
@@ -236,9 +241,9 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
         if (has) {
             ncand[p] = cnt;
             primary[p] = prim;
-            if (prim >= 0) atomicAdd(&elem_cnt[prim], 1);
-            else write_not_found(p, n, R, code, elem, r, dist);
+            if (prim < 0) write_not_found(p, n, R, code, elem, r, dist);
         }
+        (void)wave_inc(elem_cnt, prim, has && prim >= 0);
     }
 }
 
@@ -247,9 +252,10 @@ __global__ __launch_bounds__(256) void k_primary_scatter(int n, int nel, const i
                                                         int *sorted)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int e = primary[p];
-    if (e >= 0 && e < nel) sorted[elem_off[e] + atomicAdd(&elem_fill[e], 1)] = p;
+    const int e = p < n ? primary[p] : -1;
+    const bool ok = e >= 0 && e < nel;
+    const int k = wave_inc(elem_fill, e, ok);
+    if (ok) sorted[elem_off[e] + k] = p;
 }
 
 // A primary result settles the point when it is INTERIOR at least `guard`
