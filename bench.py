@@ -198,13 +198,16 @@ def particle_tracking(ratios, steps, warmup, precision):
     log("particle tracking: %s (%d elements) ready in %.1f s" % (
         wl["name"], wl["nodes"].shape[0], time.perf_counter() - t0))
     out = []
-    for ratio in ratios:
+    # every ratio with the paper's full Find; the first one also hinted
+    # (previous element first, fpts_lpt.h)
+    for ratio, hint in [(r, False) for r in ratios] + [(ratios[0], True)]:
         n_y = W.lattice_n_y(ratio, wl["n_comp"])
         pts = W.particle_lattice(n_y)
         v0 = W.channel_velocity(pts, wl["modes"])
         n = pts.shape[1]
         P = fpts.Particles(torch.from_numpy(pts).cuda(), torch.from_numpy(v0).cuda(), wl["tau"],
-                           wl["dt"], wl["lo"], wl["hi"], wl["periodic"]).start(gm, precision)
+                           wl["dt"], wl["lo"], wl["hi"], wl["periodic"],
+                           hint=hint).start(gm, precision)
         del pts, v0
         ws = torch.empty(gm.lpt_workspace_bytes(n), dtype=torch.uint8, device="cuda")
         for k in range(warmup):
@@ -225,7 +228,7 @@ def particle_tracking(ratios, steps, warmup, precision):
         interp_ms = (kt["eval_bin_ms"] + kt["eval_ms"]) / c
         adv_ms = kt["advance_ms"] / c
         tot = find_ms + interp_ms + adv_ms
-        rep = dict(ratio=ratio, particles=n, ms_per_step=round(dt * 1e3, 4),
+        rep = dict(ratio=ratio, hinted_find=hint, particles=n, ms_per_step=round(dt * 1e3, 4),
                    mparticle_steps_per_s=round(n / dt / 1e6, 3),
                    find_ms=round(find_ms, 4), interpolate_ms=round(interp_ms, 4),
                    advance_ms=round(adv_ms, 4),
@@ -233,9 +236,10 @@ def particle_tracking(ratios, steps, warmup, precision):
                                   interpolate=round(interp_ms / tot, 4),
                                   advance=round(adv_ms / tot, 4)),
                    not_found=lost)
-        log("particle tracking %.2f particles/point (%d): %.3f ms/step  %.1f M particle-steps/s  "
+        log("particle tracking %.2f particles/point (%d)%s: %.3f ms/step  %.1f M particle-steps/s  "
             "find %.3f interpolate %.3f advance %.3f ms  lost %d" % (
-                ratio, n, dt * 1e3, n / dt / 1e6, find_ms, interp_ms, adv_ms, lost))
+                ratio, n, " hinted" if hint else "", dt * 1e3, n / dt / 1e6, find_ms, interp_ms,
+                adv_ms, lost))
         out.append(rep)
         del P, ws
         torch.cuda.empty_cache()

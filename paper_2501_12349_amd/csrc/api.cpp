@@ -172,6 +172,105 @@ hipError_t launch_newton(const fpts_mesh *m, int precision, int64_t n, const dou
 
 }  // namespace fpts
 
+namespace fpts {
+
+// fpts_find with an optional keep mask: points with keep[p] != 0 hold final
+// results on entry and are not searched.
+int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int32_t *d_elem,
+              double *d_r, double *d_dist, int precision, void *d_ws, size_t ws_bytes,
+              void *stream, const int *keep)
+{
+    if (!m || n < 0 || n > INT32_MAX - 1) return FPTS_EINVAL;
+    if (precision != FPTS_FP64 && precision != FPTS_MIXED) return FPTS_EINVAL;
+    if (n == 0) return FPTS_OK;
+    if (!d_pts || !d_code || !d_elem || !d_r || !d_dist || !d_ws) return FPTS_EINVAL;
+    if (((uintptr_t)d_ws & 255) != 0) return FPTS_EINVAL;
+    const FindWs w = find_ws_layout(m, n);
+    if (w.cap2 > INT32_MAX || ws_bytes < w.total) return FPTS_EINVAL;
+    if (sticky_error()) return FPTS_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    int *cell_cnt = at<int>(d_ws, w.cell_cnt), *cell_fill = at<int>(d_ws, w.cell_fill);
+    int *cell_poff = at<int>(d_ws, w.cell_poff), *cell_choff = at<int>(d_ws, w.cell_choff);
+    int *cellpt = at<int>(d_ws, w.cellpt), *pbin = at<int>(d_ws, w.pbin);
+    int *ncand = at<int>(d_ws, w.ncand), *primary = at<int>(d_ws, w.primary);
+    int *elem_cnt = at<int>(d_ws, w.elem_cnt), *elem_fill = at<int>(d_ws, w.elem_fill);
+    int *elem_off = at<int>(d_ws, w.elem_off), *chunk_off = at<int>(d_ws, w.chunk_off);
+    int *sorted = at<int>(d_ws, w.sorted), *off2 = at<int>(d_ws, w.off2);
+    int *elem_cnt2 = at<int>(d_ws, w.elem_cnt2), *elem_fill2 = at<int>(d_ws, w.elem_fill2);
+    int *elem_off2 = at<int>(d_ws, w.elem_off2), *chunk_off2 = at<int>(d_ws, w.chunk_off2);
+    int *slot_pt = at<int>(d_ws, w.slot_pt), *slot_elem = at<int>(d_ws, w.slot_elem);
+    int *sorted2 = at<int>(d_ws, w.sorted2);
+    double *res_r = at<double>(d_ws, w.res_r), *res_dist = at<double>(d_ws, w.res_dist);
+    int *res_code = at<int>(d_ws, w.res_code), *tmp = at<int>(d_ws, w.scan_tmp);
+    int *counters = at<int>(d_ws, w.counters);
+    int *task_cell = at<int>(d_ws, w.task_cell), *task_elem = at<int>(d_ws, w.task_elem);
+    int *task_elem2 = at<int>(d_ws, w.task_elem2);
+    unsigned long long *stats = at<unsigned long long>(d_ws, w.stats);
+    const int64_t nel = m->nel, ncell = w.ncell, tb = w.scan_blocks;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+    };
+    {   // phases A and B: bin points by cell, candidates and primaries
+        Span sp(m, 0, s);
+        chk(launch_fill_i32(cell_cnt, ncell, 0, s));
+        chk(launch_fill_i32(cell_fill, ncell, 0, s));
+        chk(launch_fill_i32(elem_cnt, nel, 0, s));
+        chk(launch_fill_i32(elem_fill, nel, 0, s));
+        chk(launch_fill_i32(elem_cnt2, nel, 0, s));
+        chk(launch_fill_i32(elem_fill2, nel, 0, s));
+        chk(launch_fill_i32(counters, kCounters, 0, s));
+        chk(launch_fill_i32(reinterpret_cast<int *>(stats), 4 * kStats, 0, s));
+        chk(launch_cell_bin(m, 0, n, d_pts, keep, cellpt, cell_cnt, nullptr, nullptr, nullptr,
+                            ncand, primary, d_code, d_elem, d_r, d_dist, s));
+        chk(launch_exclusive_scan(cell_cnt, cell_poff, ncell, 1, tmp, tb, s));
+        chk(launch_exclusive_scan(cell_cnt, cell_choff, ncell, kChunk, tmp, tb, s));
+        chk(launch_task_map(cell_choff, ncell, task_cell, s));
+        chk(launch_cell_bin(m, 1, n, d_pts, keep, cellpt, nullptr, cell_poff, cell_fill, pbin,
+                            nullptr, nullptr, d_code, d_elem, d_r, d_dist, s));
+        chk(launch_locate_cells(m, n, d_pts, pbin, cell_poff, cell_choff, ncell, task_cell,
+                                w.tb_cell, ncand, primary, elem_cnt, d_code, d_elem, d_r, d_dist,
+                                s));
+        chk(launch_exclusive_scan(elem_cnt, elem_off, nel, 1, tmp, tb, s));
+        chk(launch_exclusive_scan(elem_cnt, chunk_off, nel, kChunk, tmp, tb, s));
+        chk(launch_task_map(chunk_off, nel, task_elem, s));
+        chk(launch_primary_scatter(n, nel, primary, elem_off, elem_fill, sorted, s));
+    }
+    {   // phase C: Newton on the primary candidates, results straight to the outputs
+        NewtonIO io{sorted, elem_off, chunk_off, nullptr, d_code, d_elem, d_r, n, d_dist,
+                    counters + kNewtonCounters, stats, task_elem, w.tb_elem};
+        {
+            Span sp(m, 1, s);
+            chk(launch_newton(m, precision, n, d_pts, io, 1, s));
+        }
+        Span sp(m, 2, s);
+        chk(launch_newton(m, precision, n, d_pts, io, 2, s));
+    }
+    {   // phase D: other candidates of unsettled points, then the selection rule
+        Span sp(m, 3, s);
+        chk(launch_resolve(m, 0, n, d_pts, cellpt, ncand, primary, d_code, d_r, off2, elem_cnt2,
+                           nullptr, nullptr, nullptr, nullptr, nullptr, s));
+        chk(launch_exclusive_scan(off2, off2, n, 1, tmp, tb, s));
+        chk(launch_exclusive_scan(elem_cnt2, elem_off2, nel, 1, tmp, tb, s));
+        chk(launch_exclusive_scan(elem_cnt2, chunk_off2, nel, kChunk, tmp, tb, s));
+        chk(launch_task_map(chunk_off2, nel, task_elem2, s));
+        chk(launch_resolve(m, 1, n, d_pts, cellpt, ncand, primary, d_code, d_r, off2, nullptr,
+                           elem_off2, elem_fill2, slot_pt, slot_elem, sorted2, s));
+        NewtonIO io{sorted2, elem_off2, chunk_off2, slot_pt, res_code, nullptr, res_r, w.cap2,
+                    res_dist, counters + 2 * kNewtonCounters, stats + kStats, task_elem2,
+                    w.tb_elem2};
+        // the other candidates are few and near element faces: plain FP64
+        // in both modes (an FP32 phase would not pay for its launches)
+        chk(launch_newton(m, FPTS_FP64, n, d_pts, io, 3, s));
+        chk(launch_select2(m, n, off2, primary, slot_elem, w.cap2, res_r, res_dist, res_code,
+                           d_code, d_elem, d_r, d_dist, s));
+    }
+    if (m->profiling) m->prof_find++;
+    return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;
+}
+
+}  // namespace fpts
+
 extern "C" {
 
 void fpts_params_default(fpts_params *p, int dim, int ref_dim, int nodes_1d, int64_t n_elem)
@@ -300,93 +399,8 @@ int fpts_find(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
               double *d_r, double *d_dist, int precision, void *d_ws, size_t ws_bytes,
               void *stream)
 {
-    if (!m || n < 0 || n > INT32_MAX - 1) return FPTS_EINVAL;
-    if (precision != FPTS_FP64 && precision != FPTS_MIXED) return FPTS_EINVAL;
-    if (n == 0) return FPTS_OK;
-    if (!d_pts || !d_code || !d_elem || !d_r || !d_dist || !d_ws) return FPTS_EINVAL;
-    if (((uintptr_t)d_ws & 255) != 0) return FPTS_EINVAL;
-    const FindWs w = find_ws_layout(m, n);
-    if (w.cap2 > INT32_MAX || ws_bytes < w.total) return FPTS_EINVAL;
-    if (sticky_error()) return FPTS_EDEVICE;
-    hipStream_t s = (hipStream_t)stream;
-    int *cell_cnt = at<int>(d_ws, w.cell_cnt), *cell_fill = at<int>(d_ws, w.cell_fill);
-    int *cell_poff = at<int>(d_ws, w.cell_poff), *cell_choff = at<int>(d_ws, w.cell_choff);
-    int *cellpt = at<int>(d_ws, w.cellpt), *pbin = at<int>(d_ws, w.pbin);
-    int *ncand = at<int>(d_ws, w.ncand), *primary = at<int>(d_ws, w.primary);
-    int *elem_cnt = at<int>(d_ws, w.elem_cnt), *elem_fill = at<int>(d_ws, w.elem_fill);
-    int *elem_off = at<int>(d_ws, w.elem_off), *chunk_off = at<int>(d_ws, w.chunk_off);
-    int *sorted = at<int>(d_ws, w.sorted), *off2 = at<int>(d_ws, w.off2);
-    int *elem_cnt2 = at<int>(d_ws, w.elem_cnt2), *elem_fill2 = at<int>(d_ws, w.elem_fill2);
-    int *elem_off2 = at<int>(d_ws, w.elem_off2), *chunk_off2 = at<int>(d_ws, w.chunk_off2);
-    int *slot_pt = at<int>(d_ws, w.slot_pt), *slot_elem = at<int>(d_ws, w.slot_elem);
-    int *sorted2 = at<int>(d_ws, w.sorted2);
-    double *res_r = at<double>(d_ws, w.res_r), *res_dist = at<double>(d_ws, w.res_dist);
-    int *res_code = at<int>(d_ws, w.res_code), *tmp = at<int>(d_ws, w.scan_tmp);
-    int *counters = at<int>(d_ws, w.counters);
-    int *task_cell = at<int>(d_ws, w.task_cell), *task_elem = at<int>(d_ws, w.task_elem);
-    int *task_elem2 = at<int>(d_ws, w.task_elem2);
-    unsigned long long *stats = at<unsigned long long>(d_ws, w.stats);
-    const int64_t nel = m->nel, ncell = w.ncell, tb = w.scan_blocks;
-    hipError_t e = hipSuccess;
-    auto chk = [&](hipError_t x) {
-        if (e == hipSuccess) e = x;
-    };
-    {   // phases A and B: bin points by cell, candidates and primaries
-        Span sp(m, 0, s);
-        chk(launch_fill_i32(cell_cnt, ncell, 0, s));
-        chk(launch_fill_i32(cell_fill, ncell, 0, s));
-        chk(launch_fill_i32(elem_cnt, nel, 0, s));
-        chk(launch_fill_i32(elem_fill, nel, 0, s));
-        chk(launch_fill_i32(elem_cnt2, nel, 0, s));
-        chk(launch_fill_i32(elem_fill2, nel, 0, s));
-        chk(launch_fill_i32(counters, kCounters, 0, s));
-        chk(launch_fill_i32(reinterpret_cast<int *>(stats), 4 * kStats, 0, s));
-        chk(launch_cell_bin(m, 0, n, d_pts, cellpt, cell_cnt, nullptr, nullptr, nullptr, ncand,
-                            primary, d_code, d_elem, d_r, d_dist, s));
-        chk(launch_exclusive_scan(cell_cnt, cell_poff, ncell, 1, tmp, tb, s));
-        chk(launch_exclusive_scan(cell_cnt, cell_choff, ncell, kChunk, tmp, tb, s));
-        chk(launch_task_map(cell_choff, ncell, task_cell, s));
-        chk(launch_cell_bin(m, 1, n, d_pts, cellpt, nullptr, cell_poff, cell_fill, pbin,
-                            nullptr, nullptr, d_code, d_elem, d_r, d_dist, s));
-        chk(launch_locate_cells(m, n, d_pts, pbin, cell_poff, cell_choff, ncell, task_cell,
-                                w.tb_cell, ncand, primary, elem_cnt, d_code, d_elem, d_r, d_dist,
-                                s));
-        chk(launch_exclusive_scan(elem_cnt, elem_off, nel, 1, tmp, tb, s));
-        chk(launch_exclusive_scan(elem_cnt, chunk_off, nel, kChunk, tmp, tb, s));
-        chk(launch_task_map(chunk_off, nel, task_elem, s));
-        chk(launch_primary_scatter(n, nel, primary, elem_off, elem_fill, sorted, s));
-    }
-    {   // phase C: Newton on the primary candidates, results straight to the outputs
-        NewtonIO io{sorted, elem_off, chunk_off, nullptr, d_code, d_elem, d_r, n, d_dist,
-                    counters + kNewtonCounters, stats, task_elem, w.tb_elem};
-        {
-            Span sp(m, 1, s);
-            chk(launch_newton(m, precision, n, d_pts, io, 1, s));
-        }
-        Span sp(m, 2, s);
-        chk(launch_newton(m, precision, n, d_pts, io, 2, s));
-    }
-    {   // phase D: other candidates of unsettled points, then the selection rule
-        Span sp(m, 3, s);
-        chk(launch_resolve(m, 0, n, d_pts, cellpt, ncand, primary, d_code, d_r, off2, elem_cnt2,
-                           nullptr, nullptr, nullptr, nullptr, nullptr, s));
-        chk(launch_exclusive_scan(off2, off2, n, 1, tmp, tb, s));
-        chk(launch_exclusive_scan(elem_cnt2, elem_off2, nel, 1, tmp, tb, s));
-        chk(launch_exclusive_scan(elem_cnt2, chunk_off2, nel, kChunk, tmp, tb, s));
-        chk(launch_task_map(chunk_off2, nel, task_elem2, s));
-        chk(launch_resolve(m, 1, n, d_pts, cellpt, ncand, primary, d_code, d_r, off2, nullptr,
-                           elem_off2, elem_fill2, slot_pt, slot_elem, sorted2, s));
-        NewtonIO io{sorted2, elem_off2, chunk_off2, slot_pt, res_code, nullptr, res_r, w.cap2,
-                    res_dist, counters + 2 * kNewtonCounters, stats + kStats, task_elem2,
-                    w.tb_elem2};
-        // the other candidates are few and near element faces: plain FP64
-        // in both modes (an FP32 phase would not pay for its launches)
-        chk(launch_newton(m, FPTS_FP64, n, d_pts, io, 3, s));
-        chk(launch_select2(m, n, off2, primary, slot_elem, w.cap2, res_r, res_dist, res_code,
-                           d_code, d_elem, d_r, d_dist, s));
-    }
-    if (m->profiling) m->prof_find++;
-    return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;
+    return find_impl(m, n, d_pts, d_code, d_elem, d_r, d_dist, precision, d_ws, ws_bytes,
+                     stream, nullptr);
 }
 
 size_t fpts_eval_workspace_size(const fpts_mesh *m, int64_t n)
@@ -573,7 +587,8 @@ size_t fpts_lpt_workspace_size(const fpts_mesh *m, int64_t n)
     const size_t fw = fpts_find_workspace_size(m, n);
     if (fw == 0) return 0;
     const size_t ew = eval_ws_layout(m, n).total;
-    return align_up(sizeof(double) * (size_t)m->D * (size_t)std::max<int64_t>(n, 1)) +
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    return align_up(sizeof(double) * (size_t)m->D * nn) + align_up(sizeof(int) * nn) +
            std::max(fw, ew);
 }
 
@@ -598,11 +613,14 @@ int fpts_lpt_step(fpts_mesh *m, const fpts_lpt_params *p, int64_t n, int first, 
     if (need == 0 || ws_bytes < need) return FPTS_EINVAL;
     if (sticky_error()) return FPTS_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
-    // [D][n] interpolated fluid velocity, then the Find / Interpolate space
+    // [D][n] interpolated fluid velocity, [n] keep flags of the hinted
+    // search, then the Find / Interpolate space
     const size_t u_bytes = align_up(sizeof(double) * (size_t)m->D * (size_t)n);
+    const size_t k_bytes = align_up(sizeof(int) * (size_t)n);
     double *u = static_cast<double *>(d_ws);
-    void *sub = static_cast<char *>(d_ws) + u_bytes;
-    const size_t sub_bytes = ws_bytes - u_bytes;
+    int *keep = at<int>(d_ws, u_bytes);
+    void *sub = static_cast<char *>(d_ws) + u_bytes + k_bytes;
+    const size_t sub_bytes = ws_bytes - u_bytes - k_bytes;
     int st = fpts_eval(m, n, d_code, d_elem, d_r, m->D, d_field, u, sub, sub_bytes, stream);
     if (st != FPTS_OK) return st;
     LptArgs a;
@@ -628,7 +646,44 @@ int fpts_lpt_step(fpts_mesh *m, const fpts_lpt_params *p, int64_t n, int first, 
     }
     if (e != hipSuccess) return FPTS_EDEVICE;
     if (m->profiling) m->prof_lpt++;
-    return fpts_find(m, n, d_x, d_code, d_elem, d_r, d_dist, precision, sub, sub_bytes, stream);
+    if (!p->hint)
+        return find_impl(m, n, d_x, d_code, d_elem, d_r, d_dist, precision, sub, sub_bytes,
+                         stream, nullptr);
+    // Hinted search: a particle whose last code was INTERIOR is first searched
+    // in its previous element from its previous r; the full search then
+    // skips the particles that this settled.
+    const FindWs w = find_ws_layout(m, n);
+    int *primary = at<int>(sub, w.primary), *elem_cnt = at<int>(sub, w.elem_cnt);
+    int *elem_fill = at<int>(sub, w.elem_fill), *elem_off = at<int>(sub, w.elem_off);
+    int *chunk_off = at<int>(sub, w.chunk_off), *sorted = at<int>(sub, w.sorted);
+    int *task_elem = at<int>(sub, w.task_elem), *tmp = at<int>(sub, w.scan_tmp);
+    int *counters = at<int>(sub, w.counters);
+    unsigned long long *stats = at<unsigned long long>(sub, w.stats);
+    auto chk = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+    };
+    {
+        Span sp(m, 0, s);
+        chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
+        chk(launch_fill_i32(elem_fill, m->nel, 0, s));
+        chk(launch_fill_i32(counters, kCounters, 0, s));
+        chk(launch_fill_i32(reinterpret_cast<int *>(stats), 4 * kStats, 0, s));
+        chk(launch_hint(m, 0, n, d_code, d_elem, d_r, primary, elem_cnt, nullptr, s));
+        chk(launch_exclusive_scan(elem_cnt, elem_off, m->nel, 1, tmp, w.scan_blocks, s));
+        chk(launch_exclusive_scan(elem_cnt, chunk_off, m->nel, kChunk, tmp, w.scan_blocks, s));
+        chk(launch_task_map(chunk_off, m->nel, task_elem, s));
+        chk(launch_primary_scatter(n, m->nel, primary, elem_off, elem_fill, sorted, s));
+    }
+    {
+        Span sp(m, 2, s);
+        NewtonIO io{sorted, elem_off, chunk_off, nullptr, d_code, d_elem, d_r, n, d_dist,
+                    counters + kNewtonCounters, stats, task_elem, w.tb_elem};
+        chk(launch_newton(m, precision, n, d_x, io, 2, s));
+        chk(launch_hint(m, 1, n, d_code, d_elem, d_r, primary, nullptr, keep, s));
+    }
+    if (e != hipSuccess) return FPTS_EDEVICE;
+    return find_impl(m, n, d_x, d_code, d_elem, d_r, d_dist, precision, sub, sub_bytes, stream,
+                     keep);
 }
 
 }  // extern "C"

@@ -190,6 +190,12 @@ void bound_tables(const fpts_mesh *m, BoundTables *t);
 // arithmetic in the same order as host_setup; updates the host copies.
 int device_setup(fpts_mesh *m, hipStream_t s);
 
+// fpts_find; points with keep[p] != 0 (keep may be null) hold final results
+// and are not searched (api.cpp)
+int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int32_t *d_elem,
+              double *d_r, double *d_dist, int precision, void *d_ws, size_t ws_bytes,
+              void *stream, const int *keep);
+
 // workspace layouts (api.cpp)
 FindWs find_ws_layout(const fpts_mesh *m, int64_t n);
 EvalWs eval_ws_layout(const fpts_mesh *m, int64_t n);
@@ -200,11 +206,18 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int64_t n, int ceil_di
                                  int *tmp, int64_t tmp_blocks, hipStream_t s);
 int64_t scan_tmp_blocks(int64_t n);
 // phase A: pass 0 counts points per cell (and writes NOT_FOUND for points
-// outside the map), pass 1 scatters point ids into cell buckets
+// outside the map), pass 1 scatters point ids into cell buckets; points with
+// keep[p] != 0 (keep may be null) are left out and keep their results
 hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double *pts,
-                           int *cellpt, int *cell_cnt, const int *cell_poff, int *cell_fill,
-                           int *pbin, int *ncand, int *primary, int32_t *code, int32_t *elem,
-                           double *r, double *dist, hipStream_t s);
+                           const int *keep, int *cellpt, int *cell_cnt, const int *cell_poff,
+                           int *cell_fill, int *pbin, int *ncand, int *primary, int32_t *code,
+                           int32_t *elem, double *r, double *dist, hipStream_t s);
+// search hints: pass 0 makes the previous element of each previously
+// INTERIOR point its primary (counted per element); pass 1 sets keep[p] for
+// points the hinted search settled
+hipError_t launch_hint(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
+                       const int32_t *elem, const double *r, int *primary, int *elem_cnt,
+                       int *keep, hipStream_t s);
 // phase B: candidates of each point from its cell's list (one wave per 64
 // points of one cell), primary = deepest inside its OBB
 // task -> unit map of a task grid over nunit units with task offsets chunk_off

@@ -159,7 +159,8 @@ __device__ inline void write_not_found(int p, int n, int R, int32_t *code, int32
 // outside the map; pass 1: scatter point ids into their cell's bucket.
 template <int D>
 __global__ __launch_bounds__(256) void k_cell_bin(HashView h, int pass, int n, int R,
-                                                 const double *pts, int *cellpt, int *cell_cnt,
+                                                 const double *pts, const int *keep,
+                                                 int *cellpt, int *cell_cnt,
                                                  const int *cell_poff, int *cell_fill,
                                                  int *pbin, int *ncand, int *primary,
                                                  int32_t *code, int32_t *elem, double *r,
@@ -171,15 +172,19 @@ __global__ __launch_bounds__(256) void k_cell_bin(HashView h, int pass, int n, i
     if (pass == 0) {
         int c = -1;
         if (in) {
-            double x[D];
+            // a kept point (its result is already final) is not searched
+            const bool kept = keep && keep[p];
+            if (!kept) {
+                double x[D];
 #pragma unroll
-            for (int d = 0; d < D; ++d) x[d] = pts[(size_t)d * n + p];
-            c = cell_of<D>(h, x);
+                for (int d = 0; d < D; ++d) x[d] = pts[(size_t)d * n + p];
+                c = cell_of<D>(h, x);
+            }
             cellpt[p] = c;
             // every point gets defined candidate data, also those no cell holds
             ncand[p] = 0;
             primary[p] = -1;
-            if (c < 0) write_not_found(p, n, R, code, elem, r, dist);
+            if (c < 0 && !kept) write_not_found(p, n, R, code, elem, r, dist);
         }
         (void)wave_inc(cell_cnt, c, c >= 0);
     } else {
@@ -375,6 +380,32 @@ HashView hash_view(const fpts_mesh *m)
     return h;
 }
 
+// Search hints (points that move a little between searches): pass 0 takes
+// the previous element of every point whose previous code was INTERIOR as
+// its only candidate and counts it per element; pass 1 marks the points
+// whose hinted search ended INTERIOR at least kSettleGuard inside the
+// reference box: no other element can hold them in its interior, so that
+// result is the one the full search gives, and they are kept.
+__global__ __launch_bounds__(256) void k_hint(int pass, int n, int nel, int R,
+                                             const int32_t *code, const int32_t *elem,
+                                             const double *r, int *primary, int *elem_cnt,
+                                             int *keep)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = p < n;
+    if (pass == 0) {
+        const int e = in && code[p] == FPTS_INTERIOR ? elem[p] : -1;
+        const bool ok = e >= 0 && e < nel;
+        if (in) primary[p] = ok ? e : -1;
+        (void)wave_inc(elem_cnt, e, ok);
+    } else if (in) {
+        bool k = primary[p] >= 0 && code[p] == FPTS_INTERIOR;
+        double mg = 1.0;
+        for (int a = 0; a < R; ++a) mg = fmin(mg, 1.0 - fabs(r[(size_t)a * n + p]));
+        keep[p] = k && mg > kSettleGuard;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_fill_i32(int *p, int64_t count, int value, hipStream_t s)
@@ -405,17 +436,17 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int64_t n, int ceil_di
 }
 
 hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double *pts,
-                           int *cellpt, int *cell_cnt, const int *cell_poff, int *cell_fill,
-                           int *pbin, int *ncand, int *primary, int32_t *code, int32_t *elem,
-                           double *r, double *dist, hipStream_t s)
+                           const int *keep, int *cellpt, int *cell_cnt, const int *cell_poff,
+                           int *cell_fill, int *pbin, int *ncand, int *primary, int32_t *code,
+                           int32_t *elem, double *r, double *dist, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     HashView h = hash_view(m);
     const int grid = grid_for(n, 256);
     auto k = m->D == 2 ? k_cell_bin<2> : k_cell_bin<3>;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, h, pass, (int)n, m->R, pts, cellpt,
-                       cell_cnt, cell_poff, cell_fill, pbin, ncand, primary, code, elem, r,
-                       dist);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, h, pass, (int)n, m->R, pts, keep,
+                       cellpt, cell_cnt, cell_poff, cell_fill, pbin, ncand, primary, code, elem,
+                       r, dist);
     return hipGetLastError();
 }
 
@@ -476,6 +507,20 @@ hipError_t launch_select2(const fpts_mesh *m, int64_t n, const int *off2, const 
     hipLaunchKernelGGL(k_select2, dim3(grid_for(n, 256)), dim3(256), 0, s, (int)n, m->R, off2,
                        primary, slot_elem, cap2, res_r, res_dist, res_code, code, elem, r,
                        dist);
+    return hipGetLastError();
+}
+
+}  // namespace fpts
+
+namespace fpts {
+
+hipError_t launch_hint(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
+                       const int32_t *elem, const double *r, int *primary, int *elem_cnt,
+                       int *keep, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hint, dim3(grid_for(n, 256)), dim3(256), 0, s, pass, (int)n,
+                       (int)m->nel, m->R, code, elem, r, primary, elem_cnt, keep);
     return hipGetLastError();
 }
 

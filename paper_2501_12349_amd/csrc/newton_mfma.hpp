@@ -596,7 +596,10 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
         const unsigned long long waitm = __ballot(leader && state == S_WAIT);
         const unsigned long long stepm = __ballot(leader && (state == S_STEP || state == S_INIT));
         if (!waitm && !stepm) break;
-        const bool do_s2 = waitm && (__popcll(waitm) >= 4 || !stepm);
+        // a slot that waits for second derivatives gets them at once: holding
+        // it back to batch more waiting slots (4 or 8) costs more in idle
+        // slots than the batching saves (measured on hex48)
+        const bool do_s2 = waitm != 0;
         if (do_s2) {
             T Sn[kSym<R>];
             sweep2<T, D, R, N>(xl, tab, lane, r, dx, Sn);
@@ -1075,7 +1078,8 @@ hipError_t launch_newton_kind(const fpts_mesh *m, bool mixed, int64_t n, const d
     }
     if (which & 2) {
         if (k.newton32) {
-            hipLaunchKernelGGL(k.newton32, dim3(m->cus * 8), dim3(64), k.lds_newton32, s, a);
+            // three waves per SIMD, as the kernel's register budget allows
+            hipLaunchKernelGGL(k.newton32, dim3(m->cus * 12), dim3(64), k.lds_newton32, s, a);
             const hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }

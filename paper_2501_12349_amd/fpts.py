@@ -62,7 +62,7 @@ class KernelTimes(ctypes.Structure):
 class LptParams(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("dt", ctypes.c_double),
                 ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
-                ("periodic", ctypes.c_int * 3)]
+                ("periodic", ctypes.c_int * 3), ("hint", ctypes.c_int)]
 
 
 class ServerStats(ctypes.Structure):
@@ -333,9 +333,10 @@ class Mesh:
 class Particles:
     """Device state of n particles for Mesh.lpt_step: positions x and
     velocities v [dim][n], the Adams-Bashforth history [2][dim][n] and the
-    Find result of x.  ``start(mesh)`` runs the initial Find."""
+    Find result of x.  ``start(mesh)`` runs the initial Find.  hint=True
+    searches each particle's previous element first (fpts_lpt.h)."""
 
-    def __init__(self, x, v, tau, dt, lo, hi, periodic):
+    def __init__(self, x, v, tau, dt, lo, hi, periodic, hint=False):
         import torch
         if x.dtype != torch.float64 or not x.is_cuda or x.dim() != 2 or \
                 tuple(v.shape) != tuple(x.shape) or v.dtype != torch.float64 or not v.is_cuda:
@@ -347,6 +348,7 @@ class Particles:
         self.n = n
         self.params = LptParams()
         self.params.tau, self.params.dt = float(tau), float(dt)
+        self.params.hint = 1 if hint else 0
         for d in range(3):
             self.params.lo[d] = float(lo[d]) if d < D else 0.0
             self.params.hi[d] = float(hi[d]) if d < D else 1.0

@@ -42,7 +42,7 @@ def _extra_particles(wl):
     return np.array(x), np.array(v)
 
 
-def _run_both(wl, steps, tau, dt, precision="fp64"):
+def _run_both(wl, steps, tau, dt, precision="fp64", hint=False):
     fpts = _fpts()
     xe, ve = _extra_particles(wl)
     x0 = np.ascontiguousarray(np.concatenate([wl["pts"], xe], axis=1))
@@ -50,7 +50,7 @@ def _run_both(wl, steps, tau, dt, precision="fp64"):
     gm = fpts.Mesh(wl["nodes"], wl["N"])
     field = torch.from_numpy(wl["fields"]).cuda()
     P = fpts.Particles(torch.from_numpy(x0).cuda(), torch.from_numpy(v0).cuda(), tau, dt,
-                       wl["lo"], wl["hi"], wl["periodic"]).start(gm, precision)
+                       wl["lo"], wl["hi"], wl["periodic"], hint=hint).start(gm, precision)
     for k in range(steps):
         gm.lpt_step(P, field, first=(k == 0), precision=precision)
     torch.cuda.synchronize()
@@ -78,17 +78,21 @@ def _compare(wl, om, g, o):
     return rep
 
 
+@pytest.mark.parametrize("hint", [False, True])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("tau", [0.05, 5.0])
-def test_channel3d_matches_oracle_loop(precision, tau):
+def test_channel3d_matches_oracle_loop(precision, tau, hint):
+    """The hinted Find (previous element first) is held to the same bars as
+    the full Find the oracle runs every step."""
     wl = W.channel(n_el=(6, 4, 6), N=6, n_y=6)
-    om, g, o = _run_both(wl, 20, tau, 0.01, precision)
+    om, g, o = _run_both(wl, 20, tau, 0.01, precision, hint)
     _compare(wl, om, g, o)
 
 
-def test_channel2d_matches_oracle_loop():
+@pytest.mark.parametrize("hint", [False, True])
+def test_channel2d_matches_oracle_loop(hint):
     wl = W.channel(n_el=(8, 4), N=5, n_y=10)
-    om, g, o = _run_both(wl, 25, 0.1, 0.01)
+    om, g, o = _run_both(wl, 25, 0.1, 0.01, hint=hint)
     _compare(wl, om, g, o)
 
 
@@ -133,7 +137,8 @@ def test_rejects_bad_arguments():
     torch.cuda.synchronize()
 
 
-def test_channel_full_size_sampled():
+@pytest.mark.parametrize("hint", [False, True])
+def test_channel_full_size_sampled(hint):
     """The channel of the particle-tracking table (36 x 24 x 36 hexes, p = 7,
     15.9M computational points) with 1.02 particles per point: 16.5M
     particles, three steps on the GPU; 3000 sampled particles run through
@@ -145,7 +150,8 @@ def test_channel_full_size_sampled():
     gm = fpts.Mesh(wl["nodes"], wl["N"])
     field = torch.from_numpy(wl["fields"]).cuda()
     P = fpts.Particles(torch.from_numpy(wl["pts"]).cuda(), torch.from_numpy(wl["v0"]).cuda(),
-                       wl["tau"], wl["dt"], wl["lo"], wl["hi"], wl["periodic"]).start(gm)
+                       wl["tau"], wl["dt"], wl["lo"], wl["hi"], wl["periodic"],
+                       hint=hint).start(gm)
     steps = 3
     for k in range(steps):
         gm.lpt_step(P, field, first=(k == 0))
