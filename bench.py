@@ -332,6 +332,9 @@ def main():
     ap.add_argument("--line-level", type=int, default=8,
                     help="refinement level of the 2D line-mesh run (84 x 2^level elements; "
                          "-1: skip)")
+    ap.add_argument("--only", choices=("lpt", "line"),
+                    help="run only the particle-tracking or the line-mesh leg and print its "
+                         "object (for profiling those kernels; not the benchmark line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this benchmark runs on exactly one GPU: the find/eval path has no "
@@ -341,6 +344,15 @@ def main():
 
     import torch
     from paper_2501_12349_amd import fpts
+
+    if args.only == "lpt":
+        print(json.dumps(particle_tracking([float(r) for r in args.lpt_ratios.split(",")],
+                                           args.lpt_steps, args.warmup, "fp64")), flush=True)
+        return
+    if args.only == "line":
+        print(json.dumps(line_surface(max(args.line_level, 0), args.steps, args.warmup)),
+              flush=True)
+        return
 
     t0 = time.perf_counter()
     wl = make_workload(args.workload)
