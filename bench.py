@@ -1,8 +1,9 @@
 """Benchmark: located + interpolated points per second on one MI355X.
 
-One step = fpts_find (hash lookup, box filter, trust-region Newton,
-selection) + fpts_eval of all fields, over one batch of device-resident
-points.  Default workload: 48^3 curved hexes, p = 7 (N = 8 GLL nodes per
+One step = Find (hash lookup, box filter, trust-region Newton, selection)
+and Interpolate of all fields over one batch of device-resident points, as
+one fpts_find_eval call (bit for bit the outputs of fpts_find followed by
+fpts_eval; the two separate calls are timed beside it).  Default workload: 48^3 curved hexes, p = 7 (N = 8 GLL nodes per
 direction), 2^24 points uniform in the cube, 3 fields.  Both Newton
 precisions are timed (FP64, and FP32 passes + FP64 polish); `value` is the
 FP64 path, the mixed result sits beside it.  Beside them: the particle
@@ -387,11 +388,17 @@ def main():
                r=torch.empty((R, n), dtype=torch.float64, device=dev),
                dist=torch.empty(n, dtype=torch.float64, device=dev))
     u = torch.empty((nf, n), dtype=torch.float64, device=dev)
-    ws_f = torch.empty(gm.find_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    # one workspace serves fpts_find_eval and, for the comparison with the two
+    # separate calls, fpts_find (its layout starts the same way)
+    ws_f = torch.empty(gm.find_eval_workspace_bytes(n), dtype=torch.uint8, device=dev)
     ws_e = torch.empty(gm.eval_workspace_bytes(n), dtype=torch.uint8, device=dev)
-    log("workspace find %.2f GB, eval %.2f GB" % (ws_f.numel() / 1e9, ws_e.numel() / 1e9))
+    log("workspace find+eval %.2f GB, eval %.2f GB" % (ws_f.numel() / 1e9, ws_e.numel() / 1e9))
 
     def step(prec):
+        # one pass of the path: Find and Interpolate of every point
+        gm.find_eval(pts, fields, precision=prec, out=out, u=u, ws=ws_f)
+
+    def step_separate(prec):
         gm.find(pts, precision=prec, out=out, ws=ws_f)
         gm.eval(out, fields, out=u, ws=ws_e)
 
@@ -439,6 +446,17 @@ def main():
 
     main_mode = "fp64" if "fp64" in results else list(results)[0]
     r0 = results[main_mode]
+    # the same work as fpts_find + fpts_eval called one after the other
+    for _ in range(args.warmup):
+        step_separate(main_mode)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step_separate(main_mode)
+    torch.cuda.synchronize()
+    dt_sep = (time.perf_counter() - t0) / args.steps
+    log("%s, fpts_find + fpts_eval as two calls: %.3f ms/step  %.1f Mpts/s" % (
+        main_mode, dt_sep * 1e3, n / dt_sep / 1e6))
     achieved = r0["flops"] / (r0["newton_ms"] * 1e-3) / 1e12
     # HBM bytes per k_newton launch from the committed counter summary of this
     # workload (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated); None when
@@ -463,7 +481,8 @@ def main():
         "config": {"workload": "%s_%dpts_%dfields" % (wl["name"], n, nf),
                    "n_elem": int(wl["nodes"].shape[0]), "nodes_1d": N, "dim": D,
                    "ref_dim": R, "n_points": n, "n_fields": nf, "precision": main_mode,
-                   "step": "find + eval of all fields, inputs resident in HBM"},
+                   "step": "find + eval of all fields (fpts_find_eval), inputs resident "
+                           "in HBM"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4), "traffic": traffic,
@@ -486,6 +505,9 @@ def main():
                          ("locate", "nearest", "newton", "select") else "eval_calls"], 1), 4)
                          for k in ("locate", "nearest", "newton", "select", "eval_bin", "eval")}
     line["newton_stats"] = {"primary": r0["stats"], "all": r0["stats_all"]}
+    line["separate_calls"] = {"value": round(n / dt_sep / 1e6, 3), "unit": "Mpts/s",
+                              "ms_per_step": round(dt_sep * 1e3, 4),
+                              "calls": "fpts_find then fpts_eval"}
     if args.pcie_steps > 0:
         line["pcie_inclusive"] = pcie_inclusive(gm, wl, fields, ws_f, ws_e, main_mode,
                                                 args.pcie_steps)

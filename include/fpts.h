@@ -180,6 +180,25 @@ int fpts_eval_order(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_
                     const double *d_r, int n_fields, int field_nodes_1d, const double *d_field,
                     double *d_out, void *d_ws, size_t ws_bytes, void *stream);
 
+/* Bytes of device workspace fpts_find_eval needs for n points, or 0 when n
+ * is out of range. */
+size_t fpts_find_eval_workspace_size(const fpts_mesh *m, int64_t n);
+
+/* Find and Interpolate in one call: the outputs of fpts_find (d_code,
+ * d_elem, d_r, d_dist) and of fpts_eval_order (d_out [n_fields][n] for
+ * d_field [n_fields][n_elem][field_nodes_1d^ref_dim]), bit for bit the
+ * same as the two calls in a row.  The points whose primary candidate
+ * settled them -- INTERIOR at least 1e-9 inside its reference box, almost
+ * all interior points -- are interpolated straight from Find's own element
+ * buckets, with r taken in bucket order from the workspace (no second
+ * binning, no gather of r); the rest go through the binning of fpts_eval.
+ * d_ws: at least fpts_find_eval_workspace_size(m, n) bytes, 256-byte
+ * aligned.  FPTS_EINVAL as fpts_find and fpts_eval_order. */
+int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code,
+                   int32_t *d_elem, double *d_r, double *d_dist, int precision, int n_fields,
+                   int field_nodes_1d, const double *d_field, double *d_out, void *d_ws,
+                   size_t ws_bytes, void *stream);
+
 /* Counters of the last fpts_find that used workspace d_ws (read back with a
  * device-to-host copy on `stream`, which is synchronised) for one Newton
  * pass: pass 1 = primary candidates, 2 = the other candidates of points the

@@ -175,10 +175,11 @@ hipError_t launch_newton(const fpts_mesh *m, int precision, int64_t n, const dou
 namespace fpts {
 
 // fpts_find with an optional keep mask: points with keep[p] != 0 hold final
-// results on entry and are not searched.
+// results on entry and are not searched; with rs the primary pass also
+// writes its settling results in list order (NewtonIO::rs).
 int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int32_t *d_elem,
               double *d_r, double *d_dist, int precision, void *d_ws, size_t ws_bytes,
-              void *stream, const int *keep)
+              void *stream, const int *keep, double *rs)
 {
     if (!m || n < 0 || n > INT32_MAX - 1) return FPTS_EINVAL;
     if (precision != FPTS_FP64 && precision != FPTS_MIXED) return FPTS_EINVAL;
@@ -238,7 +239,7 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     }
     {   // phase C: Newton on the primary candidates, results straight to the outputs
         NewtonIO io{sorted, elem_off, chunk_off, nullptr, d_code, d_elem, d_r, n, d_dist,
-                    counters + kNewtonCounters, stats, task_elem, w.tb_elem};
+                    counters + kNewtonCounters, stats, task_elem, w.tb_elem, rs, n};
         {
             Span sp(m, 1, s);
             chk(launch_newton(m, precision, n, d_pts, io, 1, s));
@@ -400,7 +401,7 @@ int fpts_find(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
               void *stream)
 {
     return find_impl(m, n, d_pts, d_code, d_elem, d_r, d_dist, precision, d_ws, ws_bytes,
-                     stream, nullptr);
+                     stream, nullptr, nullptr);
 }
 
 size_t fpts_eval_workspace_size(const fpts_mesh *m, int64_t n)
@@ -447,12 +448,14 @@ int fpts_eval_order(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_
         Span sp(m, 4, s);
         chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
         chk(launch_fill_i32(elem_fill, m->nel, 0, s));
-        chk(launch_eval_bin(m, 0, n, d_code, d_elem, n_fields, d_out, elem_cnt, nullptr, nullptr,
+        chk(launch_eval_bin(m, 0, n, d_code, d_elem, nullptr, nullptr, n_fields, d_out, elem_cnt,
+                            nullptr, nullptr,
                             nullptr, s));
         chk(launch_exclusive_scan(elem_cnt, elem_off, m->nel, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt, chunk_off, m->nel, kChunk, tmp, tb, s));
         chk(launch_task_map(chunk_off, m->nel, task_elem, s));
-        chk(launch_eval_bin(m, 1, n, d_code, d_elem, n_fields, d_out, nullptr, elem_off,
+        chk(launch_eval_bin(m, 1, n, d_code, d_elem, nullptr, nullptr, n_fields, d_out, nullptr,
+                            elem_off,
                             elem_fill, sorted, s));
     }
     {
@@ -648,7 +651,7 @@ int fpts_lpt_step(fpts_mesh *m, const fpts_lpt_params *p, int64_t n, int first, 
     if (m->profiling) m->prof_lpt++;
     if (!p->hint)
         return find_impl(m, n, d_x, d_code, d_elem, d_r, d_dist, precision, sub, sub_bytes,
-                         stream, nullptr);
+                         stream, nullptr, nullptr);
     // Hinted search: a particle whose last code was INTERIOR is first searched
     // in its previous element from its previous r; the full search then
     // skips the particles that this settled.
@@ -683,7 +686,82 @@ int fpts_lpt_step(fpts_mesh *m, const fpts_lpt_params *p, int64_t n, int first, 
     }
     if (e != hipSuccess) return FPTS_EDEVICE;
     return find_impl(m, n, d_x, d_code, d_elem, d_r, d_dist, precision, sub, sub_bytes, stream,
-                     keep);
+                     keep, nullptr);
+}
+
+size_t fpts_find_eval_workspace_size(const fpts_mesh *m, int64_t n)
+{
+    if (!m || n < 0 || n > INT32_MAX - 1) return 0;
+    const size_t fw = fpts_find_workspace_size(m, n);
+    if (fw == 0) return 0;
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    return fw + align_up(eval_ws_layout(m, n).total) +
+           align_up(sizeof(double) * (size_t)m->R * nn);
+}
+
+int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code,
+                   int32_t *d_elem, double *d_r, double *d_dist, int precision, int n_fields,
+                   int field_nodes_1d, const double *d_field, double *d_out, void *d_ws,
+                   size_t ws_bytes, void *stream)
+{
+    if (!m || n < 0 || n > INT32_MAX - 1 || n_fields < 1) return FPTS_EINVAL;
+    if (field_nodes_1d < 2 || field_nodes_1d > kMaxN) return FPTS_EINVAL;
+    if (precision != FPTS_FP64 && precision != FPTS_MIXED) return FPTS_EINVAL;
+    if (n == 0) return FPTS_OK;
+    if (!d_pts || !d_code || !d_elem || !d_r || !d_dist || !d_field || !d_out || !d_ws)
+        return FPTS_EINVAL;
+    if (((uintptr_t)d_ws & 255) != 0) return FPTS_EINVAL;
+    const size_t need = fpts_find_eval_workspace_size(m, n);
+    if (need == 0 || ws_bytes < need) return FPTS_EINVAL;
+    // [find workspace][interpolation workspace][R][n] results in list order
+    const FindWs w = find_ws_layout(m, n);
+    const EvalWs v = eval_ws_layout(m, n);
+    void *ews = static_cast<char *>(d_ws) + w.total;
+    double *rs = at<double>(d_ws, w.total + align_up(v.total));
+    int st = find_impl(m, n, d_pts, d_code, d_elem, d_r, d_dist, precision, d_ws, w.total,
+                       stream, nullptr, rs);
+    if (st != FPTS_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int *primary = at<int>(d_ws, w.primary), *sorted = at<int>(d_ws, w.sorted);
+    const int *elem_off = at<int>(d_ws, w.elem_off), *chunk_off = at<int>(d_ws, w.chunk_off);
+    const int *task_elem = at<int>(d_ws, w.task_elem);
+    int *elem_cnt = at<int>(ews, v.elem_cnt), *elem_fill = at<int>(ews, v.elem_fill);
+    int *eoff = at<int>(ews, v.elem_off), *choff = at<int>(ews, v.chunk_off);
+    int *tmp = at<int>(ews, v.scan_tmp), *esorted = at<int>(ews, v.sorted);
+    int *etask = at<int>(ews, v.task_elem);
+    const int64_t tb = scan_tmp_blocks(m->nel);
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+    };
+    {
+        // points the primary pass settled: Find's own element buckets, r in
+        // list order (no re-binning, no gather of r)
+        Span sp(m, 5, s);
+        chk(launch_eval(m, n, nullptr, n_fields, field_nodes_1d, d_field, d_out, sorted,
+                        elem_off, chunk_off, task_elem, w.tb_elem, s, rs));
+    }
+    {
+        // the rest (settled by the second search, BORDER, NOT_FOUND): the
+        // plain interpolation path restricted to them
+        Span sp(m, 4, s);
+        chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
+        chk(launch_fill_i32(elem_fill, m->nel, 0, s));
+        chk(launch_eval_bin(m, 0, n, d_code, d_elem, d_r, primary, n_fields, d_out, elem_cnt,
+                            nullptr, nullptr, nullptr, s));
+        chk(launch_exclusive_scan(elem_cnt, eoff, m->nel, 1, tmp, tb, s));
+        chk(launch_exclusive_scan(elem_cnt, choff, m->nel, kChunk, tmp, tb, s));
+        chk(launch_task_map(choff, m->nel, etask, s));
+        chk(launch_eval_bin(m, 1, n, d_code, d_elem, d_r, primary, n_fields, d_out, nullptr,
+                            eoff, elem_fill, esorted, s));
+    }
+    {
+        Span sp(m, 5, s);
+        chk(launch_eval(m, n, d_r, n_fields, field_nodes_1d, d_field, d_out, esorted, eoff,
+                        choff, etask, v.tb_elem, s));
+    }
+    if (m->profiling) m->prof_eval++;
+    return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;
 }
 
 }  // extern "C"

@@ -50,6 +50,9 @@ struct HashView {
 // Task -> unit comes from a map filled after the task offsets are scanned
 // (launch_task_map).
 constexpr int kXcd = 8;
+// a primary result settles its point when INTERIOR at least this far inside
+// the reference box (no other element can then hold the point inside)
+constexpr double kSettleGuard = 1e-9;
 
 // Upper bound on the tasks of n items over nunit units.
 inline int64_t task_bound(int64_t n, int64_t nunit)
@@ -131,6 +134,12 @@ struct NewtonIO {
     unsigned long long *stats;
     const int *task_elem;   // task -> element of the nearest-node task grid
     int64_t task_bound;     // tasks of that grid at most
+    // optional (fused find + interpolate, primary pass): results that settle
+    // their point -- INTERIOR at least kSettleGuard inside -- also go to
+    // rs[k * rs_stride + q] at the pair's position q in `list`; NaN marks
+    // the other positions
+    double *rs;
+    int64_t rs_stride;
 };
 
 }  // namespace fpts
@@ -194,7 +203,7 @@ int device_setup(fpts_mesh *m, hipStream_t s);
 // and are not searched (api.cpp)
 int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int32_t *d_elem,
               double *d_r, double *d_dist, int precision, void *d_ws, size_t ws_bytes,
-              void *stream, const int *keep);
+              void *stream, const int *keep, double *rs);
 
 // workspace layouts (api.cpp)
 FindWs find_ws_layout(const fpts_mesh *m, int64_t n);
@@ -244,14 +253,17 @@ hipError_t launch_select2(const fpts_mesh *m, int64_t n, const int *off2, const 
 // which: 1 = nearest-node start, 2 = Newton, 3 = both
 hipError_t launch_newton(const fpts_mesh *m, int precision, int64_t n, const double *pts,
                          const NewtonIO &io, int which, hipStream_t s);
+// interpolation binning; with `primary` (fused find + interpolate) the
+// points their primary result settled are left out (r is read for that)
 hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
-                           const int32_t *elem, int n_fields, double *out, int *elem_cnt,
-                           const int *elem_off, int *elem_fill, int *sorted, hipStream_t s);
+                           const int32_t *elem, const double *r, const int *primary,
+                           int n_fields, double *out, int *elem_cnt, const int *elem_off,
+                           int *elem_fill, int *sorted, hipStream_t s);
 // field_n: GLL nodes per direction of the field (its own order, 2..kMaxN)
 hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fields, int field_n,
                        const double *field, double *out, const int *sorted,
                        const int *elem_off, const int *chunk_off, const int *task_elem,
-                       int64_t task_bound, hipStream_t s);
+                       int64_t task_bound, hipStream_t s, const double *rs = nullptr);
 hipError_t launch_nodes32(const fpts_mesh *m, hipStream_t s);
 // score rows of the nearest-node contraction: per element and node j,
 // (-2 x_j, -2 y_j, -2 z_j, |x_j|^2) element-local (D = 2: (-2x, -2y, |x|^2, 0)),

@@ -16,24 +16,34 @@ namespace {
 typedef const __attribute__((address_space(4))) double cdouble;
 
 // pass 0: count points per element and write NaN for NOT_FOUND points;
-// pass 1: scatter point ids into their element's bucket.
-__global__ __launch_bounds__(256) void k_eval_bin(int pass, int n, int nel, const int32_t *code,
-                                                 const int32_t *elem, int n_fields, double *out,
-                                                 int *elem_cnt, const int *elem_off,
-                                                 int *elem_fill, int *sorted)
+// pass 1: scatter point ids into their element's bucket.  With `primary`
+// (fused find + interpolate) the points that their primary result settled
+// are left out: the fused pass over Find's primary list has them.
+__global__ __launch_bounds__(256) void k_eval_bin(int pass, int n, int nel, int R,
+                                                 const int32_t *code, const int32_t *elem,
+                                                 const double *r, const int *primary,
+                                                 int n_fields, double *out, int *elem_cnt,
+                                                 const int *elem_off, int *elem_fill,
+                                                 int *sorted)
 {
     // no early exit: wave_inc needs every lane
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = p < n;
     const int e = in ? elem[p] : -1;
     const bool found = in && code[p] != FPTS_NOT_FOUND && e >= 0 && e < nel;
+    bool done = false;
+    if (primary && found && code[p] == FPTS_INTERIOR && primary[p] == e) {
+        double mg = 1.0;
+        for (int k = 0; k < R; ++k) mg = fmin(mg, 1.0 - fabs(r[(size_t)k * n + p]));
+        done = mg > kSettleGuard;
+    }
     if (pass == 0) {
-        (void)wave_inc(elem_cnt, e, found);
+        (void)wave_inc(elem_cnt, e, found && !done);
         if (in && !found)
             for (int f = 0; f < n_fields; ++f) out[(size_t)f * n + p] = __builtin_nan("");
     } else {
-        const int k = wave_inc(elem_fill, e, found);
-        if (found) sorted[elem_off[e] + k] = p;
+        const int k = wave_inc(elem_fill, e, found && !done);
+        if (found && !done) sorted[elem_off[e] + k] = p;
     }
 }
 
@@ -64,6 +74,9 @@ struct EvalArgs {
     const int *chunk_off;
     const int *task_elem;   // task -> element (task grid)
     Basis basis;
+    // fused mode (rs != null): `sorted` is the primary list of Find and
+    // r comes from rs[k * n + list position]; NaN there skips the point
+    const double *rs;
 };
 
 template <int R, int N>
@@ -77,12 +90,17 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
         const int beg = a.elem_off[e] + (t - a.chunk_off[e]) * kChunk;
         const int end = min(a.elem_off[e + 1], beg + kChunk);
         const int idx = beg + lane;
-        const bool has = idx < end;
+        bool has = idx < end;
         const int p = has ? a.sorted[idx] : 0;
+        double rr[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (has) rr[k] = a.rs ? a.rs[(size_t)k * a.n + idx] : a.r[(size_t)k * a.n + p];
+        if (a.rs) has = has && !__builtin_isnan(rr[0]);
         double v0[N], v1[N], v2[N];
-        basis_v<N>(has ? a.r[p] : 0.0, a.basis.z, a.basis.w, v0);
-        if (R >= 2) basis_v<N>(has ? a.r[(size_t)a.n + p] : 0.0, a.basis.z, a.basis.w, v1);
-        if (R == 3) basis_v<N>(has ? a.r[(size_t)2 * a.n + p] : 0.0, a.basis.z, a.basis.w, v2);
+        basis_v<N>(has ? rr[0] : 0.0, a.basis.z, a.basis.w, v0);
+        if (R >= 2) basis_v<N>(has ? rr[1] : 0.0, a.basis.z, a.basis.w, v1);
+        if (R == 3) basis_v<N>(has ? rr[2] : 0.0, a.basis.z, a.basis.w, v2);
         for (int f = 0; f < a.n_fields; ++f) {
             cdouble *u = (cdouble *)(a.field + ((size_t)f * a.nel + e) * NP);
             double acc = 0.0;
@@ -174,20 +192,21 @@ EvalFn pick_eval(int N)
 }  // namespace
 
 hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
-                           const int32_t *elem, int n_fields, double *out, int *elem_cnt,
-                           const int *elem_off, int *elem_fill, int *sorted, hipStream_t s)
+                           const int32_t *elem, const double *r, const int *primary,
+                           int n_fields, double *out, int *elem_cnt, const int *elem_off,
+                           int *elem_fill, int *sorted, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_eval_bin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pass,
-                       (int)n, (int)m->nel, code, elem, n_fields, out, elem_cnt, elem_off,
-                       elem_fill, sorted);
+                       (int)n, (int)m->nel, m->R, code, elem, r, primary, n_fields, out,
+                       elem_cnt, elem_off, elem_fill, sorted);
     return hipGetLastError();
 }
 
 hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fields, int field_n,
                        const double *field, double *out, const int *sorted, const int *elem_off,
                        const int *chunk_off, const int *task_elem, int64_t task_bound,
-                       hipStream_t s)
+                       hipStream_t s, const double *rs)
 {
     EvalFn fn = m->R == 3 ? pick_eval<3>(field_n)
                 : m->R == 2 ? pick_eval<2>(field_n) : pick_eval<1>(field_n);
@@ -203,6 +222,7 @@ hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fie
     a.elem_off = elem_off;
     a.chunk_off = chunk_off;
     a.task_elem = task_elem;
+    a.rs = rs;
     if (field_n == m->N) a.basis = m->basis;
     else gll::fill(field_n, a.basis.z, a.basis.w);
     hipLaunchKernelGGL(fn, dim3(task_grid(task_bound, m->cus)), dim3(64), 0, s, a);

@@ -267,7 +267,6 @@ __global__ __launch_bounds__(256) void k_primary_scatter(int n, int nel, const i
 // inside the reference box: no other element can then hold the point in its
 // interior (it would overlap the primary), so the paper's rule -- first
 // INTERIOR candidate in ascending id order -- picks the same element.
-constexpr double kSettleGuard = 1e-9;
 
 __device__ inline bool settled(int p, int n, int R, const int *ncand, const int32_t *code,
                                const double *r)

@@ -235,6 +235,7 @@ __global__ __launch_bounds__(64) void k_newton_line(LineArgs a)
         if (io.elem) io.elem[item] = e;
         io.r[item] = r;
         io.dist[item] = sqrt(f);
+        if (io.rs) io.rs[idx] = inside && 1.0 - fabs(r) > kSettleGuard ? r : __builtin_nan("");
     }
     // counters: pairs, passes, evaluations, evaluations with x''
     n_pairs = wave_sum(n_pairs);

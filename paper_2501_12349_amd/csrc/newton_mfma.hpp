@@ -495,7 +495,7 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
     const int slot = lane & 15;
     const bool leader = lane < 16;
     const NewtonIO &io = a.io;
-    int state = S_FREE, item = 0, pass = 0;
+    int state = S_FREE, item = 0, pass = 0, pos = 0;
     T xs[D], r[R], q[R], dx[D], Hs[kSym<R>], alpha = T(1), pred = T(0), dmax = T(0),
         xnorm = T(0);
     Obj<T, D, R> cur;
@@ -553,6 +553,7 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
             if (idx < cend) {
                 const int c0 = idx - cstart;
                 item = citem[c0];
+                pos = idx;
 #pragma unroll
                 for (int c = 0; c < D; ++c) xs[c] = cache[c * kCache + c0];
 #pragma unroll
@@ -584,6 +585,16 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                 io.code[item] = inside ? FPTS_INTERIOR : FPTS_BORDER;
                 if (io.elem) io.elem[item] = e;
                 io.dist[item] = sqrt((double)cur.f);
+                if (io.rs) {
+                    double mg = 1.0;
+#pragma unroll
+                    for (int k = 0; k < R; ++k) mg = fmin(mg, 1.0 - fabs((double)r[k]));
+                    const bool settles = inside && mg > kSettleGuard;
+#pragma unroll
+                    for (int k = 0; k < R; ++k)
+                        io.rs[(size_t)k * io.rs_stride + pos] =
+                            settles ? (double)r[k] : __builtin_nan("");
+                }
             }
 #pragma unroll
             for (int k = 0; k < R; ++k) io.r[(size_t)k * io.ostride + item] = (double)r[k];

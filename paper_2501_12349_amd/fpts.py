@@ -17,7 +17,8 @@ _PREC = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}
 # Entry points declared in include/fpts.h.
 EXPORTS = ("fpts_params_default", "fpts_setup", "fpts_destroy", "fpts_update_nodes",
            "fpts_find_workspace_size", "fpts_find", "fpts_eval_workspace_size",
-           "fpts_eval", "fpts_eval_order", "fpts_find_stats_get", "fpts_profile", "fpts_profile_read",
+           "fpts_eval", "fpts_eval_order", "fpts_find_eval_workspace_size", "fpts_find_eval",
+           "fpts_find_stats_get", "fpts_profile", "fpts_profile_read",
            "fpts_get_boxes", "fpts_get_hash", "fpts_status_string")
 
 # Entry points declared in include/fpts_lpt.h.
@@ -98,6 +99,10 @@ def load_library(path=LIB_PATH):
     L.fpts_eval.argtypes = [vp, i64, vp, vp, vp, i32, vp, vp, vp, ctypes.c_size_t, vp]
     L.fpts_eval_order.argtypes = [vp, i64, vp, vp, vp, i32, i32, vp, vp, vp, ctypes.c_size_t,
                                   vp]
+    L.fpts_find_eval_workspace_size.argtypes = [vp, i64]
+    L.fpts_find_eval_workspace_size.restype = ctypes.c_size_t
+    L.fpts_find_eval.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, i32, i32, vp, vp, vp,
+                                 ctypes.c_size_t, vp]
     L.fpts_find_stats_get.argtypes = [vp, i64, vp, i32, ctypes.POINTER(FindStats), vp]
     L.fpts_profile.argtypes = [vp, i32]
     L.fpts_profile_read.argtypes = [vp, ctypes.POINTER(KernelTimes)]
@@ -299,6 +304,46 @@ class Mesh:
             _dptr(P.hist), _dptr(field.contiguous()), _dptr(f["code"]), _dptr(f["elem"]),
             _dptr(f["r"]), _dptr(f["dist"]), _PREC[precision], _dptr(wsb), wsb.numel(),
             _stream_ptr(stream)))
+
+    # -- Find and Interpolate in one call
+    def find_eval_workspace_bytes(self, n):
+        return load_library().fpts_find_eval_workspace_size(self._h, n)
+
+    def find_eval(self, pts, field, precision="fp64", out=None, u=None, ws=None, stream=None,
+                  field_nodes_1d=None):
+        """fpts_find_eval: (dict(code, elem, r, dist), u [n_fields][n])."""
+        import torch
+        L = load_library()
+        if pts.dtype != torch.float64 or not pts.is_cuda or pts.dim() != 2 or \
+                pts.shape[0] != self.dim:
+            raise FptsError("pts must be a float64 device tensor [dim][n]")
+        Nf = self.N if field_nodes_1d is None else int(field_nodes_1d)
+        if field.dim() == 2:
+            field = field.unsqueeze(0)
+        if field.dtype != torch.float64 or not field.is_cuda or \
+                tuple(field.shape[1:]) != (self.n_elem, Nf ** self.ref_dim):
+            raise FptsError("field must be float64 [n_fields][n_elem][Nf^ref_dim] on the device")
+        pts = pts.contiguous()
+        field = field.contiguous()
+        n = pts.shape[1]
+        nf = field.shape[0]
+        if out is None:
+            out = dict(code=torch.empty(n, dtype=torch.int32, device=pts.device),
+                       elem=torch.empty(n, dtype=torch.int32, device=pts.device),
+                       r=torch.empty((self.ref_dim, n), dtype=torch.float64, device=pts.device),
+                       dist=torch.empty(n, dtype=torch.float64, device=pts.device))
+        if u is None:
+            u = torch.empty((nf, n), dtype=torch.float64, device=pts.device)
+        need = self.find_eval_workspace_bytes(n)
+        if need == 0:
+            raise FptsError("too many points for one call")
+        wsb = ws if ws is not None else self.workspace(need)
+        _check(L.fpts_find_eval(self._h, n, _dptr(pts), _dptr(out["code"]), _dptr(out["elem"]),
+                                _dptr(out["r"]), _dptr(out["dist"]), _PREC[precision], nf, Nf,
+                                _dptr(field), _dptr(u), _dptr(wsb), wsb.numel(),
+                                _stream_ptr(stream)))
+        self._last_find_ws = (wsb, n)
+        return out, u
 
     # -- kernel timing (HIP events on the call's stream)
     def profile(self, enable=True):
