@@ -3,17 +3,15 @@
 //
 // Points are first counted and scattered into per-element buckets (the
 // grouping by element the paper's CPU code uses, Section 5 remark), then a
-// wavefront takes up to 64 points of ONE element, reads the element's nodal
-// values with scalar loads (once per wave, not once per point) and each lane
-// contracts them sum-factorised: N^3 + N^2 + N FMAs per field and point.
+// wavefront takes up to 64 points of ONE element, stages the element's nodal
+// values in LDS (once per wave, not once per point) and each lane contracts
+// them sum-factorised: N^3 + N^2 + N FMAs per field and point.
 // Also: the FP32 element-local node copy used by mixed-precision Newton.
 #include "fpts_internal.hpp"
 #include "gll_table.hpp"
 
 namespace fpts {
 namespace {
-
-typedef const __attribute__((address_space(4))) double cdouble;
 
 // pass 0: count points per element and write NaN for NOT_FOUND points;
 // pass 1: scatter point ids into their element's bucket.  With `primary`
@@ -79,10 +77,53 @@ struct EvalArgs {
     const double *rs;
 };
 
-template <int R, int N>
+typedef const __attribute__((address_space(4))) double cdouble;
+
+// sum over the element's nodal values u of one field times the tensor bases
+template <int R, int N, typename P>
+__device__ __forceinline__ double contract(P u, const double (&v0)[N], const double (&v1)[N],
+                                           const double (&v2)[N])
+{
+    double acc = 0.0;
+    if constexpr (R == 3) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            double B = 0.0;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                double A = 0.0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) A = fma(u[i + N * (j + N * k)], v0[i], A);
+                B = fma(A, v1[j], B);
+            }
+            acc = fma(B, v2[k], acc);
+        }
+    } else if constexpr (R == 2) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double A = 0.0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) A = fma(u[i + N * j], v0[i], A);
+            acc = fma(A, v1[j], acc);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc = fma(u[i], v0[i], acc);
+    }
+    return acc;
+}
+
+// LDS: the element's nodal values of each field are staged in LDS with
+// coalesced loads and read by every lane at the same address (broadcast);
+// otherwise they are read with scalar loads.  Staging wins when an element
+// holds few points (its values are cold, and scalar loads of them stall on
+// latency); when many tasks share an element its values stay in the scalar
+// cache and the scalar operands save the LDS reads.
+template <int R, int N, bool LDS>
 __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
 {
     constexpr int NP = (R == 3) ? N * N * N : (R == 2) ? N * N : N;
+    extern __shared__ double ldsu[];   // [NP] (LDS staging)
     const int lane = threadIdx.x;
     const int total = a.chunk_off[a.nel];
     for (int t = task_of_block(); t < total; t += gridDim.x) {
@@ -102,32 +143,15 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
         if (R >= 2) basis_v<N>(has ? rr[1] : 0.0, a.basis.z, a.basis.w, v1);
         if (R == 3) basis_v<N>(has ? rr[2] : 0.0, a.basis.z, a.basis.w, v2);
         for (int f = 0; f < a.n_fields; ++f) {
-            cdouble *u = (cdouble *)(a.field + ((size_t)f * a.nel + e) * NP);
-            double acc = 0.0;
-            if constexpr (R == 3) {
-#pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    double B = 0.0;
-#pragma unroll
-                    for (int j = 0; j < N; ++j) {
-                        double A = 0.0;
-#pragma unroll
-                        for (int i = 0; i < N; ++i) A = fma(u[i + N * (j + N * k)], v0[i], A);
-                        B = fma(A, v1[j], B);
-                    }
-                    acc = fma(B, v2[k], acc);
-                }
-            } else if constexpr (R == 2) {
-#pragma unroll
-                for (int j = 0; j < N; ++j) {
-                    double A = 0.0;
-#pragma unroll
-                    for (int i = 0; i < N; ++i) A = fma(u[i + N * j], v0[i], A);
-                    acc = fma(A, v1[j], acc);
-                }
+            const double *src = a.field + ((size_t)f * a.nel + e) * NP;
+            double acc;
+            if constexpr (LDS) {
+                __syncthreads();   // the previous field's reads come first
+                for (int j = lane; j < NP; j += 64) ldsu[j] = src[j];
+                __syncthreads();
+                acc = contract<R, N>((const double *)ldsu, v0, v1, v2);
             } else {
-#pragma unroll
-                for (int i = 0; i < N; ++i) acc = fma(u[i], v0[i], acc);
+                acc = contract<R, N>((cdouble *)src, v0, v1, v2);
             }
             if (has) a.out[(size_t)f * a.n + p] = acc;
         }
@@ -172,21 +196,27 @@ __global__ void k_near_rows(const double *nodes, const double *xc, double *rows,
 
 typedef void (*EvalFn)(EvalArgs);
 
-template <int R>
+template <int R, bool LDS>
 EvalFn pick_eval(int N)
 {
     switch (N) {
-    case 2: return k_eval<R, 2>;
-    case 3: return k_eval<R, 3>;
-    case 4: return k_eval<R, 4>;
-    case 5: return k_eval<R, 5>;
-    case 6: return k_eval<R, 6>;
-    case 7: return k_eval<R, 7>;
-    case 8: return k_eval<R, 8>;
-    case 9: return k_eval<R, 9>;
-    case 10: return k_eval<R, 10>;
+    case 2: return k_eval<R, 2, LDS>;
+    case 3: return k_eval<R, 3, LDS>;
+    case 4: return k_eval<R, 4, LDS>;
+    case 5: return k_eval<R, 5, LDS>;
+    case 6: return k_eval<R, 6, LDS>;
+    case 7: return k_eval<R, 7, LDS>;
+    case 8: return k_eval<R, 8, LDS>;
+    case 9: return k_eval<R, 9, LDS>;
+    case 10: return k_eval<R, 10, LDS>;
     default: return nullptr;
     }
+}
+
+template <bool LDS>
+EvalFn pick_eval_r(int R, int N)
+{
+    return R == 3 ? pick_eval<3, LDS>(N) : R == 2 ? pick_eval<2, LDS>(N) : pick_eval<1, LDS>(N);
 }
 
 }  // namespace
@@ -208,8 +238,9 @@ hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fie
                        const int *chunk_off, const int *task_elem, int64_t task_bound,
                        hipStream_t s, const double *rs)
 {
-    EvalFn fn = m->R == 3 ? pick_eval<3>(field_n)
-                : m->R == 2 ? pick_eval<2>(field_n) : pick_eval<1>(field_n);
+    // stage in LDS unless elements hold many points (several tasks each)
+    const bool lds = n <= (int64_t)4 * kChunk * m->nel;
+    EvalFn fn = lds ? pick_eval_r<true>(m->R, field_n) : pick_eval_r<false>(m->R, field_n);
     if (!fn) return hipErrorInvalidValue;
     EvalArgs a;
     a.r = r;
@@ -225,7 +256,10 @@ hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fie
     a.rs = rs;
     if (field_n == m->N) a.basis = m->basis;
     else gll::fill(field_n, a.basis.z, a.basis.w);
-    hipLaunchKernelGGL(fn, dim3(task_grid(task_bound, m->cus)), dim3(64), 0, s, a);
+    int npf = field_n;   // LDS: one field of one element
+    for (int k = 1; k < m->R; ++k) npf *= field_n;
+    hipLaunchKernelGGL(fn, dim3(task_grid(task_bound, m->cus)), dim3(64),
+                       lds ? sizeof(double) * npf : 0, s, a);
     return hipGetLastError();
 }
 

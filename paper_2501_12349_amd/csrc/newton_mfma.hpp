@@ -868,46 +868,57 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
             for (int k = 0; k < 4; ++k) Pt[k * 64 + lane] = pa[k];
         }
         wave_lds_sync();
-        const int ntile = (cnt + 15) >> 4;   // pair tiles of this task
-#pragma unroll 1
-        for (int pt = 0; pt < ntile; ++pt) {
-            const T av = Pt[g * 64 + 16 * pt + col];
-            T best[4];
-            int bix[4];
+        const int ntile = (cnt + 15) >> 4;   // pair tiles of this task (wave-uniform)
+        T av[4], best[4][4];
+        int bix[4][4];
+#pragma unroll
+        for (int pt = 0; pt < 4; ++pt) {
+            av[pt] = Pt[g * 64 + 16 * pt + col];
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq) {
-                best[qq] = T(__builtin_huge_valf());
-                bix[qq] = 0;
+                best[pt][qq] = T(__builtin_huge_valf());
+                bix[pt][qq] = 0;
             }
+        }
+        // node tiles outside, pair tiles inside: each B value is read once
+        // per task and scores every pair tile
 #pragma unroll 2
-            for (int nt = 0; nt < NT; ++nt) {
-                const T bv = L::B_IN_LDS
-                                 ? Bt[g * L::NPAD + 16 * nt + col]
-                                 : T(a.near[((size_t)e * 4 + g) * L::NPAD + 16 * nt + col]);
-                const v4 d = mfma16(av, bv, v4{0, 0, 0, 0});
-                const int node = 16 * nt + col;
+        for (int nt = 0; nt < NT; ++nt) {
+            const T bv = L::B_IN_LDS ? Bt[g * L::NPAD + 16 * nt + col]
+                                     : T(a.near[((size_t)e * 4 + g) * L::NPAD + 16 * nt + col]);
+            const int node = 16 * nt + col;
 #pragma unroll
-                for (int qq = 0; qq < 4; ++qq) {
-                    const bool lt = d[qq] < best[qq];
-                    bix[qq] = lt ? node : bix[qq];
-                    best[qq] = lt ? d[qq] : best[qq];
+            for (int pt = 0; pt < 4; ++pt) {
+                if (pt < ntile) {
+                    const v4 d = mfma16(av[pt], bv, v4{0, 0, 0, 0});
+#pragma unroll
+                    for (int qq = 0; qq < 4; ++qq) {
+                        const bool lt = d[qq] < best[pt][qq];
+                        bix[pt][qq] = lt ? node : bix[pt][qq];
+                        best[pt][qq] = lt ? d[qq] : best[pt][qq];
+                    }
                 }
             }
+        }
+#pragma unroll
+        for (int pt = 0; pt < 4; ++pt) {
+            if (pt >= ntile) break;
             // lexicographic (score, node) minimum over the 16 lanes of a row
 #pragma unroll
             for (int o = 1; o < 16; o <<= 1) {
 #pragma unroll
                 for (int qq = 0; qq < 4; ++qq) {
-                    const T so = __shfl_xor(best[qq], o);
-                    const int io2 = __shfl_xor(bix[qq], o);
-                    const bool take = so < best[qq] || (so == best[qq] && io2 < bix[qq]);
-                    bix[qq] = take ? io2 : bix[qq];
-                    best[qq] = take ? so : best[qq];
+                    const T so = __shfl_xor(best[pt][qq], o);
+                    const int io2 = __shfl_xor(bix[pt][qq], o);
+                    const bool take =
+                        so < best[pt][qq] || (so == best[pt][qq] && io2 < bix[pt][qq]);
+                    bix[pt][qq] = take ? io2 : bix[pt][qq];
+                    best[pt][qq] = take ? so : best[pt][qq];
                 }
             }
             // lane `col` < 4 writes the pair of its row group held in item qq = col
-            int bi = bix[0] * (col == 0) + bix[1] * (col == 1) + bix[2] * (col == 2) +
-                     bix[3] * (col == 3);
+            int bi = bix[pt][0] * (col == 0) + bix[pt][1] * (col == 1) +
+                     bix[pt][2] * (col == 2) + bix[pt][3] * (col == 3);
             const int pl = 16 * pt + (MIXED ? 4 * g + col : g + 4 * col);
             if (col < 4 && pl < cnt) {
                 const int item = items[pl];

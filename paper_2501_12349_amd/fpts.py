@@ -82,6 +82,9 @@ def load_library(path=LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch's HIP runtime is loaded first, so that the library binds to the
+    # same runtime and shares its device memory and streams
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise FptsError("libfpts.so is not built (run __graft_entry__.build())")
     L = ctypes.CDLL(path)
