@@ -121,10 +121,8 @@ int fpts_destroy(fpts_mesh *m);
  * N_L stay.  The results equal those of fpts_setup on the same nodes bit
  * for bit.  Synchronises `stream` (the map size is read back); workspace
  * sizes may grow, so query them again.  FPTS_EINVAL (null arguments, or
- * nodes whose boxes are not finite), FPTS_EUNSUPPORTED for line elements
- * (no device kernels for their boxes; the mesh is left unchanged),
- * FPTS_ENOMEM, FPTS_EDEVICE; after another error the mesh must be
- * destroyed. */
+ * nodes whose boxes are not finite), FPTS_ENOMEM, FPTS_EDEVICE; after an
+ * error the mesh must be destroyed. */
 int fpts_update_nodes(fpts_mesh *m, const double *d_nodes, void *stream);
 
 /* Bytes of device workspace fpts_find needs for n points (an upper bound

@@ -533,7 +533,6 @@ int fpts_profile_read(fpts_mesh *m, fpts_kernel_times *out)
 int fpts_update_nodes(fpts_mesh *m, const double *d_nodes, void *stream)
 {
     if (!m || !d_nodes) return FPTS_EINVAL;
-    if (m->R == 1) return FPTS_EUNSUPPORTED;   // the device setup has no line kernels
     if (sticky_error()) return FPTS_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
     const size_t nn = (size_t)m->nel * m->D * m->NP;

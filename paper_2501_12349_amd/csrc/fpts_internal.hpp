@@ -74,6 +74,36 @@ __device__ __forceinline__ int task_of_block()
     return (b % kXcd) * (G / kXcd) + b / kXcd;
 }
 
+// OBB frame of a line element (Section 4.2): J_c = Q^T for the rotation Q
+// that takes the unit centre tangent u = t/|t| to e1, by Rodrigues' formula
+// about k = u x e1 with cos = u.e1 and sin = |u x e1|; u = -e1 takes the half
+// turn about e3.  Left all zero when t = 0.  Host and device setup share it,
+// so both round alike (the device file is built without contraction).
+__host__ __device__ inline void rodrigues_frame(int D, double tx, double ty, double tz,
+                                                double *Jc)
+{
+    const double tn = sqrt(tx * tx + ty * ty + tz * tz);
+    if (!(tn > 0.0)) return;
+    const double u[3] = {tx / tn, ty / tn, tz / tn};
+    double Q[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    const double sn = sqrt(u[1] * u[1] + u[2] * u[2]), cs = u[0];
+    if (sn > 0.0) {
+        const double k[3] = {0.0, u[2] / sn, -u[1] / sn};
+        const double K[3][3] = {{0.0, -k[2], k[1]}, {k[2], 0.0, -k[0]}, {-k[1], k[0], 0.0}};
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double kk = 0.0;
+                for (int q = 0; q < 3; ++q) kk += K[i][q] * K[q][j];
+                Q[i][j] = (i == j ? 1.0 : 0.0) + sn * K[i][j] + (1.0 - cs) * kk;
+            }
+    } else if (cs < 0.0) {
+        Q[0][0] = -1.0;
+        Q[1][1] = -1.0;
+    }
+    for (int c = 0; c < D; ++c)
+        for (int q = 0; q < D; ++q) Jc[c * D + q] = Q[q][c];
+}
+
 // ctr[key]++ for every active lane, returning the lane's old value, with one
 // atomic per group of lanes that share a key: the group of the lowest pending
 // lane is peeled off with a ballot and takes a block of consecutive values.

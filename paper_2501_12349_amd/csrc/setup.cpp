@@ -320,32 +320,6 @@ bool invert(int D, const double *A, double *I)
     return true;
 }
 
-// J_c = Q^T for a line element with centre tangent t (see element_setup);
-// left all zero when t = 0.
-void rodrigues_frame(int D, double tx, double ty, double tz, double *Jc)
-{
-    const double tn = std::sqrt(tx * tx + ty * ty + tz * tz);
-    if (!(tn > 0.0)) return;
-    const double u[3] = {tx / tn, ty / tn, tz / tn};
-    double Q[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
-    const double sn = std::sqrt(u[1] * u[1] + u[2] * u[2]), cs = u[0];
-    if (sn > 0.0) {
-        const double k[3] = {0.0, u[2] / sn, -u[1] / sn};
-        const double K[3][3] = {{0.0, -k[2], k[1]}, {k[2], 0.0, -k[0]}, {-k[1], k[0], 0.0}};
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                double kk = 0.0;
-                for (int q = 0; q < 3; ++q) kk += K[i][q] * K[q][j];
-                Q[i][j] = (i == j ? 1.0 : 0.0) + sn * K[i][j] + (1.0 - cs) * kk;
-            }
-    } else if (cs < 0.0) {
-        Q[0][0] = -1.0;
-        Q[1][1] = -1.0;
-    }
-    for (int c = 0; c < D; ++c)
-        for (int q = 0; q < D; ++q) Jc[c * D + q] = Q[q][c];
-}
-
 // AABB and OBB of element e (Section 3.1.1, 3.1.2, 4.1, 4.2).
 void element_setup(fpts_mesh *m, const Tables &T, const double *x, int64_t e)
 {

@@ -122,7 +122,8 @@ __device__ void bound2_w(const BoundTables &T, const double *u, double *w, doubl
 }
 
 // Bound of one coordinate function f[NP] (LDS): the edges of a quad, the
-// faces of a hex, the whole patch of a surface quad.
+// faces of a hex, the whole patch of a surface quad, the whole curve of a
+// line element.
 __device__ void bound_fun_w(const BoundTables &T, int D, int R, const double *f, double *buf,
                             double *w, double *sc, int lane, double &lo, double &hi)
 {
@@ -160,14 +161,19 @@ __device__ void bound_fun_w(const BoundTables &T, int D, int R, const double *f,
                 hi = mx(hi, b);
             }
         }
-    } else {
+    } else if (R == 2) {
         bound2_w(T, f, w, sc, lane, a, b);
+        lo = mn(lo, a);
+        hi = mx(hi, b);
+    } else {
+        bound1_w(T, f, sc, lane, a, b);
         lo = mn(lo, a);
         hi = mx(hi, b);
     }
 }
 
-// Thin-extent rule (surfaces) and expansion by tol of the extent in total.
+// Thin-extent rule (manifolds; reference: the smallest other extent, the
+// largest for lines) and expansion by tol of the extent in total.
 __device__ void finish_d(int D, int R, double tol, double *lo, double *hi, const double *len)
 {
     double L[3];
@@ -176,10 +182,10 @@ __device__ void finish_d(int D, int R, double tol, double *lo, double *hi, const
         double P[3];
         for (int d = 0; d < D; ++d) P[d] = L[d] * len[d];
         for (int d = 0; d < D; ++d) {
-            double small = INFINITY;
+            double ref = R == 1 ? 0.0 : INFINITY;
             for (int q = 0; q < D; ++q)
-                if (q != d) small = mn(small, P[q]);
-            const double need = tol * small / len[d];
+                if (q != d) ref = R == 1 ? mx(ref, P[q]) : mn(ref, P[q]);
+            const double need = tol * ref / len[d];
             if (L[d] < need) {
                 const double c = 0.5 * (lo[d] + hi[d]);
                 lo[d] = c - 0.5 * need;
@@ -230,7 +236,7 @@ __global__ __launch_bounds__(kLanes) void k_elem_boxes(const BoundTables *Tg, co
 {
     extern __shared__ double lds[];
     const BoundTables &T = *Tg;
-    const int N = T.N, NP = (R == 3) ? N * N * N : N * N, W = 3 * D + D * D;
+    const int N = T.N, NP = (R == 3) ? N * N * N : (R == 2) ? N * N : N, W = 3 * D + D * D;
     const int lane = threadIdx.x;
     double *xe = lds;              // [D][NP]
     double *f = xe + D * NP;       // [NP]
@@ -251,6 +257,11 @@ __global__ __launch_bounds__(kLanes) void k_elem_boxes(const BoundTables *Tg, co
                 const int ii = idx % N, jj = (idx / N) % N, kk = idx / (N * N);
                 double b0 = T.v0[ii] * T.v0[jj], br = T.d0[ii] * T.v0[jj],
                        bs = T.v0[ii] * T.d0[jj], bt = 0.0;
+                if (R == 1) {
+                    b0 = T.v0[ii];
+                    br = T.d0[ii];
+                    bs = 0.0;
+                }
                 if (R == 3) {
                     bt = b0 * T.d0[kk];
                     b0 *= T.v0[kk];
@@ -281,6 +292,8 @@ __global__ __launch_bounds__(kLanes) void k_elem_boxes(const BoundTables *Tg, co
         if (R == D) {
             for (int a = 0; a < D; ++a)
                 for (int b = 0; b < D; ++b) Jc[a * D + b] = G[a][b];
+        } else if (R == 1) {
+            rodrigues_frame(D, G[0][0], G[1][0], D == 3 ? G[2][0] : 0.0, Jc);
         } else {
             const double t1[3] = {G[0][0], G[1][0], G[2][0]}, t2[3] = {G[0][1], G[1][1], G[2][1]};
             const double n[3] = {t1[1] * t2[2] - t1[2] * t2[1], t1[2] * t2[0] - t1[0] * t2[2],

@@ -76,12 +76,28 @@ def test_line_ragged_and_empty():
         _run(wl, pts)
 
 
-def test_line_update_nodes_is_unsupported():
+@pytest.mark.parametrize("D", [2, 3])
+def test_line_update_nodes_matches_fresh_setup(D):
+    """Device setup of a moved line mesh equals a fresh host setup bit for
+    bit, and both find the same results."""
     fpts = _fpts()
-    wl = W.line3d(n_elem=8, per_elem=3)
-    gm = fpts.Mesh(wl["nodes"], wl["N"], dim=3, ref_dim=1)
-    with pytest.raises(fpts.FptsError):
-        gm.update_nodes(torch.from_numpy(wl["nodes"]).cuda())
+    wl = W.line2d(level=1, per_elem=50) if D == 2 else W.line3d(n_elem=40, per_elem=50)
+    a = wl["nodes"]
+    X = np.moveaxis(a, 1, 0)
+    b = np.ascontiguousarray(a * 1.05 + 0.02 * np.sin(2.0 * X.sum(axis=0))[:, None, :])
+    moved = fpts.Mesh(a, wl["N"], dim=D, ref_dim=1)
+    moved.update_nodes(torch.from_numpy(b).cuda())
+    fresh = fpts.Mesh(b, wl["N"], dim=D, ref_dim=1)
+    for u, v in zip(moved.boxes(), fresh.boxes()):
+        assert np.array_equal(u, v), np.abs(u - v).max()
+    hu, hv = moved.hash_info(), fresh.hash_info()
+    for k in hu:
+        assert np.array_equal(np.asarray(hu[k]), np.asarray(hv[k])), k
+    pts = torch.from_numpy(np.ascontiguousarray(wl["pts"] * 1.05)).cuda()
+    ra, rb = to_np(moved.find(pts)), to_np(fresh.find(pts))
+    torch.cuda.synchronize()
+    for k in ra:
+        assert np.array_equal(ra[k], rb[k], equal_nan=True), k
 
 
 def test_line2d_full_size_sampled():
