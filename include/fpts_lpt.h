@@ -57,14 +57,15 @@ typedef struct fpts_lpt_params {
     int periodic[3];     /* per direction: 1 wrap, 0 walls that mirror */
     int hint;            /* nonzero: hinted Find.  A particle whose last code
                             was INTERIOR is first searched in its previous
-                            element from its previous r; when that ends
-                            INTERIOR at least 1e-9 inside the reference box
-                            no other element can hold the particle in its
-                            interior, so the full Find would give the same
-                            element and r, and the particle keeps it.  All
-                            other particles take the full Find.  Not part
-                            of the paper's method, which runs the full Find
-                            every step; 0 runs exactly that */
+                            element from its previous r, for at most 8
+                            Newton passes; when that converges INTERIOR at
+                            least 1e-9 inside the reference box no other
+                            element can hold the particle in its interior,
+                            so the full Find would give the same element and
+                            r, and the particle keeps it.  All other
+                            particles take the full Find.  Not part of the
+                            paper's method, which runs the full Find every
+                            step; 0 runs exactly that */
 } fpts_lpt_params;
 
 /* Bytes of device workspace fpts_lpt_step needs for n particles (the

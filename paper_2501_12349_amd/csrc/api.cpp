@@ -42,6 +42,7 @@ constexpr int kCounters = 64;   // ints: element-queue counters of the Newton pa
 constexpr int kNewtonCounters = 16;   // each Newton pass owns 16 counters from here on
 static_assert(3 * kNewtonCounters <= kCounters, "the two Newton passes need disjoint counters");
 constexpr int kStats = 16;      // unsigned long long: Newton counters per pass
+constexpr int kHintPasses = 8;  // Newton passes of the hinted search
 
 void clear_events(fpts_mesh *m)
 {
@@ -678,8 +679,12 @@ int fpts_lpt_step(fpts_mesh *m, const fpts_lpt_params *p, int64_t n, int first, 
     }
     {
         Span sp(m, 2, s);
+        // a particle that left its element walks to the face and on: a few
+        // passes tell, and the full Find takes it (kHintPasses; a warm
+        // start converges in three or four)
         NewtonIO io{sorted, elem_off, chunk_off, nullptr, d_code, d_elem, d_r, n, d_dist,
-                    counters + kNewtonCounters, stats, task_elem, w.tb_elem};
+                    counters + kNewtonCounters, stats, task_elem, w.tb_elem, nullptr, 0,
+                    keep, kHintPasses};
         chk(launch_newton(m, precision, n, d_x, io, 2, s));
         chk(launch_hint(m, 1, n, d_code, d_elem, d_r, primary, nullptr, keep, s));
     }

@@ -170,6 +170,10 @@ struct NewtonIO {
     // the other positions
     double *rs;
     int64_t rs_stride;
+    // optional: conv[item] = 1 when the step test ended the iteration, 0 when
+    // the pass limit did; max_iter > 0 replaces the mesh's pass limit
+    int *conv;
+    int max_iter;
 };
 
 }  // namespace fpts

@@ -382,9 +382,10 @@ HashView hash_view(const fpts_mesh *m)
 // Search hints (points that move a little between searches): pass 0 takes
 // the previous element of every point whose previous code was INTERIOR as
 // its only candidate and counts it per element; pass 1 marks the points
-// whose hinted search ended INTERIOR at least kSettleGuard inside the
-// reference box: no other element can hold them in its interior, so that
-// result is the one the full search gives, and they are kept.
+// whose hinted search converged (keep[p] holds the Newton convergence flag
+// on entry) INTERIOR at least kSettleGuard inside the reference box: no
+// other element can hold them in its interior, so that result is the one
+// the full search gives, and they are kept.
 __global__ __launch_bounds__(256) void k_hint(int pass, int n, int nel, int R,
                                              const int32_t *code, const int32_t *elem,
                                              const double *r, int *primary, int *elem_cnt,
@@ -398,7 +399,7 @@ __global__ __launch_bounds__(256) void k_hint(int pass, int n, int nel, int R,
         if (in) primary[p] = ok ? e : -1;
         (void)wave_inc(elem_cnt, e, ok);
     } else if (in) {
-        bool k = primary[p] >= 0 && code[p] == FPTS_INTERIOR;
+        bool k = primary[p] >= 0 && code[p] == FPTS_INTERIOR && keep[p] == 1;
         double mg = 1.0;
         for (int a = 0; a < R; ++a) mg = fmin(mg, 1.0 - fabs(r[(size_t)a * n + p]));
         keep[p] = k && mg > kSettleGuard;

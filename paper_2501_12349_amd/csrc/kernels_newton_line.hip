@@ -157,6 +157,7 @@ __global__ __launch_bounds__(64) void k_newton_line(LineArgs a)
         ++n_pairs;
         ++n_evals;
         double alpha = 1.0;
+        bool converged = false;
         for (int l = 0; l < a.max_iter; ++l) {
             ++n_passes;
             double g = 0.0, H = 0.0;
@@ -228,8 +229,12 @@ __global__ __launch_bounds__(64) void k_newton_line(LineArgs a)
                     dx[c] = dxn[c];
                 }
             }
-            if (conv) break;
+            if (conv) {
+                converged = true;
+                break;
+            }
         }
+        if (io.conv) io.conv[item] = converged ? 1 : 0;
         const bool inside = fabs(r) < 1.0 && f < a.eps_d;
         io.code[item] = inside ? FPTS_INTERIOR : FPTS_BORDER;
         if (io.elem) io.elem[item] = e;
@@ -283,7 +288,7 @@ hipError_t launch_newton_line(const fpts_mesh *m, int64_t n, const double *pts,
     a.n = (int)n;
     a.nel = (int)m->nel;
     a.io = io;
-    a.max_iter = m->p.max_iter;
+    a.max_iter = io.max_iter > 0 ? io.max_iter : m->p.max_iter;
     a.tol = m->p.newton_tol;
     a.eps_d = m->p.surf_eps_d;
     // phase C calls the start (which 1) and the iteration (which 2) apart;

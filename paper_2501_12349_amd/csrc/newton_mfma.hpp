@@ -575,8 +575,9 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
         head = min(head + nfree, cend);
     };
     // A pair is done: results out, slot free.
-    auto finish = [&]() {
+    auto finish = [&](bool converged) {
         if (leader) {
+            if (FINAL && io.conv) io.conv[item] = converged ? 1 : 0;
             if (FINAL) {
                 bool inside = true;
 #pragma unroll
@@ -683,7 +684,7 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
 #pragma unroll
                     for (int k = 0; k < R; ++k) r[k] = q[k];
                     cur.f = fmax(cur.f - pred, T(0));
-                    finish();
+                    finish(true);
                     ended = true;
                 }
             }
@@ -747,7 +748,7 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                 for (int c = 0; c < D; ++c) dx[c] = dxn[c];
                 hb_ok = false;
             }
-            if (pass >= max_iter) finish();
+            if (pass >= max_iter) finish(false);
             else if (accept && on_face(r)) state = S_WAIT;   // next pass: beta = 1
         }
     }
@@ -1087,7 +1088,7 @@ hipError_t launch_newton_kind(const fpts_mesh *m, bool mixed, int64_t n, const d
     a.n = (int)n;
     a.nel = (int)m->nel;
     a.io = io;
-    a.max_iter = m->p.max_iter;
+    a.max_iter = io.max_iter > 0 ? io.max_iter : m->p.max_iter;
     a.tol = m->p.newton_tol;
     a.eps_d = m->p.surf_eps_d;
     a.max_iter32 = m->p.mixed_max_iter;
