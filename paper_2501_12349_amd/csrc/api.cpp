@@ -109,15 +109,14 @@ FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
     w.scan_blocks = scan_tmp_blocks(std::max<int64_t>(std::max<int64_t>(n, m->nel), ncell));
     const size_t I = sizeof(int);
     w.cell_cnt = c.take(I * ncell);
-    w.cell_fill = c.take(I * ncell);
     w.cell_poff = c.take(I * (ncell + 1));
     w.cell_choff = c.take(I * (ncell + 1));
     w.cellpt = c.take(I * n);
     w.pbin = c.take(I * n);
     w.ncand = c.take(I * n);
     w.primary = c.take(I * n);
+    w.rank = c.take(I * n);
     w.elem_cnt = c.take(I * m->nel);
-    w.elem_fill = c.take(I * m->nel);
     w.elem_off = c.take(I * (m->nel + 1));
     w.chunk_off = c.take(I * (m->nel + 1));
     w.sorted = c.take(I * n);
@@ -151,7 +150,7 @@ EvalWs eval_ws_layout(const fpts_mesh *m, int64_t n)
     Cursor c;
     w.elem_cnt = c.take(sizeof(int) * m->nel);
     w.elem_off = c.take(sizeof(int) * (m->nel + 1));
-    w.elem_fill = c.take(sizeof(int) * m->nel);
+    w.rank = c.take(sizeof(int) * std::max<int64_t>(n, 1));
     w.chunk_off = c.take(sizeof(int) * (m->nel + 1));
     w.scan_tmp = c.take(sizeof(int) * scan_tmp_blocks(m->nel));
     w.sorted = c.take(sizeof(int) * std::max<int64_t>(n, 1));
@@ -191,11 +190,11 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     if (w.cap2 > INT32_MAX || ws_bytes < w.total) return FPTS_EINVAL;
     if (sticky_error()) return FPTS_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
-    int *cell_cnt = at<int>(d_ws, w.cell_cnt), *cell_fill = at<int>(d_ws, w.cell_fill);
+    int *cell_cnt = at<int>(d_ws, w.cell_cnt), *rank = at<int>(d_ws, w.rank);
     int *cell_poff = at<int>(d_ws, w.cell_poff), *cell_choff = at<int>(d_ws, w.cell_choff);
     int *cellpt = at<int>(d_ws, w.cellpt), *pbin = at<int>(d_ws, w.pbin);
     int *ncand = at<int>(d_ws, w.ncand), *primary = at<int>(d_ws, w.primary);
-    int *elem_cnt = at<int>(d_ws, w.elem_cnt), *elem_fill = at<int>(d_ws, w.elem_fill);
+    int *elem_cnt = at<int>(d_ws, w.elem_cnt);
     int *elem_off = at<int>(d_ws, w.elem_off), *chunk_off = at<int>(d_ws, w.chunk_off);
     int *sorted = at<int>(d_ws, w.sorted), *off2 = at<int>(d_ws, w.off2);
     int *elem_cnt2 = at<int>(d_ws, w.elem_cnt2), *elem_fill2 = at<int>(d_ws, w.elem_fill2);
@@ -216,27 +215,25 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     {   // phases A and B: bin points by cell, candidates and primaries
         Span sp(m, 0, s);
         chk(launch_fill_i32(cell_cnt, ncell, 0, s));
-        chk(launch_fill_i32(cell_fill, ncell, 0, s));
         chk(launch_fill_i32(elem_cnt, nel, 0, s));
-        chk(launch_fill_i32(elem_fill, nel, 0, s));
         chk(launch_fill_i32(elem_cnt2, nel, 0, s));
         chk(launch_fill_i32(elem_fill2, nel, 0, s));
         chk(launch_fill_i32(counters, kCounters, 0, s));
         chk(launch_fill_i32(reinterpret_cast<int *>(stats), 4 * kStats, 0, s));
-        chk(launch_cell_bin(m, 0, n, d_pts, keep, cellpt, cell_cnt, nullptr, nullptr, nullptr,
+        chk(launch_cell_bin(m, 0, n, d_pts, keep, cellpt, cell_cnt, nullptr, rank, nullptr,
                             ncand, primary, d_code, d_elem, d_r, d_dist, s));
         chk(launch_exclusive_scan(cell_cnt, cell_poff, ncell, 1, tmp, tb, s));
         chk(launch_exclusive_scan(cell_cnt, cell_choff, ncell, kChunk, tmp, tb, s));
         chk(launch_task_map(cell_choff, ncell, task_cell, s));
-        chk(launch_cell_bin(m, 1, n, d_pts, keep, cellpt, nullptr, cell_poff, cell_fill, pbin,
+        chk(launch_cell_bin(m, 1, n, d_pts, keep, cellpt, nullptr, cell_poff, rank, pbin,
                             nullptr, nullptr, d_code, d_elem, d_r, d_dist, s));
         chk(launch_locate_cells(m, n, d_pts, pbin, cell_poff, cell_choff, ncell, task_cell,
-                                w.tb_cell, ncand, primary, elem_cnt, d_code, d_elem, d_r, d_dist,
-                                s));
+                                w.tb_cell, ncand, primary, elem_cnt, rank, d_code, d_elem, d_r,
+                                d_dist, s));
         chk(launch_exclusive_scan(elem_cnt, elem_off, nel, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt, chunk_off, nel, kChunk, tmp, tb, s));
         chk(launch_task_map(chunk_off, nel, task_elem, s));
-        chk(launch_primary_scatter(n, nel, primary, elem_off, elem_fill, sorted, s));
+        chk(launch_primary_scatter(n, nel, primary, elem_off, rank, sorted, s));
     }
     {   // phase C: Newton on the primary candidates, results straight to the outputs
         NewtonIO io{sorted, elem_off, chunk_off, nullptr, d_code, d_elem, d_r, n, d_dist,
@@ -435,7 +432,7 @@ int fpts_eval_order(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_
     hipStream_t s = (hipStream_t)stream;
     int *elem_cnt = at<int>(d_ws, w.elem_cnt);
     int *elem_off = at<int>(d_ws, w.elem_off);
-    int *elem_fill = at<int>(d_ws, w.elem_fill);
+    int *rank = at<int>(d_ws, w.rank);
     int *chunk_off = at<int>(d_ws, w.chunk_off);
     int *tmp = at<int>(d_ws, w.scan_tmp);
     int *sorted = at<int>(d_ws, w.sorted);
@@ -448,16 +445,14 @@ int fpts_eval_order(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_
     {
         Span sp(m, 4, s);
         chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
-        chk(launch_fill_i32(elem_fill, m->nel, 0, s));
         chk(launch_eval_bin(m, 0, n, d_code, d_elem, nullptr, nullptr, n_fields, d_out, elem_cnt,
-                            nullptr, nullptr,
-                            nullptr, s));
+                            nullptr, rank, nullptr, s));
         chk(launch_exclusive_scan(elem_cnt, elem_off, m->nel, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt, chunk_off, m->nel, kChunk, tmp, tb, s));
         chk(launch_task_map(chunk_off, m->nel, task_elem, s));
         chk(launch_eval_bin(m, 1, n, d_code, d_elem, nullptr, nullptr, n_fields, d_out, nullptr,
                             elem_off,
-                            elem_fill, sorted, s));
+                            rank, sorted, s));
     }
     {
         Span sp(m, 5, s);
@@ -657,7 +652,7 @@ int fpts_lpt_step(fpts_mesh *m, const fpts_lpt_params *p, int64_t n, int first, 
     // skips the particles that this settled.
     const FindWs w = find_ws_layout(m, n);
     int *primary = at<int>(sub, w.primary), *elem_cnt = at<int>(sub, w.elem_cnt);
-    int *elem_fill = at<int>(sub, w.elem_fill), *elem_off = at<int>(sub, w.elem_off);
+    int *rank = at<int>(sub, w.rank), *elem_off = at<int>(sub, w.elem_off);
     int *chunk_off = at<int>(sub, w.chunk_off), *sorted = at<int>(sub, w.sorted);
     int *task_elem = at<int>(sub, w.task_elem), *tmp = at<int>(sub, w.scan_tmp);
     int *counters = at<int>(sub, w.counters);
@@ -668,14 +663,13 @@ int fpts_lpt_step(fpts_mesh *m, const fpts_lpt_params *p, int64_t n, int first, 
     {
         Span sp(m, 0, s);
         chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
-        chk(launch_fill_i32(elem_fill, m->nel, 0, s));
         chk(launch_fill_i32(counters, kCounters, 0, s));
         chk(launch_fill_i32(reinterpret_cast<int *>(stats), 4 * kStats, 0, s));
-        chk(launch_hint(m, 0, n, d_code, d_elem, d_r, primary, elem_cnt, nullptr, s));
+        chk(launch_hint(m, 0, n, d_code, d_elem, d_r, primary, elem_cnt, rank, nullptr, s));
         chk(launch_exclusive_scan(elem_cnt, elem_off, m->nel, 1, tmp, w.scan_blocks, s));
         chk(launch_exclusive_scan(elem_cnt, chunk_off, m->nel, kChunk, tmp, w.scan_blocks, s));
         chk(launch_task_map(chunk_off, m->nel, task_elem, s));
-        chk(launch_primary_scatter(n, m->nel, primary, elem_off, elem_fill, sorted, s));
+        chk(launch_primary_scatter(n, m->nel, primary, elem_off, rank, sorted, s));
     }
     {
         Span sp(m, 2, s);
@@ -686,7 +680,7 @@ int fpts_lpt_step(fpts_mesh *m, const fpts_lpt_params *p, int64_t n, int first, 
                     counters + kNewtonCounters, stats, task_elem, w.tb_elem, nullptr, 0,
                     keep, kHintPasses};
         chk(launch_newton(m, precision, n, d_x, io, 2, s));
-        chk(launch_hint(m, 1, n, d_code, d_elem, d_r, primary, nullptr, keep, s));
+        chk(launch_hint(m, 1, n, d_code, d_elem, d_r, primary, nullptr, nullptr, keep, s));
     }
     if (e != hipSuccess) return FPTS_EDEVICE;
     return find_impl(m, n, d_x, d_code, d_elem, d_r, d_dist, precision, sub, sub_bytes, stream,
@@ -729,7 +723,7 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
     const int *primary = at<int>(d_ws, w.primary), *sorted = at<int>(d_ws, w.sorted);
     const int *elem_off = at<int>(d_ws, w.elem_off), *chunk_off = at<int>(d_ws, w.chunk_off);
     const int *task_elem = at<int>(d_ws, w.task_elem);
-    int *elem_cnt = at<int>(ews, v.elem_cnt), *elem_fill = at<int>(ews, v.elem_fill);
+    int *elem_cnt = at<int>(ews, v.elem_cnt), *erank = at<int>(ews, v.rank);
     int *eoff = at<int>(ews, v.elem_off), *choff = at<int>(ews, v.chunk_off);
     int *tmp = at<int>(ews, v.scan_tmp), *esorted = at<int>(ews, v.sorted);
     int *etask = at<int>(ews, v.task_elem);
@@ -750,14 +744,13 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
         // plain interpolation path restricted to them
         Span sp(m, 4, s);
         chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
-        chk(launch_fill_i32(elem_fill, m->nel, 0, s));
         chk(launch_eval_bin(m, 0, n, d_code, d_elem, d_r, primary, n_fields, d_out, elem_cnt,
-                            nullptr, nullptr, nullptr, s));
+                            nullptr, erank, nullptr, s));
         chk(launch_exclusive_scan(elem_cnt, eoff, m->nel, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt, choff, m->nel, kChunk, tmp, tb, s));
         chk(launch_task_map(choff, m->nel, etask, s));
         chk(launch_eval_bin(m, 1, n, d_code, d_elem, d_r, primary, n_fields, d_out, nullptr,
-                            eoff, elem_fill, esorted, s));
+                            eoff, erank, esorted, s));
     }
     {
         Span sp(m, 5, s);

@@ -134,8 +134,8 @@ __device__ __forceinline__ int wave_inc(int *ctr, int key, bool active)
 }
 
 struct FindWs {
-    size_t cell_cnt, cell_fill, cell_poff, cell_choff, cellpt, pbin, ncand, primary,
-        elem_cnt, elem_fill, elem_off, chunk_off, sorted, off2, elem_cnt2, elem_fill2,
+    size_t cell_cnt, cell_poff, cell_choff, cellpt, pbin, ncand, primary, rank,
+        elem_cnt, elem_off, chunk_off, sorted, off2, elem_cnt2, elem_fill2,
         elem_off2, chunk_off2, slot_pt, slot_elem, sorted2, res_r, res_dist, res_code,
         task_cell, task_elem, task_elem2, scan_tmp, counters, stats, total;
     int64_t cap2;           // capacity for second-pass (point, candidate) pairs
@@ -145,7 +145,7 @@ struct FindWs {
 };
 
 struct EvalWs {
-    size_t elem_cnt, elem_off, elem_fill, chunk_off, scan_tmp, sorted, task_elem, total;
+    size_t elem_cnt, elem_off, rank, chunk_off, scan_tmp, sorted, task_elem, total;
     int64_t tb_elem;
 };
 
@@ -249,29 +249,33 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int64_t n, int ceil_di
                                  int *tmp, int64_t tmp_blocks, hipStream_t s);
 int64_t scan_tmp_blocks(int64_t n);
 // phase A: pass 0 counts points per cell (and writes NOT_FOUND for points
-// outside the map), pass 1 scatters point ids into cell buckets; points with
-// keep[p] != 0 (keep may be null) are left out and keep their results
+// outside the map), keeping each point's rank among its cell's points; pass 1
+// puts point ids into cell buckets at those ranks; points with keep[p] != 0
+// (keep may be null) are left out and keep their results
 hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double *pts,
                            const int *keep, int *cellpt, int *cell_cnt, const int *cell_poff,
-                           int *cell_fill, int *pbin, int *ncand, int *primary, int32_t *code,
+                           int *rank, int *pbin, int *ncand, int *primary, int32_t *code,
                            int32_t *elem, double *r, double *dist, hipStream_t s);
 // search hints: pass 0 makes the previous element of each previously
 // INTERIOR point its primary (counted per element); pass 1 sets keep[p] for
 // points the hinted search settled
 hipError_t launch_hint(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
                        const int32_t *elem, const double *r, int *primary, int *elem_cnt,
-                       int *keep, hipStream_t s);
+                       int *rank, int *keep, hipStream_t s);
 // phase B: candidates of each point from its cell's list (one wave per 64
 // points of one cell), primary = deepest inside its OBB
 // task -> unit map of a task grid over nunit units with task offsets chunk_off
 hipError_t launch_task_map(const int *chunk_off, int64_t nunit, int *task_unit, hipStream_t s);
+// (counts primaries per element and keeps each point's rank in rank[p])
 hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
                                const int *pbin, const int *cell_poff, const int *cell_choff,
                                int64_t ncell, const int *task_cell, int64_t task_bound,
-                               int *ncand, int *primary, int *elem_cnt, int32_t *code,
-                               int32_t *elem, double *r, double *dist, hipStream_t s);
+                               int *ncand, int *primary, int *elem_cnt, int *rank,
+                               int32_t *code, int32_t *elem, double *r, double *dist,
+                               hipStream_t s);
+// sorted[elem_off[primary[p]] + rank[p]] = p
 hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int *primary,
-                                  const int *elem_off, int *elem_fill, int *sorted,
+                                  const int *elem_off, const int *rank, int *sorted,
                                   hipStream_t s);
 // phase D: pass 0 counts the other candidates of unsettled points, pass 1
 // writes their (point, element) slots into element buckets
@@ -289,10 +293,11 @@ hipError_t launch_newton(const fpts_mesh *m, int precision, int64_t n, const dou
                          const NewtonIO &io, int which, hipStream_t s);
 // interpolation binning; with `primary` (fused find + interpolate) the
 // points their primary result settled are left out (r is read for that)
+// (pass 0 keeps each point's rank in its element's bucket, pass 1 uses it)
 hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
                            const int32_t *elem, const double *r, const int *primary,
                            int n_fields, double *out, int *elem_cnt, const int *elem_off,
-                           int *elem_fill, int *sorted, hipStream_t s);
+                           int *rank, int *sorted, hipStream_t s);
 // field_n: GLL nodes per direction of the field (its own order, 2..kMaxN)
 hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fields, int field_n,
                        const double *field, double *out, const int *sorted,

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(256) void k_eval_bin(int pass, int n, int nel, int 
                                                  const int32_t *code, const int32_t *elem,
                                                  const double *r, const int *primary,
                                                  int n_fields, double *out, int *elem_cnt,
-                                                 const int *elem_off, int *elem_fill,
+                                                 const int *elem_off, int *rank,
                                                  int *sorted)
 {
     // no early exit: wave_inc needs every lane
@@ -36,12 +36,12 @@ __global__ __launch_bounds__(256) void k_eval_bin(int pass, int n, int nel, int 
         done = mg > kSettleGuard;
     }
     if (pass == 0) {
-        (void)wave_inc(elem_cnt, e, found && !done);
+        const int k = wave_inc(elem_cnt, e, found && !done);
+        if (found && !done) rank[p] = k;
         if (in && !found)
             for (int f = 0; f < n_fields; ++f) out[(size_t)f * n + p] = __builtin_nan("");
-    } else {
-        const int k = wave_inc(elem_fill, e, found && !done);
-        if (found && !done) sorted[elem_off[e] + k] = p;
+    } else if (found && !done) {
+        sorted[elem_off[e] + rank[p]] = p;
     }
 }
 
@@ -224,12 +224,12 @@ EvalFn pick_eval_r(int R, int N)
 hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
                            const int32_t *elem, const double *r, const int *primary,
                            int n_fields, double *out, int *elem_cnt, const int *elem_off,
-                           int *elem_fill, int *sorted, hipStream_t s)
+                           int *rank, int *sorted, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_eval_bin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pass,
                        (int)n, (int)m->nel, m->R, code, elem, r, primary, n_fields, out,
-                       elem_cnt, elem_off, elem_fill, sorted);
+                       elem_cnt, elem_off, rank, sorted);
     return hipGetLastError();
 }
 

@@ -161,7 +161,7 @@ template <int D>
 __global__ __launch_bounds__(256) void k_cell_bin(HashView h, int pass, int n, int R,
                                                  const double *pts, const int *keep,
                                                  int *cellpt, int *cell_cnt,
-                                                 const int *cell_poff, int *cell_fill,
+                                                 const int *cell_poff, int *rank,
                                                  int *pbin, int *ncand, int *primary,
                                                  int32_t *code, int32_t *elem, double *r,
                                                  double *dist)
@@ -186,11 +186,11 @@ __global__ __launch_bounds__(256) void k_cell_bin(HashView h, int pass, int n, i
             primary[p] = -1;
             if (c < 0 && !kept) write_not_found(p, n, R, code, elem, r, dist);
         }
-        (void)wave_inc(cell_cnt, c, c >= 0);
+        const int k = wave_inc(cell_cnt, c, c >= 0);
+        if (c >= 0) rank[p] = k;
     } else {
         const int c = in ? cellpt[p] : -1;
-        const int k = wave_inc(cell_fill, c, c >= 0);
-        if (c >= 0) pbin[cell_poff[c] + k] = p;
+        if (c >= 0) pbin[cell_poff[c] + rank[p]] = p;
     }
 }
 
@@ -213,8 +213,9 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
                                                     const int *pbin, const int *cell_poff,
                                                     const int *cell_choff, int ncell,
                                                     const int *task_cell, int *ncand,
-                                                    int *primary, int *elem_cnt, int32_t *code,
-                                                    int32_t *elem, double *r, double *dist)
+                                                    int *primary, int *elem_cnt, int *rank,
+                                                    int32_t *code, int32_t *elem, double *r,
+                                                    double *dist)
 {
     const int lane = threadIdx.x;
     const int total = cell_choff[ncell];
@@ -248,19 +249,18 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
             primary[p] = prim;
             if (prim < 0) write_not_found(p, n, R, code, elem, r, dist);
         }
-        (void)wave_inc(elem_cnt, prim, has && prim >= 0);
+        const int k = wave_inc(elem_cnt, prim, has && prim >= 0);
+        if (has && prim >= 0) rank[p] = k;
     }
 }
 
 __global__ __launch_bounds__(256) void k_primary_scatter(int n, int nel, const int *primary,
-                                                        const int *elem_off, int *elem_fill,
+                                                        const int *elem_off, const int *rank,
                                                         int *sorted)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int e = p < n ? primary[p] : -1;
-    const bool ok = e >= 0 && e < nel;
-    const int k = wave_inc(elem_fill, e, ok);
-    if (ok) sorted[elem_off[e] + k] = p;
+    if (e >= 0 && e < nel) sorted[elem_off[e] + rank[p]] = p;
 }
 
 // A primary result settles the point when it is INTERIOR at least `guard`
@@ -389,7 +389,7 @@ HashView hash_view(const fpts_mesh *m)
 __global__ __launch_bounds__(256) void k_hint(int pass, int n, int nel, int R,
                                              const int32_t *code, const int32_t *elem,
                                              const double *r, int *primary, int *elem_cnt,
-                                             int *keep)
+                                             int *rank, int *keep)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = p < n;
@@ -397,7 +397,8 @@ __global__ __launch_bounds__(256) void k_hint(int pass, int n, int nel, int R,
         const int e = in && code[p] == FPTS_INTERIOR ? elem[p] : -1;
         const bool ok = e >= 0 && e < nel;
         if (in) primary[p] = ok ? e : -1;
-        (void)wave_inc(elem_cnt, e, ok);
+        const int k = wave_inc(elem_cnt, e, ok);
+        if (ok) rank[p] = k;
     } else if (in) {
         bool k = primary[p] >= 0 && code[p] == FPTS_INTERIOR && keep[p] == 1;
         double mg = 1.0;
@@ -437,7 +438,7 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int64_t n, int ceil_di
 
 hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double *pts,
                            const int *keep, int *cellpt, int *cell_cnt, const int *cell_poff,
-                           int *cell_fill, int *pbin, int *ncand, int *primary, int32_t *code,
+                           int *rank, int *pbin, int *ncand, int *primary, int32_t *code,
                            int32_t *elem, double *r, double *dist, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
@@ -445,8 +446,8 @@ hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double
     const int grid = grid_for(n, 256);
     auto k = m->D == 2 ? k_cell_bin<2> : k_cell_bin<3>;
     hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, h, pass, (int)n, m->R, pts, keep,
-                       cellpt, cell_cnt, cell_poff, cell_fill, pbin, ncand, primary, code, elem,
-                       r, dist);
+                       cellpt, cell_cnt, cell_poff, rank, pbin, ncand, primary, code, elem, r,
+                       dist);
     return hipGetLastError();
 }
 
@@ -461,25 +462,26 @@ hipError_t launch_task_map(const int *chunk_off, int64_t nunit, int *task_unit, 
 hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
                                const int *pbin, const int *cell_poff, const int *cell_choff,
                                int64_t ncell, const int *task_cell, int64_t task_bound,
-                               int *ncand, int *primary, int *elem_cnt, int32_t *code,
-                               int32_t *elem, double *r, double *dist, hipStream_t s)
+                               int *ncand, int *primary, int *elem_cnt, int *rank,
+                               int32_t *code, int32_t *elem, double *r, double *dist,
+                               hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     HashView h = hash_view(m);
     auto k = m->D == 2 ? k_locate_cells<2> : k_locate_cells<3>;
     hipLaunchKernelGGL(k, dim3(task_grid(task_bound, m->cus)), dim3(64), 0, s, h, (int)n, m->R,
                        pts, pbin, cell_poff, cell_choff, (int)ncell, task_cell, ncand, primary,
-                       elem_cnt, code, elem, r, dist);
+                       elem_cnt, rank, code, elem, r, dist);
     return hipGetLastError();
 }
 
 hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int *primary,
-                                  const int *elem_off, int *elem_fill, int *sorted,
+                                  const int *elem_off, const int *rank, int *sorted,
                                   hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_primary_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, (int)n,
-                       (int)nel, primary, elem_off, elem_fill, sorted);
+                       (int)nel, primary, elem_off, rank, sorted);
     return hipGetLastError();
 }
 
@@ -516,11 +518,11 @@ namespace fpts {
 
 hipError_t launch_hint(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
                        const int32_t *elem, const double *r, int *primary, int *elem_cnt,
-                       int *keep, hipStream_t s)
+                       int *rank, int *keep, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_hint, dim3(grid_for(n, 256)), dim3(256), 0, s, pass, (int)n,
-                       (int)m->nel, m->R, code, elem, r, primary, elem_cnt, keep);
+                       (int)m->nel, m->R, code, elem, r, primary, elem_cnt, rank, keep);
     return hipGetLastError();
 }
 
