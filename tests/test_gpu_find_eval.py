@@ -64,3 +64,40 @@ def test_field_of_another_order():
 
 def test_hex48_full_size():
     _same(W.hex48(), "fp64")
+
+
+def test_ragged_sizes_and_arguments():
+    """Sizes around the task size, n = 0, and argument errors."""
+    from paper_2501_12349_amd import fpts
+    wl = W.hex16(n_in=3000, n_out=100)
+    gm = fpts.Mesh(wl["nodes"], wl["N"])
+    f = torch.from_numpy(wl["fields"]).cuda()
+    allp = torch.from_numpy(np.ascontiguousarray(wl["pts"])).cuda()
+    for n in (1, 63, 64, 65, 257):
+        pts = allp[:, :n].contiguous()
+        a = gm.find(pts)
+        ua = gm.eval(a, f)
+        b, ub = gm.find_eval(pts, f)
+        torch.cuda.synchronize()
+        for k in a:
+            assert torch.equal(a[k], b[k]), (n, k)
+        assert torch.equal(torch.nan_to_num(ua), torch.nan_to_num(ub)), n
+    empty = torch.zeros((3, 0), dtype=torch.float64, device="cuda")
+    b, ub = gm.find_eval(empty, f)
+    torch.cuda.synchronize()
+    assert ub.shape == (1, 0)
+    L = fpts.load_library()
+    assert L.fpts_find_eval_workspace_size(None, 10) == 0
+    ws = torch.empty(256, dtype=torch.uint8, device="cuda")
+    out = {k: v for k, v in gm.find(allp[:, :10].contiguous()).items()}
+    u = torch.empty((1, 10), dtype=torch.float64, device="cuda")
+    with pytest.raises(fpts.FptsError):      # workspace too small
+        gm.find_eval(allp[:, :10].contiguous(), f, out=out, u=u, ws=ws)
+    with pytest.raises(fpts.FptsError):      # field order out of range
+        gm.find_eval(allp[:, :10].contiguous(),
+                     torch.zeros((1, gm.n_elem, 11 ** 3), dtype=torch.float64, device="cuda"),
+                     field_nodes_1d=11)
+    st = L.fpts_find_eval(gm._h, 10, None, None, None, None, None, 0, 1, wl["N"], None, None,
+                          None, 0, None)
+    assert st == -1       # null pointers
+    torch.cuda.synchronize()
