@@ -5,9 +5,10 @@
  * queued by fpts_server_submit and served by a worker thread: requests are
  * admitted in arrival order while their device workspace fits in the
  * server's memory budget and a stream is free; requests for the same mesh
- * that are admitted together are concatenated into one batch (one fpts_find
- * and one fpts_eval launch set), and batches on different streams overlap on
- * the device.  Requests that arrive while others run are admitted as soon as
+ * that are admitted together are concatenated into one batch (one
+ * fpts_find_eval call, or fpts_find for a mesh without a field), and batches
+ * on different streams overlap on the device.  Requests that arrive while
+ * others run are admitted as soon as
  * a stream and memory free up (continuous batching).  Per-point results do
  * not depend on the batch a point travels in: each request's outputs are
  * bit-identical alone and in the mix.

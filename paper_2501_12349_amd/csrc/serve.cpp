@@ -122,14 +122,20 @@ double now_us(const fpts_server *s)
         .count();
 }
 
+// Workspace of one batch: Find and Interpolate in one call when the mesh has
+// a field, Find alone otherwise.
+size_t batch_ws(const MeshEntry &me, int64_t n)
+{
+    return me.n_fields > 0 ? fpts_find_eval_workspace_size(me.m, n)
+                           : fpts_find_workspace_size(me.m, n);
+}
+
 // Device bytes one batch of `nreq` requests with `ntot` points needs:
-// workspace (find, then eval reusing it) plus, when concatenated, staging
-// copies of inputs and outputs.
+// workspace plus, when concatenated, staging copies of inputs and outputs.
 size_t batch_bytes(const fpts_server *s, int mesh, int64_t ntot, size_t nreq)
 {
     const MeshEntry &me = s->meshes[mesh];
-    size_t ws = std::max(fpts_find_workspace_size(me.m, ntot),
-                         fpts_eval_workspace_size(me.m, ntot));
+    size_t ws = batch_ws(me, ntot);
     if (ws == 0) return (size_t)-1;
     size_t b = up(ws);
     if (nreq > 1) {
@@ -153,7 +159,7 @@ bool launch(fpts_server *s, Batch &b)
     int32_t *code, *elem;
     double *r, *dist, *out;
     char *ws;
-    size_t wsb = std::max(fpts_find_workspace_size(me.m, n), fpts_eval_workspace_size(me.m, n));
+    size_t wsb = batch_ws(me, n);
     bool ok = true;
     auto cp = [&](void *dst, const void *src, size_t bytes) {
         if (bytes && hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
@@ -189,10 +195,14 @@ bool launch(fpts_server *s, Batch &b)
         pts = pts_b;
     }
     if (!ok) return false;
-    if (fpts_find(me.m, n, pts, code, elem, r, dist, r0.precision, ws, wsb, st) != FPTS_OK)
+    if (nf > 0) {
+        if (fpts_find_eval(me.m, n, pts, code, elem, r, dist, r0.precision, nf, me.m->N, me.field,
+                           out, ws, wsb, st) != FPTS_OK)
+            return false;
+    } else if (fpts_find(me.m, n, pts, code, elem, r, dist, r0.precision, ws, wsb, st) !=
+               FPTS_OK) {
         return false;
-    if (nf > 0 && fpts_eval(me.m, n, code, elem, r, nf, me.field, out, ws, wsb, st) != FPTS_OK)
-        return false;
+    }
     if (b.reqs.size() > 1) {
         for (int64_t id : b.reqs) {
             const Req &q = s->reqs[id];
