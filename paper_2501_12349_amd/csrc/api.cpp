@@ -116,6 +116,7 @@ FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
     w.ncand = c.take(I * n);
     w.primary = c.take(I * n);
     w.rank = c.take(I * n);
+    w.bin_prim = c.take(I * n);
     w.elem_cnt = c.take(I * m->nel);
     w.elem_off = c.take(I * (m->nel + 1));
     w.chunk_off = c.take(I * (m->nel + 1));
@@ -191,6 +192,7 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     if (sticky_error()) return FPTS_EDEVICE;
     hipStream_t s = (hipStream_t)stream;
     int *cell_cnt = at<int>(d_ws, w.cell_cnt), *rank = at<int>(d_ws, w.rank);
+    int *bin_prim = at<int>(d_ws, w.bin_prim);
     int *cell_poff = at<int>(d_ws, w.cell_poff), *cell_choff = at<int>(d_ws, w.cell_choff);
     int *cellpt = at<int>(d_ws, w.cellpt), *pbin = at<int>(d_ws, w.pbin);
     int *ncand = at<int>(d_ws, w.ncand), *primary = at<int>(d_ws, w.primary);
@@ -228,12 +230,14 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         chk(launch_cell_bin(m, 1, n, d_pts, keep, cellpt, nullptr, cell_poff, rank, pbin,
                             nullptr, nullptr, d_code, d_elem, d_r, d_dist, s));
         chk(launch_locate_cells(m, n, d_pts, pbin, cell_poff, cell_choff, ncell, task_cell,
-                                w.tb_cell, ncand, primary, elem_cnt, rank, d_code, d_elem, d_r,
-                                d_dist, s));
+                                w.tb_cell, ncand, primary, elem_cnt, rank, bin_prim, d_code,
+                                d_elem, d_r, d_dist, s));
         chk(launch_exclusive_scan(elem_cnt, elem_off, nel, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt, chunk_off, nel, kChunk, tmp, tb, s));
         chk(launch_task_map(chunk_off, nel, task_elem, s));
-        chk(launch_primary_scatter(n, nel, primary, elem_off, rank, sorted, s));
+        // the binned points number cell_poff[ncell]
+        chk(launch_primary_scatter_bins(n, cell_poff + ncell, pbin, bin_prim, rank, elem_off,
+                                        sorted, s));
     }
     {   // phase C: Newton on the primary candidates, results straight to the outputs
         NewtonIO io{sorted, elem_off, chunk_off, nullptr, d_code, d_elem, d_r, n, d_dist,

@@ -134,7 +134,7 @@ __device__ __forceinline__ int wave_inc(int *ctr, int key, bool active)
 }
 
 struct FindWs {
-    size_t cell_cnt, cell_poff, cell_choff, cellpt, pbin, ncand, primary, rank,
+    size_t cell_cnt, cell_poff, cell_choff, cellpt, pbin, ncand, primary, rank, bin_prim,
         elem_cnt, elem_off, chunk_off, sorted, off2, elem_cnt2, elem_fill2,
         elem_off2, chunk_off2, slot_pt, slot_elem, sorted2, res_r, res_dist, res_code,
         task_cell, task_elem, task_elem2, scan_tmp, counters, stats, total;
@@ -266,13 +266,18 @@ hipError_t launch_hint(const fpts_mesh *m, int pass, int64_t n, const int32_t *c
 // points of one cell), primary = deepest inside its OBB
 // task -> unit map of a task grid over nunit units with task offsets chunk_off
 hipError_t launch_task_map(const int *chunk_off, int64_t nunit, int *task_unit, hipStream_t s);
-// (counts primaries per element and keeps each point's rank in rank[p])
+// (counts primaries per element; in bin order, bin_prim[i] and rank[i] are
+// the primary of the point at bin position i and its rank in that bucket)
 hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
                                const int *pbin, const int *cell_poff, const int *cell_choff,
                                int64_t ncell, const int *task_cell, int64_t task_bound,
                                int *ncand, int *primary, int *elem_cnt, int *rank,
-                               int32_t *code, int32_t *elem, double *r, double *dist,
-                               hipStream_t s);
+                               int *bin_prim, int32_t *code, int32_t *elem, double *r,
+                               double *dist, hipStream_t s);
+// sorted[elem_off[bin_prim[i]] + rank[i]] = pbin[i] for i < *nbinned
+hipError_t launch_primary_scatter_bins(int64_t n, const int *nbinned, const int *pbin,
+                                       const int *bin_prim, const int *rank,
+                                       const int *elem_off, int *sorted, hipStream_t s);
 // sorted[elem_off[primary[p]] + rank[p]] = p
 hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int *primary,
                                   const int *elem_off, const int *rank, int *sorted,

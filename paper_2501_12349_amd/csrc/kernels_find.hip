@@ -214,8 +214,8 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
                                                     const int *cell_choff, int ncell,
                                                     const int *task_cell, int *ncand,
                                                     int *primary, int *elem_cnt, int *rank,
-                                                    int32_t *code, int32_t *elem, double *r,
-                                                    double *dist)
+                                                    int *bin_prim, int32_t *code, int32_t *elem,
+                                                    double *r, double *dist)
 {
     const int lane = threadIdx.x;
     const int total = cell_choff[ncell];
@@ -250,7 +250,11 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
             if (prim < 0) write_not_found(p, n, R, code, elem, r, dist);
         }
         const int k = wave_inc(elem_cnt, prim, has && prim >= 0);
-        if (has && prim >= 0) rank[p] = k;
+        // primary and rank in bin order (coalesced), for the scatter by bins
+        if (has) {
+            bin_prim[beg + lane] = prim;
+            rank[beg + lane] = k;
+        }
     }
 }
 
@@ -261,6 +265,20 @@ __global__ __launch_bounds__(256) void k_primary_scatter(int n, int nel, const i
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int e = p < n ? primary[p] : -1;
     if (e >= 0 && e < nel) sorted[elem_off[e] + rank[p]] = p;
+}
+
+// Primary buckets from the bin-ordered output of k_locate_cells: the point
+// at bin position i goes to sorted[elem_off[bin_prim[i]] + rank[i]].
+__global__ __launch_bounds__(256) void k_primary_scatter_bins(int n, const int *nbinned,
+                                                             const int *pbin,
+                                                             const int *bin_prim,
+                                                             const int *rank,
+                                                             const int *elem_off, int *sorted)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || i >= *nbinned) return;
+    const int e = bin_prim[i];
+    if (e >= 0) sorted[elem_off[e] + rank[i]] = pbin[i];
 }
 
 // A primary result settles the point when it is INTERIOR at least `guard`
@@ -463,15 +481,25 @@ hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
                                const int *pbin, const int *cell_poff, const int *cell_choff,
                                int64_t ncell, const int *task_cell, int64_t task_bound,
                                int *ncand, int *primary, int *elem_cnt, int *rank,
-                               int32_t *code, int32_t *elem, double *r, double *dist,
-                               hipStream_t s)
+                               int *bin_prim, int32_t *code, int32_t *elem, double *r,
+                               double *dist, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     HashView h = hash_view(m);
     auto k = m->D == 2 ? k_locate_cells<2> : k_locate_cells<3>;
     hipLaunchKernelGGL(k, dim3(task_grid(task_bound, m->cus)), dim3(64), 0, s, h, (int)n, m->R,
                        pts, pbin, cell_poff, cell_choff, (int)ncell, task_cell, ncand, primary,
-                       elem_cnt, rank, code, elem, r, dist);
+                       elem_cnt, rank, bin_prim, code, elem, r, dist);
+    return hipGetLastError();
+}
+
+hipError_t launch_primary_scatter_bins(int64_t n, const int *nbinned, const int *pbin,
+                                       const int *bin_prim, const int *rank,
+                                       const int *elem_off, int *sorted, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_primary_scatter_bins, dim3(grid_for(n, 256)), dim3(256), 0, s, (int)n,
+                       nbinned, pbin, bin_prim, rank, elem_off, sorted);
     return hipGetLastError();
 }
 
