@@ -286,19 +286,20 @@ __global__ __launch_bounds__(256) void k_primary_scatter_bins(int n, const int *
 // interior (it would overlap the primary), so the paper's rule -- first
 // INTERIOR candidate in ascending id order -- picks the same element.
 
-__device__ inline bool settled(int p, int n, int R, const int *ncand, const int32_t *code,
-                               const double *r)
+__device__ inline bool settled(int nc, int32_t cd, const double (&rr)[3], int R)
 {
-    if (ncand[p] <= 1) return true;
-    if (code[p] != FPTS_INTERIOR) return false;
+    if (nc <= 1) return true;
+    if (cd != FPTS_INTERIOR) return false;
     double m = 1.0;
-    for (int a = 0; a < R; ++a) m = fmin(m, 1.0 - fabs(r[(size_t)a * n + p]));
+    for (int a = 0; a < R; ++a) m = fmin(m, 1.0 - fabs(rr[a]));
     return m > kSettleGuard;
 }
 
 // Phase D.  pass 0: for unsettled points count the other candidates (and
 // per element); pass 1: write their slots (k-th other candidate in
-// ascending id at off2[p] + k) and bucket them by element.
+// ascending id at off2[p] + k) and bucket them by element.  Pass 0 issues
+// all of a point's loads at once (a chain of dependent loads would leave the
+// kernel waiting on latency); pass 1 visits only points that have slots.
 template <int D>
 __global__ __launch_bounds__(256) void k_resolve(HashView h, int pass, int n, int R,
                                                 const double *pts, const int *cellpt,
@@ -310,18 +311,27 @@ __global__ __launch_bounds__(256) void k_resolve(HashView h, int pass, int n, in
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const int prim = primary[p];
-    const bool todo = cellpt[p] >= 0 && prim >= 0 && !settled(p, n, R, ncand, code, r);
-    if (pass == 0 && !todo) {
-        cnt_or_off[p] = 0;
-        return;
+    int s0 = 0;
+    if (pass == 0) {
+        const int c = cellpt[p], prim = primary[p], nc = ncand[p];
+        const int32_t cd = code[p];
+        double rr[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (a < R) rr[a] = r[(size_t)a * n + p];
+        if (!(c >= 0 && prim >= 0 && !settled(nc, cd, rr, R))) {
+            cnt_or_off[p] = 0;
+            return;
+        }
+    } else {
+        s0 = cnt_or_off[p];
+        if (cnt_or_off[p + 1] == s0) return;
     }
-    if (!todo) return;
+    const int prim = primary[p];
+    const int c = cellpt[p];
     double x[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) x[d] = pts[(size_t)d * n + p];
-    const int c = cellpt[p];
-    const int s0 = pass ? cnt_or_off[p] : 0;
     int k = 0;
     for (int q = h.cell_off[c]; q < h.cell_off[c + 1]; ++q) {
         const int e = h.cell_el[q];

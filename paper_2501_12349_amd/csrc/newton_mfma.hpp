@@ -941,7 +941,12 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
 // counter io.counter[8] for the FP64 kernel, [9] for the FP32 phase of mixed
 // mode), over the elements that have pairs.  The start of every pair is
 // read from io.r: the nearest node, or the FP32 result in mixed mode.
-template <typename T, int D, int R, int N>
+// TASKS: the waves stride over the 64-pair tasks of io.task_elem instead
+// (no counter).  The other candidates of unsettled points are a few pairs
+// scattered over many elements; a counter would be stepped once per element
+// of the mesh, mostly past empty queues, one same-address atomic after the
+// other.
+template <typename T, int D, int R, int N, bool TASKS>
 __device__ __forceinline__ void newton_body(const NewtonArgs &a)
 {
     typedef Shape<D, R, N> S;
@@ -955,18 +960,27 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &a)
     T *tab = xl + Lds<T, D, R, N>::NODES;
     T *cache = tab + 2 * Lds<T, D, R, N>::TAB;
     Counters cn;
-    for (;;) {
-        int e = 0;
-        if (lane == 0) {
-            // next element with a non-empty queue
-            for (;;) {
-                e = atomicAdd(io.counter + (FINAL ? 8 : 9), 1);
-                if (e >= a.nel || io.elem_off[e + 1] > io.elem_off[e]) break;
+    const int total = TASKS ? io.chunk_off[a.nel] : 0;
+    for (int t = TASKS ? task_of_block() : 0;; t += gridDim.x) {
+        int e = 0, q0, q1;
+        if constexpr (TASKS) {
+            if (t >= total) break;
+            e = __builtin_amdgcn_readfirstlane(io.task_elem[t]);
+            q0 = io.elem_off[e] + (t - io.chunk_off[e]) * kChunk;
+            q1 = min(io.elem_off[e + 1], q0 + kChunk);
+        } else {
+            if (lane == 0) {
+                // next element with a non-empty queue
+                for (;;) {
+                    e = atomicAdd(io.counter + (FINAL ? 8 : 9), 1);
+                    if (e >= a.nel || io.elem_off[e + 1] > io.elem_off[e]) break;
+                }
             }
+            e = __builtin_amdgcn_readfirstlane(__shfl(e, 0));
+            if (e >= a.nel) break;
+            q0 = io.elem_off[e];
+            q1 = io.elem_off[e + 1];
         }
-        e = __builtin_amdgcn_readfirstlane(__shfl(e, 0));
-        if (e >= a.nel) break;
-        const int q0 = io.elem_off[e], q1 = io.elem_off[e + 1];
         __syncthreads();
         if constexpr (FINAL) {
             stage<double, D * S::NP>(xl, a.nodes + (size_t)e * D * S::NP, lane);
@@ -1006,25 +1020,25 @@ __global__ __launch_bounds__(64) void k_nearest_resolve(NewtonArgs a)
 template <int D, int R, int N>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_newton(NewtonArgs a)
 {
-    newton_body<double, D, R, N>(a);
+    newton_body<double, D, R, N, false>(a);
 }
 template <int D, int R, int N>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 k_newton_resolve(NewtonArgs a)
 {
-    newton_body<double, D, R, N>(a);
+    newton_body<double, D, R, N, true>(a);
 }
 template <int D, int R, int N>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 k_newton32(NewtonArgs a)
 {
-    newton_body<float, D, R, N>(a);
+    newton_body<float, D, R, N, false>(a);
 }
 template <int D, int R, int N>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 k_newton32_resolve(NewtonArgs a)
 {
-    newton_body<float, D, R, N>(a);
+    newton_body<float, D, R, N, true>(a);
 }
 
 typedef void (*KernelFn)(NewtonArgs);
@@ -1069,7 +1083,8 @@ Kernels pick_kernels(int N, bool resolve)
 // 64-pair tasks over io.chunk_off, io.task_elem), then Newton (which & 2; element
 // tasks: in mixed mode the FP32 phase, counter io.counter[9], then the FP64
 // kernel, counter io.counter[8]).  io.counter[0..15] must be zero.  A list
-// with io.slot_pt set (other candidates) selects the *_resolve kernels.
+// with io.slot_pt set (other candidates) selects the *_resolve kernels, whose
+// Newton strides over the 64-pair tasks like the nearest-node kernel.
 template <int D, int R>
 hipError_t launch_newton_kind(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
                               const NewtonIO &io, int which, hipStream_t s)
