@@ -38,7 +38,8 @@ T *at(void *base, size_t off)
     return reinterpret_cast<T *>(static_cast<char *>(base) + off);
 }
 
-constexpr int kCounters = 64;   // ints: element-queue counters of the Newton passes
+constexpr int kCounters = 64;   // ints: 0, 1 the second search's list and slot counts;
+                                 // from 16 on the Newton passes' element-queue counters
 constexpr int kNewtonCounters = 16;   // each Newton pass owns 16 counters from here on
 static_assert(3 * kNewtonCounters <= kCounters, "the two Newton passes need disjoint counters");
 constexpr int kStats = 16;      // unsigned long long: Newton counters per pass
@@ -121,7 +122,9 @@ FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
     w.elem_off = c.take(I * (m->nel + 1));
     w.chunk_off = c.take(I * (m->nel + 1));
     w.sorted = c.take(I * n);
-    w.off2 = c.take(I * (n + 1));
+    w.ulist = c.take(I * n);
+    w.uoff = c.take(I * n);
+    w.ucnt = c.take(I * n);
     w.elem_cnt2 = c.take(I * m->nel);
     w.elem_fill2 = c.take(I * m->nel);
     w.elem_off2 = c.take(I * (m->nel + 1));
@@ -198,7 +201,8 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     int *ncand = at<int>(d_ws, w.ncand), *primary = at<int>(d_ws, w.primary);
     int *elem_cnt = at<int>(d_ws, w.elem_cnt);
     int *elem_off = at<int>(d_ws, w.elem_off), *chunk_off = at<int>(d_ws, w.chunk_off);
-    int *sorted = at<int>(d_ws, w.sorted), *off2 = at<int>(d_ws, w.off2);
+    int *sorted = at<int>(d_ws, w.sorted), *ulist = at<int>(d_ws, w.ulist);
+    int *uoff = at<int>(d_ws, w.uoff), *ucnt = at<int>(d_ws, w.ucnt);
     int *elem_cnt2 = at<int>(d_ws, w.elem_cnt2), *elem_fill2 = at<int>(d_ws, w.elem_fill2);
     int *elem_off2 = at<int>(d_ws, w.elem_off2), *chunk_off2 = at<int>(d_ws, w.chunk_off2);
     int *slot_pt = at<int>(d_ws, w.slot_pt), *slot_elem = at<int>(d_ws, w.slot_elem);
@@ -251,22 +255,25 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     }
     {   // phase D: other candidates of unsettled points, then the selection rule
         Span sp(m, 3, s);
-        chk(launch_resolve(m, 0, n, d_pts, cellpt, ncand, primary, d_code, d_r, off2, elem_cnt2,
-                           nullptr, nullptr, nullptr, nullptr, nullptr, s));
-        chk(launch_exclusive_scan(off2, off2, n, 1, tmp, tb, s));
+        // counters[0]: listed points, counters[1]: slots handed out
+        chk(launch_unsettled(m, n, cellpt, ncand, primary, d_code, d_r, ulist, counters, s));
+        chk(launch_resolve(m, 0, n, d_pts, cellpt, primary, ulist, counters, uoff, ucnt,
+                           counters + 1, elem_cnt2, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           s));
         chk(launch_exclusive_scan(elem_cnt2, elem_off2, nel, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt2, chunk_off2, nel, kChunk, tmp, tb, s));
         chk(launch_task_map(chunk_off2, nel, task_elem2, s));
-        chk(launch_resolve(m, 1, n, d_pts, cellpt, ncand, primary, d_code, d_r, off2, nullptr,
-                           elem_off2, elem_fill2, slot_pt, slot_elem, sorted2, s));
+        chk(launch_resolve(m, 1, n, d_pts, cellpt, primary, ulist, counters, uoff, ucnt,
+                           nullptr, nullptr, elem_off2, elem_fill2, slot_pt, slot_elem, sorted2,
+                           s));
         NewtonIO io{sorted2, elem_off2, chunk_off2, slot_pt, res_code, nullptr, res_r, w.cap2,
                     res_dist, counters + 2 * kNewtonCounters, stats + kStats, task_elem2,
                     w.tb_elem2};
         // the other candidates are few and near element faces: plain FP64
         // in both modes (an FP32 phase would not pay for its launches)
         chk(launch_newton(m, FPTS_FP64, n, d_pts, io, 3, s));
-        chk(launch_select2(m, n, off2, primary, slot_elem, w.cap2, res_r, res_dist, res_code,
-                           d_code, d_elem, d_r, d_dist, s));
+        chk(launch_select2(m, n, ulist, counters, uoff, ucnt, primary, slot_elem, w.cap2, res_r,
+                           res_dist, res_code, d_code, d_elem, d_r, d_dist, s));
     }
     if (m->profiling) m->prof_find++;
     return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;

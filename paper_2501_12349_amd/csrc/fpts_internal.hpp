@@ -135,7 +135,7 @@ __device__ __forceinline__ int wave_inc(int *ctr, int key, bool active)
 
 struct FindWs {
     size_t cell_cnt, cell_poff, cell_choff, cellpt, pbin, ncand, primary, rank, bin_prim,
-        elem_cnt, elem_off, chunk_off, sorted, off2, elem_cnt2, elem_fill2,
+        elem_cnt, elem_off, chunk_off, sorted, ulist, uoff, ucnt, elem_cnt2, elem_fill2,
         elem_off2, chunk_off2, slot_pt, slot_elem, sorted2, res_r, res_dist, res_code,
         task_cell, task_elem, task_elem2, scan_tmp, counters, stats, total;
     int64_t cap2;           // capacity for second-pass (point, candidate) pairs
@@ -282,14 +282,21 @@ hipError_t launch_primary_scatter_bins(int64_t n, const int *nbinned, const int 
 hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int *primary,
                                   const int *elem_off, const int *rank, int *sorted,
                                   hipStream_t s);
-// phase D: pass 0 counts the other candidates of unsettled points, pass 1
-// writes their (point, element) slots into element buckets
+// phase D: list the points whose primary result does not settle them
+// (ulist, *ucount of them); pass 0 counts their other candidates and gives
+// each point a block of slots (uoff, ucnt, running total *slot_total), pass
+// 1 writes the (point, element) slots into element buckets; select2 applies
+// the selection rule to every listed point
+hipError_t launch_unsettled(const fpts_mesh *m, int64_t n, const int *cellpt, const int *ncand,
+                            const int *primary, const int32_t *code, const double *r, int *ulist,
+                            int *ucount, hipStream_t s);
 hipError_t launch_resolve(const fpts_mesh *m, int pass, int64_t n, const double *pts,
-                          const int *cellpt, const int *ncand, const int *primary,
-                          const int32_t *code, const double *r, int *cnt_or_off,
+                          const int *cellpt, const int *primary, const int *ulist,
+                          const int *ucount, int *uoff, int *ucnt, int *slot_total,
                           int *elem_cnt2, const int *elem_off2, int *elem_fill2, int *slot_pt,
                           int *slot_elem, int *sorted2, hipStream_t s);
-hipError_t launch_select2(const fpts_mesh *m, int64_t n, const int *off2, const int *primary,
+hipError_t launch_select2(const fpts_mesh *m, int64_t n, const int *ulist, const int *ucount,
+                          const int *uoff, const int *ucnt, const int *primary,
                           const int *slot_elem, int64_t cap2, const double *res_r,
                           const double *res_dist, const int *res_code, int32_t *code,
                           int32_t *elem, double *r, double *dist, hipStream_t s);

@@ -13,8 +13,9 @@
 namespace fpts {
 namespace {
 
-// pass 0: count points per element and write NaN for NOT_FOUND points;
-// pass 1: scatter point ids into their element's bucket.  With `primary`
+// pass 0: count points per element, keep each point's rank in its bucket
+// (-1 for points not binned) and write NaN for NOT_FOUND points; pass 1:
+// place point ids at their ranks in their element's bucket.  With `primary`
 // (fused find + interpolate) the points that their primary result settled
 // are left out: the fused pass over Find's primary list has them.
 __global__ __launch_bounds__(256) void k_eval_bin(int pass, int n, int nel, int R,
@@ -24,25 +25,42 @@ __global__ __launch_bounds__(256) void k_eval_bin(int pass, int n, int nel, int 
                                                  const int *elem_off, int *rank,
                                                  int *sorted)
 {
-    // no early exit: wave_inc needs every lane
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = p < n;
-    const int e = in ? elem[p] : -1;
-    const bool found = in && code[p] != FPTS_NOT_FOUND && e >= 0 && e < nel;
+    if (pass == 1) {
+        // rank[p] < 0: not binned
+        if (!in) return;
+        const int k = rank[p], e = elem[p];
+        if (k >= 0) sorted[elem_off[e] + k] = p;
+        return;
+    }
+    // pass 0, no early exit (wave_inc needs every lane); all of a point's
+    // loads are issued at once
+    int e = -1, pr = -1;
+    int32_t cd = FPTS_NOT_FOUND;
+    double rr[3] = {0.0, 0.0, 0.0};
+    if (in) {
+        e = elem[p];
+        cd = code[p];
+        if (primary) {
+            pr = primary[p];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (k < R) rr[k] = r[(size_t)k * n + p];
+        }
+    }
+    const bool found = in && cd != FPTS_NOT_FOUND && e >= 0 && e < nel;
     bool done = false;
-    if (primary && found && code[p] == FPTS_INTERIOR && primary[p] == e) {
+    if (primary && found && cd == FPTS_INTERIOR && pr == e) {
         double mg = 1.0;
-        for (int k = 0; k < R; ++k) mg = fmin(mg, 1.0 - fabs(r[(size_t)k * n + p]));
+        for (int k = 0; k < R; ++k) mg = fmin(mg, 1.0 - fabs(rr[k]));
         done = mg > kSettleGuard;
     }
-    if (pass == 0) {
-        const int k = wave_inc(elem_cnt, e, found && !done);
-        if (found && !done) rank[p] = k;
-        if (in && !found)
-            for (int f = 0; f < n_fields; ++f) out[(size_t)f * n + p] = __builtin_nan("");
-    } else if (found && !done) {
-        sorted[elem_off[e] + rank[p]] = p;
-    }
+    const bool bin = found && !done;
+    const int k = wave_inc(elem_cnt, e, bin);
+    if (in) rank[p] = bin ? k : -1;
+    if (in && !found)
+        for (int f = 0; f < n_fields; ++f) out[(size_t)f * n + p] = __builtin_nan("");
 }
 
 template <int N>

@@ -295,99 +295,170 @@ __device__ inline bool settled(int nc, int32_t cd, const double (&rr)[3], int R)
     return m > kSettleGuard;
 }
 
-// Phase D.  pass 0: for unsettled points count the other candidates (and
-// per element); pass 1: write their slots (k-th other candidate in
-// ascending id at off2[p] + k) and bucket them by element.  Pass 0 issues
-// all of a point's loads at once (a chain of dependent loads would leave the
-// kernel waiting on latency); pass 1 visits only points that have slots.
-template <int D>
-__global__ __launch_bounds__(256) void k_resolve(HashView h, int pass, int n, int R,
-                                                const double *pts, const int *cellpt,
-                                                const int *ncand, const int *primary,
-                                                const int32_t *code, const double *r,
-                                                int *cnt_or_off, int *elem_cnt2,
-                                                const int *elem_off2, int *elem_fill2,
-                                                int *slot_pt, int *slot_elem, int *sorted2)
+// Phase D, marking: every point whose primary result leaves the search open
+// (a cell, a primary and not settled) is appended to ulist, in no particular
+// order, *ucount of them.  The other candidates of the few listed points are
+// then handled by dense wavefronts: tested where they lie among all points,
+// their candidate loops (dependent loads) kept whole wavefronts waiting.
+// A block marks kMarkChunk consecutive points, gathers its listed points in
+// LDS and reserves their places with one atomic: device-scope atomics on one
+// address serialise (several ns each), so one per wavefront with a listed
+// point would take longer than the loads.  All of a point's loads are
+// issued at once.
+constexpr int kMarkChunk = 4096;
+
+__global__ __launch_bounds__(256) void k_unsettled(int n, int R, const int *cellpt,
+                                                  const int *ncand, const int *primary,
+                                                  const int32_t *code, const double *r,
+                                                  int *ulist, int *ucount)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    int s0 = 0;
-    if (pass == 0) {
-        const int c = cellpt[p], prim = primary[p], nc = ncand[p];
-        const int32_t cd = code[p];
-        double rr[3] = {0.0, 0.0, 0.0};
+    __shared__ int lst[kMarkChunk];
+    __shared__ int lcnt, gbase;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) lcnt = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kMarkChunk;
+    for (int it = 0; it < kMarkChunk / 256; ++it) {
+        const int64_t q = base + it * 256 + threadIdx.x;
+        const int p = (int)q;
+        bool todo = false;
+        if (q < n) {
+            const int c = cellpt[p], prim = primary[p], nc = ncand[p];
+            const int32_t cd = code[p];
+            double rr[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-            if (a < R) rr[a] = r[(size_t)a * n + p];
-        if (!(c >= 0 && prim >= 0 && !settled(nc, cd, rr, R))) {
-            cnt_or_off[p] = 0;
-            return;
+            for (int a = 0; a < 3; ++a)
+                if (a < R) rr[a] = r[(size_t)a * n + p];
+            todo = c >= 0 && prim >= 0 && !settled(nc, cd, rr, R);
         }
-    } else {
-        s0 = cnt_or_off[p];
-        if (cnt_or_off[p + 1] == s0) return;
-    }
-    const int prim = primary[p];
-    const int c = cellpt[p];
-    double x[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) x[d] = pts[(size_t)d * n + p];
-    int k = 0;
-    for (int q = h.cell_off[c]; q < h.cell_off[c + 1]; ++q) {
-        const int e = h.cell_el[q];
-        if (e == prim) continue;
-        double depth;
-        if (!box_pass<D>(h.box + (size_t)e * (3 * D + D * D), x, depth)) continue;
-        if (pass == 0) {
-            atomicAdd(&elem_cnt2[e], 1);
-        } else {
-            const int s = s0 + k;
-            slot_pt[s] = p;
-            slot_elem[s] = e;
-            sorted2[elem_off2[e] + atomicAdd(&elem_fill2[e], 1)] = s;
+        const unsigned long long m = __ballot(todo);
+        if (m) {
+            int at = 0;
+            if (lane == 0) at = atomicAdd(&lcnt, __popcll(m));
+            at = __shfl(at, 0, 64);
+            if (todo) lst[at + __popcll(m & ((1ull << lane) - 1))] = p;
         }
-        ++k;
     }
-    if (pass == 0) cnt_or_off[p] = k;
+    __syncthreads();
+    const int cnt = lcnt;
+    if (cnt == 0) return;
+    if (threadIdx.x == 0) gbase = atomicAdd(ucount, cnt);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += 256) ulist[gbase + i] = lst[i];
 }
 
-// Section 3.2 selection over the primary and the other candidates of an
-// unsettled point: the lowest-id INTERIOR candidate, else the smallest
-// distance (lowest id on ties).
-__global__ __launch_bounds__(256) void k_select2(int n, int R, const int *off2,
-                                                const int *primary, const int *slot_elem,
-                                                int64_t cap2, const double *res_r,
-                                                const double *res_dist, const int *res_code,
-                                                int32_t *code, int32_t *elem, double *r,
-                                                double *dist)
+// Exclusive prefix sum of v over the lanes of a wavefront; total = the sum.
+__device__ __forceinline__ int wave_excl_sum(int v, int &total)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int s0 = off2[p], s1 = off2[p + 1];
-    if (s0 == s1) return;
-    // best so far: the primary (slot -1)
-    int best = -1;
-    int bcode = code[p], belem = primary[p];
-    double bdist = dist[p];
-    for (int s = s0; s < s1; ++s) {
-        const int e = slot_elem[s], cd = res_code[s];
-        const double dd = res_dist[s];
-        bool take;
-        if (bcode == FPTS_INTERIOR) take = cd == FPTS_INTERIOR && e < belem;
-        else if (cd == FPTS_INTERIOR) take = true;
-        else take = dd < bdist || (dd == bdist && e < belem);
-        if (take) {
-            best = s;
-            bcode = cd;
-            belem = e;
-            bdist = dd;
+    const int lane = __lane_id();
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+    }
+    total = __shfl(incl, 63, 64);
+    return incl - v;
+}
+
+// Phase D over the listed points (grid-stride).  pass 0: count each point's
+// other candidates (and per element) and give the point a block of that many
+// slots, uoff[i] .. uoff[i] + ucnt[i] - 1 (one atomic per wavefront on
+// *slot_total); pass 1: write the slots (k-th other candidate in ascending
+// id at uoff[i] + k) and bucket them by element.
+template <int D>
+__global__ __launch_bounds__(256) void k_resolve(HashView h, int pass, int n, const double *pts,
+                                                const int *cellpt, const int *primary,
+                                                const int *ulist, const int *ucount,
+                                                int *uoff, int *ucnt, int *slot_total,
+                                                int *elem_cnt2, const int *elem_off2,
+                                                int *elem_fill2, int *slot_pt, int *slot_elem,
+                                                int *sorted2)
+{
+    const int cnt = *ucount;
+    const int lane = threadIdx.x & 63;
+    const int stride = gridDim.x * blockDim.x;
+    // the loop condition is wave-uniform (the stride is a multiple of 64)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i - lane < cnt; i += stride) {
+        const bool act = i < cnt;
+        int k = 0;
+        if (act) {
+            const int p = ulist[i];
+            const int prim = primary[p], c = cellpt[p];
+            const int s0 = pass ? uoff[i] : 0;
+            double x[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) x[d] = pts[(size_t)d * n + p];
+            for (int q = h.cell_off[c]; q < h.cell_off[c + 1]; ++q) {
+                const int e = h.cell_el[q];
+                if (e == prim) continue;
+                double depth;
+                if (!box_pass<D>(h.box + (size_t)e * (3 * D + D * D), x, depth)) continue;
+                if (pass == 0) {
+                    atomicAdd(&elem_cnt2[e], 1);
+                } else {
+                    const int sl = s0 + k;
+                    slot_pt[sl] = p;
+                    slot_elem[sl] = e;
+                    sorted2[elem_off2[e] + atomicAdd(&elem_fill2[e], 1)] = sl;
+                }
+                ++k;
+            }
+        }
+        if (pass == 0) {
+            int tot;
+            const int ex = wave_excl_sum(k, tot);
+            int base = 0;
+            if (lane == 0 && tot > 0) base = atomicAdd(slot_total, tot);
+            base = __shfl(base, 0, 64);
+            if (act) {
+                uoff[i] = base + ex;
+                ucnt[i] = k;
+            }
         }
     }
-    if (best < 0) return;
-    code[p] = bcode;
-    elem[p] = belem;
-    dist[p] = bdist;
-    for (int a = 0; a < R; ++a) r[(size_t)a * n + p] = res_r[(size_t)a * cap2 + best];
+}
+
+// Section 3.2 selection over the primary and the other candidates of a
+// listed point: the lowest-id INTERIOR candidate, else the smallest
+// distance (lowest id on ties).
+__global__ __launch_bounds__(256) void k_select2(int n, int R, const int *ulist,
+                                                const int *ucount, const int *uoff,
+                                                const int *ucnt, const int *primary,
+                                                const int *slot_elem, int64_t cap2,
+                                                const double *res_r, const double *res_dist,
+                                                const int *res_code, int32_t *code,
+                                                int32_t *elem, double *r, double *dist)
+{
+    const int cnt = *ucount;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+        const int p = ulist[i];
+        const int s0 = uoff[i], s1 = s0 + ucnt[i];
+        if (s0 == s1) continue;
+        // best so far: the primary (slot -1)
+        int best = -1;
+        int bcode = code[p], belem = primary[p];
+        double bdist = dist[p];
+        for (int s = s0; s < s1; ++s) {
+            const int e = slot_elem[s], cd = res_code[s];
+            const double dd = res_dist[s];
+            bool take;
+            if (bcode == FPTS_INTERIOR) take = cd == FPTS_INTERIOR && e < belem;
+            else if (cd == FPTS_INTERIOR) take = true;
+            else take = dd < bdist || (dd == bdist && e < belem);
+            if (take) {
+                best = s;
+                bcode = cd;
+                belem = e;
+                bdist = dd;
+            }
+        }
+        if (best < 0) continue;
+        code[p] = bcode;
+        elem[p] = belem;
+        dist[p] = bdist;
+        for (int a = 0; a < R; ++a) r[(size_t)a * n + p] = res_r[(size_t)a * cap2 + best];
+    }
 }
 
 inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
@@ -523,30 +594,48 @@ hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int *primary,
     return hipGetLastError();
 }
 
+hipError_t launch_unsettled(const fpts_mesh *m, int64_t n, const int *cellpt, const int *ncand,
+                            const int *primary, const int32_t *code, const double *r, int *ulist,
+                            int *ucount, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unsettled, dim3(grid_for(n, kMarkChunk)), dim3(256), 0, s, (int)n, m->R,
+                       cellpt, ncand, primary, code, r, ulist, ucount);
+    return hipGetLastError();
+}
+
+// grid-stride kernels over the unsettled list: enough blocks to fill the
+// chip when the list is long, few to launch when it is short
+static int list_grid(const fpts_mesh *m, int64_t n)
+{
+    return std::max(1, (int)std::min<int64_t>(grid_for(n, 256), (int64_t)m->cus * 16));
+}
+
 hipError_t launch_resolve(const fpts_mesh *m, int pass, int64_t n, const double *pts,
-                          const int *cellpt, const int *ncand, const int *primary,
-                          const int32_t *code, const double *r, int *cnt_or_off,
+                          const int *cellpt, const int *primary, const int *ulist,
+                          const int *ucount, int *uoff, int *ucnt, int *slot_total,
                           int *elem_cnt2, const int *elem_off2, int *elem_fill2, int *slot_pt,
                           int *slot_elem, int *sorted2, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     HashView h = hash_view(m);
     auto k = m->D == 2 ? k_resolve<2> : k_resolve<3>;
-    hipLaunchKernelGGL(k, dim3(grid_for(n, 256)), dim3(256), 0, s, h, pass, (int)n, m->R, pts,
-                       cellpt, ncand, primary, code, r, cnt_or_off, elem_cnt2, elem_off2,
+    hipLaunchKernelGGL(k, dim3(list_grid(m, n)), dim3(256), 0, s, h, pass, (int)n, pts, cellpt,
+                       primary, ulist, ucount, uoff, ucnt, slot_total, elem_cnt2, elem_off2,
                        elem_fill2, slot_pt, slot_elem, sorted2);
     return hipGetLastError();
 }
 
-hipError_t launch_select2(const fpts_mesh *m, int64_t n, const int *off2, const int *primary,
+hipError_t launch_select2(const fpts_mesh *m, int64_t n, const int *ulist, const int *ucount,
+                          const int *uoff, const int *ucnt, const int *primary,
                           const int *slot_elem, int64_t cap2, const double *res_r,
                           const double *res_dist, const int *res_code, int32_t *code,
                           int32_t *elem, double *r, double *dist, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_select2, dim3(grid_for(n, 256)), dim3(256), 0, s, (int)n, m->R, off2,
-                       primary, slot_elem, cap2, res_r, res_dist, res_code, code, elem, r,
-                       dist);
+    hipLaunchKernelGGL(k_select2, dim3(list_grid(m, n)), dim3(256), 0, s, (int)n, m->R, ulist,
+                       ucount, uoff, ucnt, primary, slot_elem, cap2, res_r, res_dist, res_code,
+                       code, elem, r, dist);
     return hipGetLastError();
 }
 
