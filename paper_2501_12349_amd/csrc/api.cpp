@@ -160,6 +160,8 @@ EvalWs eval_ws_layout(const fpts_mesh *m, int64_t n)
     w.sorted = c.take(sizeof(int) * std::max<int64_t>(n, 1));
     w.tb_elem = task_bound(n, m->nel);
     w.task_elem = c.take(sizeof(int) * w.tb_elem);
+    w.slist = c.take(sizeof(int) * std::max<int64_t>(n, 1));
+    w.scount = c.take(sizeof(int));
     w.total = c.at;
     return w;
 }
@@ -738,6 +740,7 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
     int *eoff = at<int>(ews, v.elem_off), *choff = at<int>(ews, v.chunk_off);
     int *tmp = at<int>(ews, v.scan_tmp), *esorted = at<int>(ews, v.sorted);
     int *etask = at<int>(ews, v.task_elem);
+    int *slist = at<int>(ews, v.slist), *scount = at<int>(ews, v.scount);
     const int64_t tb = scan_tmp_blocks(m->nel);
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) {
@@ -753,20 +756,26 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
     {
         // the rest (settled by the second search, BORDER, NOT_FOUND): the
         // plain interpolation path restricted to them
+        // (they are few and scattered: elements holding at most a few of
+        // them have their points interpolated one lane per point)
         Span sp(m, 4, s);
         chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
+        chk(launch_fill_i32(scount, 1, 0, s));
         chk(launch_eval_bin(m, 0, n, d_code, d_elem, d_r, primary, n_fields, d_out, elem_cnt,
                             nullptr, erank, nullptr, s));
+        chk(launch_eval_split(m, n, d_elem, erank, elem_cnt, nullptr, nullptr, nullptr, nullptr,
+                              0, s));
         chk(launch_exclusive_scan(elem_cnt, eoff, m->nel, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt, choff, m->nel, kChunk, tmp, tb, s));
         chk(launch_task_map(choff, m->nel, etask, s));
-        chk(launch_eval_bin(m, 1, n, d_code, d_elem, d_r, primary, n_fields, d_out, nullptr,
-                            eoff, erank, esorted, s));
+        chk(launch_eval_split(m, n, d_elem, erank, elem_cnt, eoff, esorted, slist, scount, 1, s));
     }
     {
         Span sp(m, 5, s);
         chk(launch_eval(m, n, d_r, n_fields, field_nodes_1d, d_field, d_out, esorted, eoff,
                         choff, etask, v.tb_elem, s));
+        chk(launch_eval_sparse(m, n, d_r, n_fields, field_nodes_1d, d_field, d_out, d_elem, slist,
+                               scount, s));
     }
     if (m->profiling) m->prof_eval++;
     return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;

@@ -145,7 +145,8 @@ struct FindWs {
 };
 
 struct EvalWs {
-    size_t elem_cnt, elem_off, rank, chunk_off, scan_tmp, sorted, task_elem, total;
+    size_t elem_cnt, elem_off, rank, chunk_off, scan_tmp, sorted, task_elem, slist, scount,
+        total;
     int64_t tb_elem;
 };
 
@@ -306,6 +307,17 @@ hipError_t launch_newton(const fpts_mesh *m, int precision, int64_t n, const dou
 // interpolation binning; with `primary` (fused find + interpolate) the
 // points their primary result settled are left out (r is read for that)
 // (pass 0 keeps each point's rank in its element's bucket, pass 1 uses it)
+// fused rest, split into element buckets and a per-point list: phase 0
+// zeroes the counts of elements with few points, phase 1 places every binned
+// point (bucket at its rank, or the list, *count entries)
+hipError_t launch_eval_split(const fpts_mesh *m, int64_t n, const int32_t *elem, const int *rank,
+                             int *elem_cnt, const int *elem_off, int *sorted, int *list,
+                             int *count, int phase, hipStream_t s);
+// interpolation of the listed points, one lane per point
+hipError_t launch_eval_sparse(const fpts_mesh *m, int64_t n, const double *r, int n_fields,
+                              int field_n, const double *field, double *out,
+                              const int32_t *elem, const int *list, const int *count,
+                              hipStream_t s);
 hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
                            const int32_t *elem, const double *r, const int *primary,
                            int n_fields, double *out, int *elem_cnt, const int *elem_off,

@@ -13,6 +13,10 @@
 namespace fpts {
 namespace {
 
+// fused find + interpolate: elements holding at most this many of the
+// remaining points have them interpolated one lane per point
+constexpr int kSparseMax = 4;
+
 // pass 0: count points per element, keep each point's rank in its bucket
 // (-1 for points not binned) and write NaN for NOT_FOUND points; pass 1:
 // place point ids at their ranks in their element's bucket.  With `primary`
@@ -176,6 +180,86 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
     }
 }
 
+// Points of elements that hold at most kSparseMax of the points to
+// interpolate, one lane per point: a wavefront per element task would run
+// the whole element's contraction for one or two points.  Each lane reads
+// its own element's nodal values (global loads), with the arithmetic of
+// k_eval, so both give the same bits.  Grid-stride over the list.
+template <int R, int N>
+__global__ __launch_bounds__(256) void k_eval_sparse(EvalArgs a, const int32_t *elem,
+                                                    const int *list, const int *count)
+{
+    constexpr int NP = (R == 3) ? N * N * N : (R == 2) ? N * N : N;
+    const int cnt = *count;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+        const int p = list[i];
+        const int e = elem[p];
+        double rr[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < R; ++k) rr[k] = a.r[(size_t)k * a.n + p];
+        double v0[N], v1[N], v2[N];
+        basis_v<N>(rr[0], a.basis.z, a.basis.w, v0);
+        if (R >= 2) basis_v<N>(rr[1], a.basis.z, a.basis.w, v1);
+        if (R == 3) basis_v<N>(rr[2], a.basis.z, a.basis.w, v2);
+        for (int f = 0; f < a.n_fields; ++f) {
+            const double *src = a.field + ((size_t)f * a.nel + e) * NP;
+            a.out[(size_t)f * a.n + p] = contract<R, N>(src, v0, v1, v2);
+        }
+    }
+}
+
+// Elements with at most kSparseMax binned points drop out of the bucket
+// counts (their points go to the per-point list).
+__global__ __launch_bounds__(256) void k_eval_dense(int nel, int *elem_cnt)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nel && elem_cnt[e] <= kSparseMax) elem_cnt[e] = 0;
+}
+
+// Pass 1 with the split: a binned point (rank >= 0) of a dense element goes
+// to its bucket, one of a sparse element to the list.  A block takes
+// kSplitChunk consecutive points, gathers its listed points in LDS and
+// reserves their places with one atomic (same-address device atomics
+// serialise).
+constexpr int kSplitChunk = 4096;
+
+__global__ __launch_bounds__(256) void k_eval_split(int n, const int32_t *elem, const int *rank,
+                                                   const int *dense_cnt, const int *elem_off,
+                                                   int *sorted, int *list, int *count)
+{
+    __shared__ int lst[kSplitChunk];
+    __shared__ int lcnt, gbase;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) lcnt = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSplitChunk;
+    for (int it = 0; it < kSplitChunk / 256; ++it) {
+        const int64_t q = base + it * 256 + threadIdx.x;
+        const int p = (int)q;
+        bool sp = false;
+        if (q < n) {
+            const int k = rank[p], e = elem[p];
+            if (k >= 0) {
+                if (dense_cnt[e] > 0) sorted[elem_off[e] + k] = p;
+                else sp = true;
+            }
+        }
+        const unsigned long long m = __ballot(sp);
+        if (m) {
+            int at = 0;
+            if (lane == 0) at = atomicAdd(&lcnt, __popcll(m));
+            at = __shfl(at, 0, 64);
+            if (sp) lst[at + __popcll(m & ((1ull << lane) - 1))] = p;
+        }
+    }
+    __syncthreads();
+    const int cnt = lcnt;
+    if (cnt == 0) return;
+    if (threadIdx.x == 0) gbase = atomicAdd(count, cnt);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += 256) list[gbase + i] = lst[i];
+}
+
 __global__ void k_nodes32(const double *nodes, const double *xc, float *out, int64_t nel, int D,
                           int NP)
 {
@@ -231,6 +315,25 @@ EvalFn pick_eval(int N)
     }
 }
 
+typedef void (*SparseFn)(EvalArgs, const int32_t *, const int *, const int *);
+
+template <int R>
+SparseFn pick_sparse(int N)
+{
+    switch (N) {
+    case 2: return k_eval_sparse<R, 2>;
+    case 3: return k_eval_sparse<R, 3>;
+    case 4: return k_eval_sparse<R, 4>;
+    case 5: return k_eval_sparse<R, 5>;
+    case 6: return k_eval_sparse<R, 6>;
+    case 7: return k_eval_sparse<R, 7>;
+    case 8: return k_eval_sparse<R, 8>;
+    case 9: return k_eval_sparse<R, 9>;
+    case 10: return k_eval_sparse<R, 10>;
+    default: return nullptr;
+    }
+}
+
 template <bool LDS>
 EvalFn pick_eval_r(int R, int N)
 {
@@ -278,6 +381,45 @@ hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fie
     for (int k = 1; k < m->R; ++k) npf *= field_n;
     hipLaunchKernelGGL(fn, dim3(task_grid(task_bound, m->cus)), dim3(64),
                        lds ? sizeof(double) * npf : 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_split(const fpts_mesh *m, int64_t n, const int32_t *elem, const int *rank,
+                             int *elem_cnt, const int *elem_off, int *sorted, int *list,
+                             int *count, int phase, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (phase == 0) {
+        hipLaunchKernelGGL(k_eval_dense, dim3((unsigned)((m->nel + 255) / 256)), dim3(256), 0, s,
+                           (int)m->nel, elem_cnt);
+    } else {
+        hipLaunchKernelGGL(k_eval_split, dim3((unsigned)((n + kSplitChunk - 1) / kSplitChunk)),
+                           dim3(256), 0, s, (int)n, elem, rank, elem_cnt, elem_off, sorted, list,
+                           count);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_sparse(const fpts_mesh *m, int64_t n, const double *r, int n_fields,
+                              int field_n, const double *field, double *out,
+                              const int32_t *elem, const int *list, const int *count,
+                              hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    SparseFn fn = m->R == 3 ? pick_sparse<3>(field_n)
+                : m->R == 2 ? pick_sparse<2>(field_n) : pick_sparse<1>(field_n);
+    if (!fn) return hipErrorInvalidValue;
+    EvalArgs a{};
+    a.r = r;
+    a.n = (int)n;
+    a.nel = (int)m->nel;
+    a.n_fields = n_fields;
+    a.field = field;
+    a.out = out;
+    if (field_n == m->N) a.basis = m->basis;
+    else gll::fill(field_n, a.basis.z, a.basis.w);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, m->cus * 8));
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, s, a, elem, list, count);
     return hipGetLastError();
 }
 
