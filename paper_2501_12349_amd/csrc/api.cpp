@@ -142,6 +142,7 @@ FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
     w.task_elem = c.take(I * w.tb_elem);
     w.task_elem2 = c.take(I * w.tb_elem2);
     w.scan_tmp = c.take(I * w.scan_blocks);
+    w.pts4 = c.take(m->R >= 2 ? sizeof(double) * pt_stride(m->D) * n : 1);
     w.counters = c.take(I * kCounters);
     w.stats = c.take(sizeof(unsigned long long) * 2 * kStats);
     w.total = c.at;
@@ -214,6 +215,9 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     int *counters = at<int>(d_ws, w.counters);
     int *task_cell = at<int>(d_ws, w.task_cell), *task_elem = at<int>(d_ws, w.task_elem);
     int *task_elem2 = at<int>(d_ws, w.task_elem2);
+    // the packed copy of the points: volume and surface meshes (the line
+    // kernel reads the [D][n] coordinates)
+    double *pts4 = m->R >= 2 ? at<double>(d_ws, w.pts4) : nullptr;
     unsigned long long *stats = at<unsigned long long>(d_ws, w.stats);
     const int64_t nel = m->nel, ncell = w.ncell, tb = w.scan_blocks;
     hipError_t e = hipSuccess;
@@ -228,14 +232,14 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         chk(launch_fill_i32(elem_fill2, nel, 0, s));
         chk(launch_fill_i32(counters, kCounters, 0, s));
         chk(launch_fill_i32(reinterpret_cast<int *>(stats), 4 * kStats, 0, s));
-        chk(launch_cell_bin(m, 0, n, d_pts, keep, cellpt, cell_cnt, nullptr, rank, nullptr,
+        chk(launch_cell_bin(m, 0, n, d_pts, pts4, keep, cellpt, cell_cnt, nullptr, rank, nullptr,
                             ncand, primary, d_code, d_elem, d_r, d_dist, s));
         chk(launch_exclusive_scan(cell_cnt, cell_poff, ncell, 1, tmp, tb, s));
         chk(launch_exclusive_scan(cell_cnt, cell_choff, ncell, kChunk, tmp, tb, s));
         chk(launch_task_map(cell_choff, ncell, task_cell, s));
-        chk(launch_cell_bin(m, 1, n, d_pts, keep, cellpt, nullptr, cell_poff, rank, pbin,
+        chk(launch_cell_bin(m, 1, n, d_pts, nullptr, keep, cellpt, nullptr, cell_poff, rank, pbin,
                             nullptr, nullptr, d_code, d_elem, d_r, d_dist, s));
-        chk(launch_locate_cells(m, n, d_pts, pbin, cell_poff, cell_choff, ncell, task_cell,
+        chk(launch_locate_cells(m, n, d_pts, pts4, pbin, cell_poff, cell_choff, ncell, task_cell,
                                 w.tb_cell, ncand, primary, elem_cnt, rank, bin_prim, d_code,
                                 d_elem, d_r, d_dist, s));
         chk(launch_exclusive_scan(elem_cnt, elem_off, nel, 1, tmp, tb, s));
@@ -248,6 +252,7 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     {   // phase C: Newton on the primary candidates, results straight to the outputs
         NewtonIO io{sorted, elem_off, chunk_off, nullptr, d_code, d_elem, d_r, n, d_dist,
                     counters + kNewtonCounters, stats, task_elem, w.tb_elem, rs, n};
+        io.pts4 = pts4;
         {
             Span sp(m, 1, s);
             chk(launch_newton(m, precision, n, d_pts, io, 1, s));
@@ -271,6 +276,7 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         NewtonIO io{sorted2, elem_off2, chunk_off2, slot_pt, res_code, nullptr, res_r, w.cap2,
                     res_dist, counters + 2 * kNewtonCounters, stats + kStats, task_elem2,
                     w.tb_elem2};
+        io.pts4 = pts4;
         // the other candidates are few and near element faces: plain FP64
         // in both modes (an FP32 phase would not pay for its launches)
         chk(launch_newton(m, FPTS_FP64, n, d_pts, io, 3, s));

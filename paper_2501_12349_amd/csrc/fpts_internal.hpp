@@ -14,6 +14,8 @@ namespace fpts {
 constexpr int kMaxN = 10;        // nodes per direction with compiled kernels
 constexpr int kWave = 64;        // CDNA wavefront
 constexpr int kChunk = 64;       // (point, element) pairs per wave task
+// doubles per point in the packed copy of the points (x, y, z, 0 / x, y)
+constexpr int pt_stride(int D) { return D == 3 ? 4 : 2; }
 
 // GLL nodes z_i and product-form weights w_i = 1 / prod_{m != i}(z_i - z_m):
 // phi_i(r) = w_i prod_{m != i}(r - z_m).
@@ -137,7 +139,7 @@ struct FindWs {
     size_t cell_cnt, cell_poff, cell_choff, cellpt, pbin, ncand, primary, rank, bin_prim,
         elem_cnt, elem_off, chunk_off, sorted, ulist, uoff, ucnt, elem_cnt2, elem_fill2,
         elem_off2, chunk_off2, slot_pt, slot_elem, sorted2, res_r, res_dist, res_code,
-        task_cell, task_elem, task_elem2, scan_tmp, counters, stats, total;
+        task_cell, task_elem, task_elem2, scan_tmp, counters, stats, pts4, total;
     int64_t cap2;           // capacity for second-pass (point, candidate) pairs
     int64_t scan_blocks;
     int64_t ncell;
@@ -175,6 +177,9 @@ struct NewtonIO {
     // the pass limit did; max_iter > 0 replaces the mesh's pass limit
     int *conv;
     int max_iter;
+    // optional: the points packed per point, [n][pt_stride(D)] (read instead
+    // of the [D][n] coordinates: one cache line per gathered point)
+    const double *pts4;
 };
 
 }  // namespace fpts
@@ -252,9 +257,10 @@ int64_t scan_tmp_blocks(int64_t n);
 // phase A: pass 0 counts points per cell (and writes NOT_FOUND for points
 // outside the map), keeping each point's rank among its cell's points; pass 1
 // puts point ids into cell buckets at those ranks; points with keep[p] != 0
-// (keep may be null) are left out and keep their results
+// (keep may be null) are left out and keep their results; pass 0 also
+// writes the coordinates packed per point to pts4 unless it is null
 hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double *pts,
-                           const int *keep, int *cellpt, int *cell_cnt, const int *cell_poff,
+                           double *pts4, const int *keep, int *cellpt, int *cell_cnt, const int *cell_poff,
                            int *rank, int *pbin, int *ncand, int *primary, int32_t *code,
                            int32_t *elem, double *r, double *dist, hipStream_t s);
 // search hints: pass 0 makes the previous element of each previously
@@ -270,6 +276,7 @@ hipError_t launch_task_map(const int *chunk_off, int64_t nunit, int *task_unit, 
 // (counts primaries per element; in bin order, bin_prim[i] and rank[i] are
 // the primary of the point at bin position i and its rank in that bucket)
 hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
+                               const double *pts4,
                                const int *pbin, const int *cell_poff, const int *cell_choff,
                                int64_t ncell, const int *task_cell, int64_t task_bound,
                                int *ncand, int *primary, int *elem_cnt, int *rank,

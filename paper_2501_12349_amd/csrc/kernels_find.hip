@@ -156,10 +156,11 @@ __device__ inline void write_not_found(int p, int n, int R, int32_t *code, int32
 }
 
 // Phase A.  pass 0: cell of each point, count per cell, NOT_FOUND for points
-// outside the map; pass 1: scatter point ids into their cell's bucket.
+// outside the map, and (pts4 not null) the coordinates packed per point;
+// pass 1: scatter point ids into their cell's bucket.
 template <int D>
 __global__ __launch_bounds__(256) void k_cell_bin(HashView h, int pass, int n, int R,
-                                                 const double *pts, const int *keep,
+                                                 const double *pts, double *pts4, const int *keep,
                                                  int *cellpt, int *cell_cnt,
                                                  const int *cell_poff, int *rank,
                                                  int *pbin, int *ncand, int *primary,
@@ -179,6 +180,14 @@ __global__ __launch_bounds__(256) void k_cell_bin(HashView h, int pass, int n, i
 #pragma unroll
                 for (int d = 0; d < D; ++d) x[d] = pts[(size_t)d * n + p];
                 c = cell_of<D>(h, x);
+                if (pts4) {
+                    // the packed copy (one cache line per point for the
+                    // kernels that visit points in bucket order)
+                    typedef double v2 __attribute__((ext_vector_type(2)));
+                    v2 *o = reinterpret_cast<v2 *>(pts4 + (size_t)p * pt_stride(D));
+                    o[0] = v2{x[0], x[1]};
+                    if (D == 3) o[1] = v2{x[D - 1], 0.0};
+                }
             }
             cellpt[p] = c;
             // every point gets defined candidate data, also those no cell holds
@@ -208,8 +217,9 @@ __global__ __launch_bounds__(256) void k_task_map(const int *chunk_off, int nuni
 // wave-uniform and read with scalar loads; every lane tests its own point.
 // Per point: number of candidates, primary candidate (smallest OBB depth,
 // lowest id on ties), and the primary's bucket count.
-template <int D>
+template <int D, bool PACKED>
 __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, const double *pts,
+                                                    const double *pts4,
                                                     const int *pbin, const int *cell_poff,
                                                     const int *cell_choff, int ncell,
                                                     const int *task_cell, int *ncand,
@@ -227,7 +237,8 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
         const int p = has ? pbin[beg + lane] : 0;
         double x[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) x[d] = has ? pts[(size_t)d * n + p] : 0.0;
+        for (int d = 0; d < D; ++d)
+            x[d] = !has ? 0.0 : PACKED ? pts4[(size_t)p * pt_stride(D) + d] : pts[(size_t)d * n + p];
         const int q0 = __builtin_amdgcn_readfirstlane(h.cell_off[c]);
         const int q1 = __builtin_amdgcn_readfirstlane(h.cell_off[c + 1]);
         int cnt = 0, prim = -1;
@@ -536,7 +547,7 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int64_t n, int ceil_di
 }
 
 hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double *pts,
-                           const int *keep, int *cellpt, int *cell_cnt, const int *cell_poff,
+                           double *pts4, const int *keep, int *cellpt, int *cell_cnt, const int *cell_poff,
                            int *rank, int *pbin, int *ncand, int *primary, int32_t *code,
                            int32_t *elem, double *r, double *dist, hipStream_t s)
 {
@@ -544,7 +555,7 @@ hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double
     HashView h = hash_view(m);
     const int grid = grid_for(n, 256);
     auto k = m->D == 2 ? k_cell_bin<2> : k_cell_bin<3>;
-    hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, h, pass, (int)n, m->R, pts, keep,
+    hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, h, pass, (int)n, m->R, pts, pts4, keep,
                        cellpt, cell_cnt, cell_poff, rank, pbin, ncand, primary, code, elem, r,
                        dist);
     return hipGetLastError();
@@ -559,6 +570,7 @@ hipError_t launch_task_map(const int *chunk_off, int64_t nunit, int *task_unit, 
 }
 
 hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
+                               const double *pts4,
                                const int *pbin, const int *cell_poff, const int *cell_choff,
                                int64_t ncell, const int *task_cell, int64_t task_bound,
                                int *ncand, int *primary, int *elem_cnt, int *rank,
@@ -567,9 +579,11 @@ hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
 {
     if (n <= 0) return hipSuccess;
     HashView h = hash_view(m);
-    auto k = m->D == 2 ? k_locate_cells<2> : k_locate_cells<3>;
+    auto k = m->D == 2 ? (pts4 ? k_locate_cells<2, true> : k_locate_cells<2, false>)
+                       : (pts4 ? k_locate_cells<3, true> : k_locate_cells<3, false>);
     hipLaunchKernelGGL(k, dim3(task_grid(task_bound, m->cus)), dim3(64), 0, s, h, (int)n, m->R,
-                       pts, pbin, cell_poff, cell_choff, (int)ncell, task_cell, ncand, primary,
+                       pts, pts4, pbin, cell_poff, cell_choff, (int)ncell, task_cell, ncand,
+                       primary,
                        elem_cnt, rank, bin_prim, code, elem, r, dist);
     return hipGetLastError();
 }

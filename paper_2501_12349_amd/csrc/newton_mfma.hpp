@@ -471,6 +471,13 @@ struct NewtonArgs {
     float tol32;
 };
 
+// Coordinate c of point p: from the packed copy when the caller made one.
+template <int D>
+__device__ __forceinline__ double point_coord(const NewtonArgs &a, int p, int c)
+{
+    return a.io.pts4 ? a.io.pts4[(size_t)p * pt_stride(D) + c] : a.pts[(size_t)c * a.n + p];
+}
+
 enum { S_FREE = 0, S_INIT = 1, S_STEP = 2, S_WAIT = 3 };
 
 // per-slot counters are kept by the slot's leader lane, per-wave (sweep)
@@ -536,7 +543,7 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
 #pragma unroll
                 for (int c = 0; c < D; ++c)
                     cache[c * kCache + lane] =
-                        T(a.pts[(size_t)c * a.n + p] - (shift ? shift[c] : 0.0));
+                        T(point_coord<D>(a, p, c) - (shift ? shift[c] : 0.0));
                 // agent-scope loads: in mixed mode the FP32 phase of this
                 // wave stored these values moments ago
 #pragma unroll
@@ -863,7 +870,7 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
             T pa[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
             for (int c = 0; c < D; ++c)
-                pa[c] = has ? T(a.pts[(size_t)c * a.n + p] - xc[c]) : T(0);
+                pa[c] = has ? T(point_coord<D>(a, p, c) - xc[c]) : T(0);
             pa[D] = T(1);
 #pragma unroll
             for (int k = 0; k < 4; ++k) Pt[k * 64 + lane] = pa[k];
