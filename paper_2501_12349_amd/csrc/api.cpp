@@ -143,6 +143,7 @@ FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
     w.task_elem2 = c.take(I * w.tb_elem2);
     w.scan_tmp = c.take(I * w.scan_blocks);
     w.pts4 = c.take(m->R >= 2 ? sizeof(double) * pt_stride(m->D) * n : 1);
+    w.start = c.take(sizeof(double) * m->R * n);
     w.counters = c.take(I * kCounters);
     w.stats = c.take(sizeof(unsigned long long) * 2 * kStats);
     w.total = c.at;
@@ -218,6 +219,7 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     // the packed copy of the points: volume and surface meshes (the line
     // kernel reads the [D][n] coordinates)
     double *pts4 = m->R >= 2 ? at<double>(d_ws, w.pts4) : nullptr;
+    double *start = at<double>(d_ws, w.start);
     unsigned long long *stats = at<unsigned long long>(d_ws, w.stats);
     const int64_t nel = m->nel, ncell = w.ncell, tb = w.scan_blocks;
     hipError_t e = hipSuccess;
@@ -253,6 +255,10 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         NewtonIO io{sorted, elem_off, chunk_off, nullptr, d_code, d_elem, d_r, n, d_dist,
                     counters + kNewtonCounters, stats, task_elem, w.tb_elem, rs, n};
         io.pts4 = pts4;
+        if (m->R >= 2) {
+            io.start = start;
+            io.start_stride = n;
+        }
         {
             Span sp(m, 1, s);
             chk(launch_newton(m, precision, n, d_pts, io, 1, s));

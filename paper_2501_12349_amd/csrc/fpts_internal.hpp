@@ -139,7 +139,7 @@ struct FindWs {
     size_t cell_cnt, cell_poff, cell_choff, cellpt, pbin, ncand, primary, rank, bin_prim,
         elem_cnt, elem_off, chunk_off, sorted, ulist, uoff, ucnt, elem_cnt2, elem_fill2,
         elem_off2, chunk_off2, slot_pt, slot_elem, sorted2, res_r, res_dist, res_code,
-        task_cell, task_elem, task_elem2, scan_tmp, counters, stats, pts4, total;
+        task_cell, task_elem, task_elem2, scan_tmp, counters, stats, pts4, start, total;
     int64_t cap2;           // capacity for second-pass (point, candidate) pairs
     int64_t scan_blocks;
     int64_t ncell;
@@ -180,6 +180,12 @@ struct NewtonIO {
     // optional: the points packed per point, [n][pt_stride(D)] (read instead
     // of the [D][n] coordinates: one cache line per gathered point)
     const double *pts4;
+    // optional: the starts of the Newton kernel (nearest node, or the FP32
+    // phase's result in mixed mode) at the pair's position q in `list`,
+    // start[k * start_stride + q], instead of in r: written and read in list
+    // order, without a gather
+    double *start;
+    int64_t start_stride;
 };
 
 }  // namespace fpts

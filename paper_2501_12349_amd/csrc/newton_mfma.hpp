@@ -549,7 +549,9 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
 #pragma unroll
                 for (int k = 0; k < R; ++k)
                     cache[(D + k) * kCache + lane] = T(__hip_atomic_load(
-                        io.r + (size_t)k * io.ostride + it, __ATOMIC_RELAXED,
+                        io.start ? io.start + (size_t)k * io.start_stride + idx
+                                 : io.r + (size_t)k * io.ostride + it,
+                        __ATOMIC_RELAXED,
                         __HIP_MEMORY_SCOPE_AGENT));
             }
             wave_lds_sync();
@@ -605,7 +607,12 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                 }
             }
 #pragma unroll
-            for (int k = 0; k < R; ++k) io.r[(size_t)k * io.ostride + item] = (double)r[k];
+            for (int k = 0; k < R; ++k) {
+                if (!FINAL && io.start)   // the FP64 phase's start
+                    io.start[(size_t)k * io.start_stride + pos] = (double)r[k];
+                else
+                    io.r[(size_t)k * io.ostride + item] = (double)r[k];
+            }
         }
         state = S_FREE;
     };
@@ -937,7 +944,10 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
 #pragma unroll
                     for (int m = 1; m < N; ++m)
                         if (ii[k] == m) v = GT.z[m];
-                    io.r[(size_t)k * io.ostride + item] = v;
+                    if (io.start)
+                        io.start[(size_t)k * io.start_stride + beg + pl] = v;
+                    else
+                        io.r[(size_t)k * io.ostride + item] = v;
                 }
             }
         }
@@ -947,7 +957,8 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
 // Newton over the element queue in precision T: one wave per element (task
 // counter io.counter[8] for the FP64 kernel, [9] for the FP32 phase of mixed
 // mode), over the elements that have pairs.  The start of every pair is
-// read from io.r: the nearest node, or the FP32 result in mixed mode.
+// read from io.start (or io.r): the nearest node, or the FP32 result in
+// mixed mode.
 // TASKS: the waves stride over the 64-pair tasks of io.task_elem instead
 // (no counter).  The other candidates of unsettled points are a few pairs
 // scattered over many elements; a counter would be stepped once per element
