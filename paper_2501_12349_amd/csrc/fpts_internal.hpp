@@ -266,9 +266,9 @@ int64_t scan_tmp_blocks(int64_t n);
 // (keep may be null) are left out and keep their results; pass 0 also
 // writes the coordinates packed per point to pts4 unless it is null
 hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double *pts,
-                           double *pts4, const int *keep, int *cellpt, int *cell_cnt, const int *cell_poff,
-                           int *rank, int *pbin, int *ncand, int *primary, int32_t *code,
-                           int32_t *elem, double *r, double *dist, hipStream_t s);
+                           double *pts4, const int *keep, int *cellpt, int *cell_cnt,
+                           const int *cell_poff, int *rank, int *pbin, int *ncand, int *primary,
+                           int32_t *code, int32_t *elem, double *r, double *dist, hipStream_t s);
 // search hints: pass 0 makes the previous element of each previously
 // INTERIOR point its primary (counted per element); pass 1 sets keep[p] for
 // points the hinted search settled
@@ -317,9 +317,6 @@ hipError_t launch_select2(const fpts_mesh *m, int64_t n, const int *ulist, const
 // which: 1 = nearest-node start, 2 = Newton, 3 = both
 hipError_t launch_newton(const fpts_mesh *m, int precision, int64_t n, const double *pts,
                          const NewtonIO &io, int which, hipStream_t s);
-// interpolation binning; with `primary` (fused find + interpolate) the
-// points their primary result settled are left out (r is read for that)
-// (pass 0 keeps each point's rank in its element's bucket, pass 1 uses it)
 // fused rest, split into element buckets and a per-point list: phase 0
 // zeroes the counts of elements with few points, phase 1 places every binned
 // point (bucket at its rank, or the list, *count entries)
@@ -331,6 +328,9 @@ hipError_t launch_eval_sparse(const fpts_mesh *m, int64_t n, const double *r, in
                               int field_n, const double *field, double *out,
                               const int32_t *elem, const int *list, const int *count,
                               hipStream_t s);
+// interpolation binning; with `primary` (fused find + interpolate) the
+// points their primary result settled are left out (r is read for that)
+// (pass 0 keeps each point's rank in its element's bucket, pass 1 uses it)
 hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
                            const int32_t *elem, const double *r, const int *primary,
                            int n_fields, double *out, int *elem_cnt, const int *elem_off,

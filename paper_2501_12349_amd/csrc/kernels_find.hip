@@ -238,7 +238,9 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
         double x[D];
 #pragma unroll
         for (int d = 0; d < D; ++d)
-            x[d] = !has ? 0.0 : PACKED ? pts4[(size_t)p * pt_stride(D) + d] : pts[(size_t)d * n + p];
+            x[d] = !has    ? 0.0
+                   : PACKED ? pts4[(size_t)p * pt_stride(D) + d]
+                            : pts[(size_t)d * n + p];
         const int q0 = __builtin_amdgcn_readfirstlane(h.cell_off[c]);
         const int q1 = __builtin_amdgcn_readfirstlane(h.cell_off[c + 1]);
         int cnt = 0, prim = -1;
@@ -547,9 +549,9 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int64_t n, int ceil_di
 }
 
 hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double *pts,
-                           double *pts4, const int *keep, int *cellpt, int *cell_cnt, const int *cell_poff,
-                           int *rank, int *pbin, int *ncand, int *primary, int32_t *code,
-                           int32_t *elem, double *r, double *dist, hipStream_t s)
+                           double *pts4, const int *keep, int *cellpt, int *cell_cnt,
+                           const int *cell_poff, int *rank, int *pbin, int *ncand, int *primary,
+                           int32_t *code, int32_t *elem, double *r, double *dist, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     HashView h = hash_view(m);
