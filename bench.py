@@ -93,9 +93,25 @@ def make_workload(name):
     raise SystemExit("unknown workload %s" % name)
 
 
-def cpu_baseline(wl, sample, log_):
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo) and logical CPU count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
+def cpu_baseline(wl, sample, log_, sample_1core=100000):
     """The oracle (FP64, OpenMP over points) on the first `sample` points:
-    find + eval timed, setup excluded."""
+    find + eval timed, setup excluded; then the first `sample_1core` points
+    on one thread.  Returns the report and the oracle's results on the
+    sample (for the error of the GPU results)."""
     import oracle
     t0 = time.perf_counter()
     om = oracle.Mesh(wl["nodes"], wl["dim"], wl["ref_dim"], wl["N"])
@@ -104,15 +120,60 @@ def cpu_baseline(wl, sample, log_):
     log_("cpu baseline: oracle setup %.1f s, timing find+eval on %d points" % (t_setup, sample))
     t0 = time.perf_counter()
     res = om.find(pts)
-    if wl.get("fields") is not None:
-        om.eval(res, wl["fields"])
+    u = om.eval(res, wl["fields"]) if wl.get("fields") is not None else None
     t = time.perf_counter() - t0
-    return dict(value=sample / t / 1e6, unit="Mpts/s", cores=oracle.max_threads(),
-                kind="oracle",
-                sample="first %d of the %d points, same mesh and %d fields; find+eval %.1f s, "
-                       "oracle setup %.1f s excluded" % (
-                           sample, wl["pts"].shape[1],
-                           0 if wl.get("fields") is None else wl["fields"].shape[0], t, t_setup))
+    n1 = min(sample_1core, sample)
+    p1 = np.ascontiguousarray(wl["pts"][:, :n1])
+    t0 = time.perf_counter()
+    r1 = om.find(p1, nthreads=1)
+    if wl.get("fields") is not None:
+        om.eval(r1, wl["fields"], nthreads=1)
+    t1 = time.perf_counter() - t0
+    model, ncpu = cpu_model()
+    log_("cpu baseline: %.3f Mpts/s on %d threads, %.3f Mpts/s on one (%s)" % (
+        sample / t / 1e6, oracle.max_threads(), n1 / t1 / 1e6, model))
+    rep = dict(value=sample / t / 1e6, unit="Mpts/s", cores=oracle.max_threads(),
+               kind="oracle", cpu_model=model, logical_cpus=ncpu,
+               value_1core=round(n1 / t1 / 1e6, 5),
+               sample="first %d of the %d points, same mesh and %d fields; find+eval %.1f s, "
+                      "oracle setup %.1f s excluded; one-thread figure on the first %d points "
+                      "(%.1f s)" % (
+                          sample, wl["pts"].shape[1],
+                          0 if wl.get("fields") is None else wl["fields"].shape[0], t, t_setup,
+                          n1, t1))
+    return rep, om, res, u
+
+
+# oracle margins below which a point is ambiguous (its answer may change under
+# rounding-level changes of the inputs): reference units from a face, box
+# slack, BORDER gap and distance over h, surface threshold
+_AMB_R, _AMB_BOX, _AMB_GAP, _AMB_EPS = 2e-6, 1e-9, 1e-8, 1e-6
+
+
+def error_vs_oracle(orc, uo, gpu, ug, h, surface):
+    """Error of GPU results against the oracle's on the same points: element
+    / code mismatches on the unambiguous points, max |dr|, max |ddist| / h
+    and the max field error relative to max(|u_oracle|, max |u|)."""
+    m, code = orc["margin"], orc["code"]
+    amb = (code == 0) & (m[0] < _AMB_R)
+    amb |= (code != 0) & (m[1] < _AMB_BOX)
+    amb |= (code == 1) & ((m[2] < _AMB_GAP) | (m[3] < _AMB_GAP))
+    if surface:
+        amb |= (code != 2) & (m[4] < _AMB_EPS)
+    una = ~amb
+    found = una & (code != 2)
+    out = dict(points=int(code.size), ambiguous=int(amb.sum()),
+               elem_mismatch=int((una & (gpu["elem"] != orc["elem"])).sum()),
+               code_mismatch=int((una & (gpu["code"] != code)).sum()))
+    same = found & (gpu["elem"] == orc["elem"])
+    out["max_dr"] = float(np.abs(gpu["r"][:, same] - orc["r"][:, same]).max()) if same.any() \
+        else 0.0
+    out["max_ddist_over_h"] = float(np.abs(gpu["dist"][same] - orc["dist"][same]).max() / h) \
+        if same.any() else 0.0
+    if uo is not None and ug is not None and same.any():
+        scale = np.maximum(np.abs(uo[:, same]), np.abs(uo[:, same]).max(axis=1, keepdims=True))
+        out["max_du_rel"] = float((np.abs(ug[:, same] - uo[:, same]) / scale).max())
+    return out
 
 
 def pcie_inclusive(gm, wl, fields, ws_f, ws_e, mode, steps):
@@ -429,12 +490,16 @@ def main():
         stats = gm.find_stats(newton_pass=1)
         stats_all = gm.find_stats()
         codes = torch.bincount(out["code"].long(), minlength=3).cpu().tolist()
+        # the sample the oracle checks: the first points of the batch
+        ns = min(args.cpu_sample, n)
+        snap = {k: (v[..., :ns].cpu().numpy()) for k, v in out.items()}
+        snap_u = u[:, :ns].cpu().numpy()
         ms = dt / args.steps * 1e3
         newton_ms = kt["newton_ms"] / max(kt["find_calls"], 1)
         fl = newton_flops(stats, D, R, N)
         results[mode] = dict(ms_per_step=ms, mpts=n / (dt / args.steps) / 1e6, kt=kt,
                              newton_ms=newton_ms, stats=stats, stats_all=stats_all, flops=fl,
-                             codes=codes)
+                             codes=codes, snap=snap, snap_u=snap_u)
         log("%s: %.3f ms/step  %.1f Mpts/s  k_newton %.3f ms (%.1f TFLOP/s)  nearest %.3f "
             "locate %.3f select %.3f eval_bin %.3f eval %.3f ms/call  codes %s  slots %s  "
             "stats %s" % (
@@ -523,7 +588,16 @@ def main():
     if args.serve_requests > 0:
         line["serving"] = serving(args.serve_requests, int(args.serve_budget_gb * (1 << 30)))
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(wl, min(args.cpu_sample, n), log)
+        rep, om, orc, uo = cpu_baseline(wl, min(args.cpu_sample, n), log)
+        line["cpu_baseline"] = rep
+        # error of every GPU result against the FP64 oracle on that sample
+        line["error_vs_oracle"] = {
+            mode: error_vs_oracle(orc, uo, results[mode]["snap"], results[mode]["snap_u"],
+                                  wl["h"], R < D)
+            for mode in results}
+        for mode, e in line["error_vs_oracle"].items():
+            log("error vs oracle, %s: %s" % (mode, e))
+        del om, orc, uo
     print(json.dumps(line), flush=True)
 
 

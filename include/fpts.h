@@ -260,6 +260,12 @@ int fpts_get_boxes(const fpts_mesh *m, double *h_aabb, double *h_obb_A,
 int fpts_get_hash(const fpts_mesh *m, double *h_lo, double *h_hi,
                   double *h_delta, int *hash_n, int64_t *nnz, int *max_cell);
 
+/* Cell lists of the local map (Section 3.1.3): h_cell_off[N_L^dim + 1]
+ * (offsets into h_cell_el, cell (i, j, k) at i + N_L (j + N_L k)) and
+ * h_cell_el[nnz] (element ids, ascending within a cell), copied to host
+ * arrays sized by fpts_get_hash.  Either pointer may be NULL. */
+int fpts_get_cells(const fpts_mesh *m, int32_t *h_cell_off, int32_t *h_cell_el);
+
 /* Text of a status code. */
 const char *fpts_status_string(int status);
 

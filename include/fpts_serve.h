@@ -62,11 +62,16 @@ int fpts_server_add_mesh(fpts_server *s, fpts_mesh *m, int n_fields, const doubl
 
 /* Queue a request: n points d_pts [dim][n]; outputs as in fpts_find plus
  * d_out [n_fields][n] for the mesh's fields (may be NULL when the mesh has
- * no fields).  Returns immediately with *req_id.  FPTS_ENOMEM when the
- * request alone can never fit the budget; FPTS_EINVAL on bad arguments. */
+ * no fields).  stream: the caller's HIP stream (NULL: the null stream) on
+ * which the points are, or are being, written: the request's work waits for
+ * everything queued on it before this call, so points produced by
+ * asynchronous kernels or copies may be submitted at once.  The submission
+ * time is taken on entry.  Returns immediately with *req_id.  FPTS_ENOMEM
+ * when the request alone can never fit the budget; FPTS_EINVAL on bad
+ * arguments; FPTS_EDEVICE when the readiness event cannot be recorded. */
 int fpts_server_submit(fpts_server *s, int mesh_id, int64_t n, const double *d_pts,
                        int32_t *d_code, int32_t *d_elem, double *d_r, double *d_dist,
-                       double *d_out, int precision, int64_t *req_id);
+                       double *d_out, int precision, void *stream, int64_t *req_id);
 
 /* State of a request and its times in microseconds since the server was
  * created: submitted, launched, completed on the device (HIP events). */

@@ -60,6 +60,7 @@ def lib():
         L.orc_get_boxes.argtypes = [P, D, D, D, I]
         L.orc_get_hash.restype = ctypes.c_int
         L.orc_get_hash.argtypes = [P, D, ctypes.POINTER(ctypes.c_longlong)]
+        L.orc_get_cells.argtypes = [P, ctypes.POINTER(ctypes.c_longlong), I]
         L.orc_map.argtypes = [P, ctypes.c_longlong, D, D, D, D]
         L.orc_newton.argtypes = [P, ctypes.c_longlong, D, D, D, I, I]
         L.orc_find.argtypes = [P, ctypes.c_longlong, D, ctypes.c_int, I, I, D, D,
@@ -175,6 +176,15 @@ class Mesh:
         D = self.D
         return dict(NL=NL, lo=out[:D].copy(), hi=out[3:3 + D].copy(),
                     delta=out[6:6 + D].copy(), nnz=nnz.value)
+
+    def cells(self):
+        """Cell lists of the local map: offsets [N_L^D + 1], element ids."""
+        h = self.hash_info()
+        off = np.zeros(h["NL"] ** self.D + 1, dtype=np.int64)
+        el = np.zeros(max(h["nnz"], 1), dtype=np.int32)
+        lib().orc_get_cells(self._h, off.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)),
+                            _i(el))
+        return off, el[:h["nnz"]]
 
     def map(self, e, r):
         """x(r), G (D x R), H2 (D x R x R) of element e."""

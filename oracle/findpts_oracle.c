@@ -739,6 +739,13 @@ int orc_get_hash(const orc_mesh *m, double *out, long long *nnz)
     return m->NL;
 }
 
+/* cell lists: off[ncell+1], el[nnz] (ascending ids per cell) */
+void orc_get_cells(const orc_mesh *m, long long *off, int *el)
+{
+    if (off) memcpy(off, m->cell_off, sizeof(long long) * ((size_t)m->ncell + 1));
+    if (el) memcpy(el, m->cell_el, sizeof(int) * (size_t)m->cell_off[m->ncell]);
+}
+
 /* Box slacks of x against element e: AABB (eq. eq_AABB_test, inclusive) as
  * the smallest normalised distance to a face (negative outside) and OBB
  * (eq. eq_OBB_test) as 1 - ||Acute{J}^{-1}(x - Acute{x}_c)||_inf. */

@@ -603,6 +603,16 @@ int fpts_get_hash(const fpts_mesh *m, double *h_lo, double *h_hi, double *h_delt
     return FPTS_OK;
 }
 
+int fpts_get_cells(const fpts_mesh *m, int32_t *h_cell_off, int32_t *h_cell_el)
+{
+    if (!m) return FPTS_EINVAL;
+    if (h_cell_off)
+        std::copy(m->cell_off.begin(), m->cell_off.end(), h_cell_off);
+    if (h_cell_el)
+        std::copy(m->cell_el.begin(), m->cell_el.begin() + m->cell_off.back(), h_cell_el);
+    return FPTS_OK;
+}
+
 
 size_t fpts_lpt_workspace_size(const fpts_mesh *m, int64_t n)
 {

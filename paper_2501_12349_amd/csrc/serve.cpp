@@ -75,6 +75,7 @@ struct Req {
     int state = FPTS_REQ_QUEUED;
     double t_submit = 0, t_start = 0, t_done = 0;
     int64_t offset = 0;     // position in its batch
+    hipEvent_t ready = nullptr;   // inputs written (recorded on the caller's stream)
 };
 
 struct MeshEntry {
@@ -103,8 +104,10 @@ struct fpts_server {
     std::vector<bool> busy;
     hipEvent_t ref_ev = nullptr;
     std::chrono::steady_clock::time_point t0;
-    std::vector<MeshEntry> meshes;
-    std::vector<Req> reqs;
+    // deques: elements keep their addresses when submit / add_mesh append,
+    // so the worker reads them while it launches without holding the lock
+    std::deque<MeshEntry> meshes;
+    std::deque<Req> reqs;
     std::deque<int64_t> pending;
     std::vector<Batch> running;
     std::mutex mu;
@@ -147,11 +150,14 @@ size_t batch_bytes(const fpts_server *s, int mesh, int64_t ntot, size_t nreq)
     return b;
 }
 
-bool launch(fpts_server *s, Batch &b)
+// Enqueue one batch on its stream.  Runs without the server lock: the
+// requests and the mesh entry are passed by address (taken under the lock;
+// deque elements do not move), and nothing here writes shared state.
+bool launch(fpts_server *s, const Batch &b, const std::vector<const Req *> &rq,
+            const MeshEntry &me)
 {
     hipStream_t st = s->streams[b.stream];
-    const Req &r0 = s->reqs[b.reqs[0]];
-    const MeshEntry &me = s->meshes[r0.mesh];
+    const Req &r0 = *rq[0];
     const int D = me.m->D, R = me.m->R, nf = me.n_fields;
     char *base = s->pool_mem + b.off;
     const int64_t n = b.ntot;
@@ -165,6 +171,8 @@ bool launch(fpts_server *s, Batch &b)
         if (bytes && hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
             ok = false;
     };
+    for (const Req *q : rq)
+        if (hipStreamWaitEvent(st, q->ready, 0) != hipSuccess) ok = false;
     if (b.reqs.size() == 1) {
         pts = r0.pts;
         code = r0.code;
@@ -187,8 +195,8 @@ bool launch(fpts_server *s, Batch &b)
         p += up(sizeof(double) * n);
         out = reinterpret_cast<double *>(p);
         ws = base;
-        for (int64_t id : b.reqs) {
-            const Req &q = s->reqs[id];
+        for (const Req *qp : rq) {
+            const Req &q = *qp;
             for (int d = 0; d < D; ++d)
                 cp(pts_b + d * n + q.offset, q.pts + d * q.n, sizeof(double) * q.n);
         }
@@ -204,8 +212,8 @@ bool launch(fpts_server *s, Batch &b)
         return false;
     }
     if (b.reqs.size() > 1) {
-        for (int64_t id : b.reqs) {
-            const Req &q = s->reqs[id];
+        for (const Req *qp : rq) {
+            const Req &q = *qp;
             cp(q.code, code + q.offset, sizeof(int32_t) * q.n);
             cp(q.elem, elem + q.offset, sizeof(int32_t) * q.n);
             cp(q.dist, dist + q.offset, sizeof(double) * q.n);
@@ -230,6 +238,10 @@ void finish(fpts_server *s, Batch &b, bool failed)
         Req &q = s->reqs[id];
         q.state = failed ? FPTS_REQ_FAILED : FPTS_REQ_DONE;
         q.t_done = t;
+        if (q.ready) {
+            (void)hipEventDestroy(q.ready);
+            q.ready = nullptr;
+        }
         if (failed) s->st.failed++;
         else s->st.completed++;
     }
@@ -304,9 +316,20 @@ void worker_loop(fpts_server *s)
             for (int64_t id : b.reqs)
                 s->pending.erase(std::find(s->pending.begin(), s->pending.end(), id));
             s->busy[sidx] = true;
-            if (!launch(s, b)) {
+            // enqueue without the lock: submissions meanwhile are neither
+            // blocked nor delayed (their timestamps are taken before they
+            // lock in any case)
+            std::vector<const Req *> rq;
+            for (int64_t id : b.reqs) rq.push_back(&s->reqs[id]);
+            const MeshEntry *me = &s->meshes[s->reqs[b.reqs[0]].mesh];
+            lk.unlock();
+            const bool launched = launch(s, b, rq, *me);
+            if (!launched) {
                 (void)hipGetLastError();
                 (void)hipStreamSynchronize(s->streams[sidx]);
+            }
+            lk.lock();
+            if (!launched) {
                 finish(s, b, true);
                 s->cv_done.notify_all();
                 continue;
@@ -409,16 +432,30 @@ int fpts_server_add_mesh(fpts_server *s, fpts_mesh *m, int n_fields, const doubl
 
 int fpts_server_submit(fpts_server *s, int mesh_id, int64_t n, const double *d_pts,
                        int32_t *d_code, int32_t *d_elem, double *d_r, double *d_dist,
-                       double *d_out, int precision, int64_t *req_id)
+                       double *d_out, int precision, void *stream, int64_t *req_id)
 {
     if (!s || !req_id || n < 1 || !d_pts || !d_code || !d_elem || !d_r || !d_dist)
         return FPTS_EINVAL;
     if (precision != FPTS_FP64 && precision != FPTS_MIXED) return FPTS_EINVAL;
+    const double t_submit = now_us(s);
+    hipEvent_t ready = nullptr;
+    if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ready, (hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        if (ready) (void)hipEventDestroy(ready);
+        return FPTS_EDEVICE;
+    }
     std::unique_lock<std::mutex> lk(s->mu);
-    if (mesh_id < 0 || mesh_id >= (int)s->meshes.size()) return FPTS_EINVAL;
-    if (s->meshes[mesh_id].n_fields > 0 && !d_out) return FPTS_EINVAL;
-    if (n > s->max_batch) return FPTS_EINVAL;
-    if (batch_bytes(s, mesh_id, n, 1) > s->budget) return FPTS_ENOMEM;
+    int bad = FPTS_OK;
+    if (mesh_id < 0 || mesh_id >= (int)s->meshes.size()) bad = FPTS_EINVAL;
+    else if (s->meshes[mesh_id].n_fields > 0 && !d_out) bad = FPTS_EINVAL;
+    else if (n > s->max_batch) bad = FPTS_EINVAL;
+    else if (batch_bytes(s, mesh_id, n, 1) > s->budget) bad = FPTS_ENOMEM;
+    if (bad != FPTS_OK) {
+        lk.unlock();
+        (void)hipEventDestroy(ready);
+        return bad;
+    }
     Req q;
     q.mesh = mesh_id;
     q.n = n;
@@ -429,7 +466,8 @@ int fpts_server_submit(fpts_server *s, int mesh_id, int64_t n, const double *d_p
     q.dist = d_dist;
     q.out = d_out;
     q.precision = precision;
-    q.t_submit = now_us(s);
+    q.t_submit = t_submit;
+    q.ready = ready;
     s->reqs.push_back(q);
     *req_id = (int64_t)s->reqs.size() - 1;
     s->pending.push_back(*req_id);

@@ -19,7 +19,7 @@ EXPORTS = ("fpts_params_default", "fpts_setup", "fpts_destroy", "fpts_update_nod
            "fpts_find_workspace_size", "fpts_find", "fpts_eval_workspace_size",
            "fpts_eval", "fpts_eval_order", "fpts_find_eval_workspace_size", "fpts_find_eval",
            "fpts_find_stats_get", "fpts_profile", "fpts_profile_read",
-           "fpts_get_boxes", "fpts_get_hash", "fpts_status_string")
+           "fpts_get_boxes", "fpts_get_hash", "fpts_get_cells", "fpts_status_string")
 
 # Entry points declared in include/fpts_lpt.h.
 LPT_EXPORTS = ("fpts_lpt_workspace_size", "fpts_lpt_step")
@@ -112,6 +112,7 @@ def load_library(path=LIB_PATH):
     L.fpts_get_boxes.argtypes = [vp, vp, vp, vp]
     L.fpts_get_hash.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i32),
                                 ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    L.fpts_get_cells.argtypes = [vp, vp, vp]
     L.fpts_lpt_workspace_size.argtypes = [vp, i64]
     L.fpts_lpt_workspace_size.restype = ctypes.c_size_t
     L.fpts_lpt_step.argtypes = [vp, ctypes.POINTER(LptParams), i64, i32, vp, vp, vp, vp, vp,
@@ -121,7 +122,7 @@ def load_library(path=LIB_PATH):
     L.fpts_server_create.argtypes = [ctypes.c_size_t, i32, i64, ctypes.POINTER(vp)]
     L.fpts_server_destroy.argtypes = [vp]
     L.fpts_server_add_mesh.argtypes = [vp, vp, i32, vp, ctypes.POINTER(i32)]
-    L.fpts_server_submit.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, i32,
+    L.fpts_server_submit.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, i32, vp,
                                      ctypes.POINTER(i64)]
     L.fpts_server_poll.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(dbl),
                                    ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
@@ -377,6 +378,14 @@ class Mesh:
                                             ctypes.byref(nnz), ctypes.byref(mc)))
         return dict(NL=nl.value, lo=lo, hi=hi, delta=de, nnz=nnz.value, max_cell=mc.value)
 
+    def cells(self):
+        """Cell lists of the local map: offsets [N_L^dim + 1], element ids."""
+        h = self.hash_info()
+        off = np.zeros(h["NL"] ** self.dim + 1, dtype=np.int32)
+        el = np.zeros(max(h["nnz"], 1), dtype=np.int32)
+        _check(load_library().fpts_get_cells(self._h, off.ctypes.data, el.ctypes.data))
+        return off, el[:h["nnz"]]
+
 
 class Particles:
     """Device state of n particles for Mesh.lpt_step: positions x and
@@ -463,10 +472,13 @@ class Server:
                     dist=torch.empty(n, dtype=torch.float64, device=device),
                     u=torch.empty((max(nf, 1), n), dtype=torch.float64, device=device))
 
-    def submit(self, mesh_id, pts, precision="fp64", out=None):
+    def submit(self, mesh_id, pts, precision="fp64", out=None, stream=None):
         """Queue find + eval of pts ([dim][n] float64 on the device) into out
         (from outputs(); allocated here when None); returns (request id,
-        output dict)."""
+        output dict).  The request waits for the work queued on ``stream``
+        (default: torch's current stream) before it reads the points, so a
+        non-contiguous input copied here, or points still being produced,
+        are safe."""
         mesh, field, nf = self._meshes[mesh_id]
         pts = pts.contiguous()
         n = pts.shape[1]
@@ -476,7 +488,7 @@ class Server:
         _check(load_library().fpts_server_submit(
             self._h, mesh_id, n, _dptr(pts), _dptr(out["code"]), _dptr(out["elem"]),
             _dptr(out["r"]), _dptr(out["dist"]), _dptr(out["u"]) if nf else ctypes.c_void_p(),
-            _PREC[precision], ctypes.byref(rid)))
+            _PREC[precision], _stream_ptr(stream), ctypes.byref(rid)))
         self._live[rid.value] = (pts, out)
         return rid.value, out
 

@@ -6,7 +6,12 @@ inputs can change the answer) must match exactly in element and code, with
 element face, at a box boundary, with two candidates at nearly equal
 distance, or at the surface threshold) must carry a valid answer: a real
 element whose map at the returned r reproduces the returned distance, no
-worse than the oracle's best, and consistent with its code."""
+worse than the oracle's best, and consistent with its code.
+
+The ambiguous set is bounded: a margin mistake that moved many points out of
+the exact comparison fails on its size (at most max_ambiguous of the points,
+and never more than 5 on small sets).  On random points the share is below
+10^-4; constructed sets of face and corner points opt out."""
 import numpy as np
 
 import oracle
@@ -30,13 +35,16 @@ def ambiguous(orc, surface=False):
     return amb
 
 
-def compare_find(omesh, pts, orc, gpu, h, surface=False, r_tol=R_TOL, d_tol=D_TOL):
+def compare_find(omesh, pts, orc, gpu, h, surface=False, r_tol=R_TOL, d_tol=D_TOL,
+                 max_ambiguous=0.01):
     """Returns a report dict; raises AssertionError on any violation."""
     code_g, elem_g = gpu["code"], gpu["elem"]
     r_g, dist_g = gpu["r"], gpu["dist"]
     amb = ambiguous(orc, surface)
     una = ~amb
     rep = dict(n=len(code_g), ambiguous=int(amb.sum()))
+    assert amb.sum() <= max(5, max_ambiguous * len(code_g)), \
+        "%d of %d points ambiguous" % (amb.sum(), len(code_g))
     bad_code = una & (code_g != orc["code"])
     bad_elem = una & (elem_g != orc["elem"])
     assert not bad_code.any(), "code mismatch at %s" % np.nonzero(bad_code)[0][:10]

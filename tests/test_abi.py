@@ -76,7 +76,8 @@ def test_server_rejects_bad_arguments_without_device(budget, streams, maxb):
     assert L.fpts_server_create(budget, streams, maxb, ctypes.byref(h)) == -1
     assert not h.value
     assert L.fpts_server_destroy(None) == 0
-    assert L.fpts_server_submit(None, 0, 10, None, None, None, None, None, None, 0, None) == -1
+    assert L.fpts_server_submit(None, 0, 10, None, None, None, None, None, None, 0, None,
+                                None) == -1
 
 
 def test_lpt_rejects_bad_arguments_without_device():

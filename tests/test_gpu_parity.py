@@ -29,11 +29,12 @@ def _run(wl, pts, precision="fp64", fields=True):
     return gm, to_np(res), out
 
 
-def _check(wl, pts, precision="fp64", surface=False):
+def _check(wl, pts, precision="fp64", surface=False, max_ambiguous=0.01):
     om = oracle.Mesh(wl["nodes"], wl["dim"], wl["ref_dim"], wl["N"])
     orc = om.find(pts)
     gm, gpu, u = _run(wl, pts, precision)
-    rep = compare_find(om, pts, orc, gpu, wl["h"], surface=surface)
+    rep = compare_find(om, pts, orc, gpu, wl["h"], surface=surface,
+                       max_ambiguous=max_ambiguous)
     if u is not None:
         uo = om.eval(orc, wl["fields"])
         # compare eval on the GPU's own coordinates where they agree with the
@@ -93,7 +94,7 @@ def test_invalid_and_far_points():
     gm, gpu, _ = _run(wl, pts, fields=False)
     assert np.all(gpu["code"][:7] == oracle.NOT_FOUND)
     assert np.all(gpu["elem"][:7] == -1)
-    compare_find(om, pts, orc, gpu, wl["h"])
+    compare_find(om, pts, orc, gpu, wl["h"], max_ambiguous=1.0)
 
 
 def test_all_points_in_one_element_many_chunks():
@@ -114,7 +115,8 @@ def test_points_at_nodes_and_corners():
     nodes = wl["nodes"]
     sel = nodes[::97]                          # every 97th element
     pts = np.ascontiguousarray(np.moveaxis(sel, 1, 0).reshape(3, -1))
-    _check(dict(wl, fields=None), pts)
+    # every point sits on a node: corners and faces are ambiguous by design
+    _check(dict(wl, fields=None), pts, max_ambiguous=1.0)
 
 
 def test_recovery_hex_gpu():
