@@ -286,7 +286,8 @@ def particle_tracking(ratios, steps, warmup, precision):
         gm.profile(False)
         lost = int((P.find["code"] == fpts.NOT_FOUND).sum().item())
         c = max(kt["lpt_calls"], 1)
-        find_ms = (kt["locate_ms"] + kt["nearest_ms"] + kt["newton_ms"] + kt["select_ms"]) / c
+        find_ms = (kt["locate_ms"] + kt["nearest_ms"] + kt["newton_ms"] + kt["face_ms"] +
+                   kt["select_ms"]) / c
         interp_ms = (kt["eval_bin_ms"] + kt["eval_ms"]) / c
         adv_ms = kt["advance_ms"] / c
         tot = find_ms + interp_ms + adv_ms
@@ -349,7 +350,8 @@ def line_surface(level, steps, warmup):
     gm.profile(False)
     stats = gm.find_stats()
     c = max(kt["find_calls"], 1)
-    find_ms = (kt["locate_ms"] + kt["nearest_ms"] + kt["newton_ms"] + kt["select_ms"]) / c
+    find_ms = (kt["locate_ms"] + kt["nearest_ms"] + kt["newton_ms"] + kt["face_ms"] +
+                   kt["select_ms"]) / c
     eval_ms = (kt["eval_bin_ms"] + kt["eval_ms"]) / max(kt["eval_calls"], 1)
     codes = torch.bincount(out["code"].long(), minlength=3).cpu().tolist()
     log("line2d %d elements, %d points: %.3f ms/step  %.1f Mpts/s  find %.3f eval %.3f ms  "
@@ -500,11 +502,11 @@ def main():
         results[mode] = dict(ms_per_step=ms, mpts=n / (dt / args.steps) / 1e6, kt=kt,
                              newton_ms=newton_ms, stats=stats, stats_all=stats_all, flops=fl,
                              codes=codes, snap=snap, snap_u=snap_u)
-        log("%s: %.3f ms/step  %.1f Mpts/s  k_newton %.3f ms (%.1f TFLOP/s)  nearest %.3f "
-            "locate %.3f select %.3f eval_bin %.3f eval %.3f ms/call  codes %s  slots %s  "
-            "stats %s" % (
+        log("%s: %.3f ms/step  %.1f Mpts/s  k_newton %.3f ms (%.1f TFLOP/s)  face %.3f  "
+            "nearest %.3f locate %.3f select %.3f eval_bin %.3f eval %.3f ms/call  codes %s  "
+            "slots %s  stats %s" % (
                 mode, ms, n / (dt / args.steps) / 1e6, newton_ms, fl / newton_ms / 1e9,
-                kt["nearest_ms"] / kt["find_calls"],
+                kt["face_ms"] / kt["find_calls"], kt["nearest_ms"] / kt["find_calls"],
                 kt["locate_ms"] / kt["find_calls"], kt["select_ms"] / kt["find_calls"],
                 kt["eval_bin_ms"] / kt["eval_calls"], kt["eval_ms"] / kt["eval_calls"],
                 codes, slot_use(stats), stats_all))
@@ -567,8 +569,9 @@ def main():
                          "newton_kernel_ms": round(rm["newton_ms"], 4)}
     kt = r0["kt"]
     line["kernel_ms"] = {k: round(kt[k + "_ms"] / max(kt["find_calls" if k in
-                         ("locate", "nearest", "newton", "select") else "eval_calls"], 1), 4)
-                         for k in ("locate", "nearest", "newton", "select", "eval_bin", "eval")}
+                         ("locate", "nearest", "newton", "face", "select") else "eval_calls"], 1), 4)
+                         for k in ("locate", "nearest", "newton", "face", "select", "eval_bin",
+                                   "eval")}
     line["newton_stats"] = {"primary": r0["stats"], "all": r0["stats_all"]}
     line["separate_calls"] = {"value": round(n / dt_sep / 1e6, 3), "unit": "Mpts/s",
                               "ms_per_step": round(dt_sep * 1e3, 4),

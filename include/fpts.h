@@ -199,10 +199,15 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
 
 /* Counters of the last fpts_find that used workspace d_ws (read back with a
  * device-to-host copy on `stream`, which is synchronised) for one Newton
- * pass: pass 1 = primary candidates, 2 = the other candidates of points the
- * primary did not settle, 0 = both summed.  A sweep is one evaluation of the
- * map by a whole wavefront at up to 16 pairs at once, so evals / (16 sweeps)
- * is the fraction of busy pair slots.  FPTS_EINVAL for another pass. */
+ * launch: pass 1 = primary candidates, 2 = the other candidates of points the
+ * primary did not settle, 3 = the face passes of primary pairs (a pair whose
+ * next pass needs second derivatives, eq. eq_newton_hessian, leaves the
+ * primary kernel and resumes there, many such pairs to a wavefront), 0 = all
+ * summed.  Passes and evaluations of a pair that moved to the face kernel
+ * are counted where they ran; its pair is counted once, in pass 1.  A sweep
+ * is one evaluation of the map by a whole wavefront at up to 16 pairs at
+ * once, so evals / (16 sweeps) is the fraction of busy pair slots.
+ * FPTS_EINVAL for another pass. */
 typedef struct fpts_find_stats {
     int64_t pairs;          /* (point, element) pairs searched */
     int64_t passes;         /* FP64 Newton passes */
@@ -216,6 +221,10 @@ typedef struct fpts_find_stats {
     int64_t sweeps;         /* FP64 first-derivative sweeps */
     int64_t sweeps_h2;      /* FP64 second-derivative sweeps */
     int64_t sweeps_fp32;    /* FP32 sweeps of mixed mode (both kinds) */
+    int64_t overflow_points;  /* unsettled points whose other candidates did
+                                 not fit the workspace's slots and were
+                                 searched one point per wavefront (any
+                                 pass) */
 } fpts_find_stats;
 
 int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws,
@@ -227,7 +236,8 @@ int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws,
  * primary pass), newton (the trust-region Newton kernel of the primary pass
  * alone), select (start, Newton and selection over the other candidates of
  * unsettled points), eval_bin and eval (point binning and interpolation),
- * advance (the particle update of fpts_lpt_step, fpts_lpt.h).  Sums over
+ * advance (the particle update of fpts_lpt_step, fpts_lpt.h), face (the
+ * face passes of primary pairs and their binning).  Sums over
  * the calls since profiling was enabled.  Meant for one stream at a time. */
 typedef struct fpts_kernel_times {
     double locate_ms;
@@ -237,6 +247,8 @@ typedef struct fpts_kernel_times {
     double eval_bin_ms;
     double eval_ms;
     double advance_ms;
+    double face_ms;         /* the parked face passes of the primary
+                               candidates, with their binning */
     int64_t find_calls;
     int64_t eval_calls;
     int64_t lpt_calls;

@@ -32,17 +32,21 @@ bool sticky_error()
     return e != hipSuccess;
 }
 
+
 template <class T>
 T *at(void *base, size_t off)
 {
     return reinterpret_cast<T *>(static_cast<char *>(base) + off);
 }
 
-constexpr int kCounters = 64;   // ints: 0, 1 the second search's list and slot counts;
+constexpr int kCounters = 64;   // ints: 0 the second search's list count, 2 to 5 below;
                                  // from 16 on the Newton passes' element-queue counters
 constexpr int kNewtonCounters = 16;   // each Newton pass owns 16 counters from here on
 static_assert(3 * kNewtonCounters <= kCounters, "the two Newton passes need disjoint counters");
 constexpr int kStats = 16;      // unsigned long long: Newton counters per pass
+constexpr int kParkCount = 2;   // int counter of the parked pairs
+constexpr int kOverflowCount = 3;   // int counter of the overflowed points
+constexpr int kSlotTotal = 4;   // 64-bit running total of the second search's slots (ints 4, 5)
 constexpr int kHintPasses = 8;  // Newton passes of the hinted search
 
 void clear_events(fpts_mesh *m)
@@ -106,7 +110,13 @@ FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
     int64_t ncell = 1;
     for (int d = 0; d < m->D; ++d) ncell *= m->NL;
     w.ncell = ncell;
-    w.cap2 = std::max<int64_t>(1, n * (int64_t)std::max(m->max_cell - 1, 1));
+    // slots for the other candidates of unsettled points: one per point (a
+    // few per cent of the points are unsettled on volume meshes, about a
+    // quarter of a slot per point on surfaces); points beyond the capacity
+    // are searched one per wavefront (overflow path).  Line meshes keep the
+    // exact bound (their kernel has no overflow path).
+    const int64_t cmax = n * (int64_t)std::max(m->max_cell - 1, 1);
+    w.cap2 = std::max<int64_t>(1, m->R == 1 ? cmax : std::min<int64_t>(cmax, n));
     w.scan_blocks = scan_tmp_blocks(std::max<int64_t>(std::max<int64_t>(n, m->nel), ncell));
     const size_t I = sizeof(int);
     w.cell_cnt = c.take(I * ncell);
@@ -144,8 +154,22 @@ FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
     w.scan_tmp = c.take(I * w.scan_blocks);
     w.pts4 = c.take(m->R >= 2 ? sizeof(double) * pt_stride(m->D) * n : 1);
     w.start = c.take(sizeof(double) * m->R * n);
+    // parked pairs of the primary pass (at most one per point)
+    w.park_meta = c.take(sizeof(int4) * n);
+    w.park_r = c.take(sizeof(double) * (m->R + 1) * n);
+    w.park_cnt = c.take(I * m->nel);
+    w.park_off = c.take(I * (m->nel + 1));
+    w.park_choff = c.take(I * (m->nel + 1));
+    w.park_rank = c.take(I * n);
+    w.park_sorted = c.take(I * n);
+    w.tb_park = task_bound(n, m->nel);
+    w.park_task = c.take(I * w.tb_park);
+    w.olist = c.take(I * n);
+    w.ov_grid = (int64_t)m->cus * 4;
+    w.ov_int = c.take(I * 3 * w.ov_grid);
+    w.ov_dbl = c.take(sizeof(double) * (m->R + 1) * w.ov_grid);
     w.counters = c.take(I * kCounters);
-    w.stats = c.take(sizeof(unsigned long long) * 2 * kStats);
+    w.stats = c.take(sizeof(unsigned long long) * 3 * kStats);
     w.total = c.at;
     return w;
 }
@@ -220,6 +244,13 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     // kernel reads the [D][n] coordinates)
     double *pts4 = m->R >= 2 ? at<double>(d_ws, w.pts4) : nullptr;
     double *start = at<double>(d_ws, w.start);
+    int4 *park_meta = at<int4>(d_ws, w.park_meta);
+    double *park_r = at<double>(d_ws, w.park_r);
+    int *park_cnt = at<int>(d_ws, w.park_cnt), *park_off = at<int>(d_ws, w.park_off);
+    int *park_choff = at<int>(d_ws, w.park_choff), *park_rank = at<int>(d_ws, w.park_rank);
+    int *park_sorted = at<int>(d_ws, w.park_sorted), *park_task = at<int>(d_ws, w.park_task);
+    int *olist = at<int>(d_ws, w.olist), *ov_int = at<int>(d_ws, w.ov_int);
+    double *ov_dbl = at<double>(d_ws, w.ov_dbl);
     unsigned long long *stats = at<unsigned long long>(d_ws, w.stats);
     const int64_t nel = m->nel, ncell = w.ncell, tb = w.scan_blocks;
     hipError_t e = hipSuccess;
@@ -232,8 +263,9 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         chk(launch_fill_i32(elem_cnt, nel, 0, s));
         chk(launch_fill_i32(elem_cnt2, nel, 0, s));
         chk(launch_fill_i32(elem_fill2, nel, 0, s));
+        chk(launch_fill_i32(park_cnt, nel, 0, s));
         chk(launch_fill_i32(counters, kCounters, 0, s));
-        chk(launch_fill_i32(reinterpret_cast<int *>(stats), 4 * kStats, 0, s));
+        chk(launch_fill_i32(reinterpret_cast<int *>(stats), 6 * kStats, 0, s));
         chk(launch_cell_bin(m, 0, n, d_pts, pts4, keep, cellpt, cell_cnt, nullptr, rank, nullptr,
                             ncand, primary, d_code, d_elem, d_r, d_dist, s));
         chk(launch_exclusive_scan(cell_cnt, cell_poff, ncell, 1, tmp, tb, s));
@@ -258,27 +290,55 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         if (m->R >= 2) {
             io.start = start;
             io.start_stride = n;
+            // pairs that reach a face leave the primary kernel's waves
+            io.park_meta = park_meta;
+            io.park_r = park_r;
+            io.park_cap = n;
+            io.park_count = counters + kParkCount;
+            io.polish = precision == FPTS_MIXED && m->R == m->D;
         }
         {
             Span sp(m, 1, s);
             chk(launch_newton(m, precision, n, d_pts, io, 1, s));
         }
-        Span sp(m, 2, s);
-        chk(launch_newton(m, precision, n, d_pts, io, 2, s));
+        {
+            Span sp(m, 2, s);
+            chk(launch_newton(m, precision, n, d_pts, io, 2, s));
+        }
+        if (m->R >= 2) {
+            // the parked pairs, binned by element, go on in the face kernel
+            Span sp(m, 7, s);
+            chk(launch_park_bin(0, park_meta, counters + kParkCount, n, park_cnt, nullptr,
+                                park_rank, nullptr, m->cus, s));
+            chk(launch_exclusive_scan(park_cnt, park_off, nel, 1, tmp, tb, s));
+            chk(launch_exclusive_scan(park_cnt, park_choff, nel, kChunk, tmp, tb, s));
+            chk(launch_task_map(park_choff, nel, park_task, s));
+            chk(launch_park_bin(1, park_meta, counters + kParkCount, n, nullptr, park_off,
+                                park_rank, park_sorted, m->cus, s));
+            NewtonIO fio{park_sorted, park_off, park_choff, nullptr, d_code, d_elem, d_r, n,
+                         d_dist, nullptr, stats + 2 * kStats, park_task, w.tb_park, rs, n};
+            fio.pts4 = pts4;
+            fio.park_meta = park_meta;
+            fio.park_r = park_r;
+            fio.park_cap = n;
+            chk(launch_newton(m, FPTS_FP64, n, d_pts, fio, 4, s));
+        }
     }
     {   // phase D: other candidates of unsettled points, then the selection rule
         Span sp(m, 3, s);
         // counters[0]: listed points, counters[1]: slots handed out
         chk(launch_unsettled(m, n, cellpt, ncand, primary, d_code, d_r, ulist, counters, s));
+        unsigned long long *slot_total =
+            reinterpret_cast<unsigned long long *>(counters + kSlotTotal);
         chk(launch_resolve(m, 0, n, d_pts, cellpt, primary, ulist, counters, uoff, ucnt,
-                           counters + 1, elem_cnt2, nullptr, nullptr, nullptr, nullptr, nullptr,
-                           s));
+                           slot_total, elem_cnt2, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           w.cap2, olist, counters + kOverflowCount, s));
         chk(launch_exclusive_scan(elem_cnt2, elem_off2, nel, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt2, chunk_off2, nel, kChunk, tmp, tb, s));
         chk(launch_task_map(chunk_off2, nel, task_elem2, s));
         chk(launch_resolve(m, 1, n, d_pts, cellpt, primary, ulist, counters, uoff, ucnt,
                            nullptr, nullptr, elem_off2, elem_fill2, slot_pt, slot_elem, sorted2,
-                           s));
+                           w.cap2, nullptr, nullptr, s));
         NewtonIO io{sorted2, elem_off2, chunk_off2, slot_pt, res_code, nullptr, res_r, w.cap2,
                     res_dist, counters + 2 * kNewtonCounters, stats + kStats, task_elem2,
                     w.tb_elem2};
@@ -288,6 +348,19 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         chk(launch_newton(m, FPTS_FP64, n, d_pts, io, 3, s));
         chk(launch_select2(m, n, ulist, counters, uoff, ucnt, primary, slot_elem, w.cap2, res_r,
                            res_dist, res_code, d_code, d_elem, d_r, d_dist, s));
+        if (m->R >= 2) {
+            // points whose other candidates did not fit the slots (none in
+            // the common case: the kernel reads the count and returns)
+            NewtonIO oio{olist, nullptr, nullptr, nullptr, d_code, d_elem, d_r, n, d_dist,
+                         nullptr, stats + kStats, nullptr, w.ov_grid};
+            oio.pts4 = pts4;
+            oio.ocount = counters + kOverflowCount;
+            oio.cellpt = cellpt;
+            oio.primary = primary;
+            oio.ov_int = ov_int;
+            oio.ov_dbl = ov_dbl;
+            chk(launch_newton(m, FPTS_FP64, n, d_pts, oio, 8, s));
+        }
     }
     if (m->profiling) m->prof_find++;
     return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;
@@ -491,16 +564,23 @@ int fpts_eval_order(fpts_mesh *m, int64_t n, const int32_t *d_code, const int32_
 int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws, int pass,
                         fpts_find_stats *out, void *stream)
 {
-    if (!m || !d_ws || !out || n < 0 || pass < 0 || pass > 2) return FPTS_EINVAL;
+    if (!m || !d_ws || !out || n < 0 || pass < 0 || pass > 3) return FPTS_EINVAL;
     const FindWs w = find_ws_layout(m, n);
-    unsigned long long both[2 * kStats] = {0}, v[kStats] = {0};
+    unsigned long long all[3 * kStats] = {0}, v[kStats] = {0};
     hipStream_t s = (hipStream_t)stream;
-    if (hipMemcpyAsync(both, static_cast<const char *>(d_ws) + w.stats, sizeof(both),
+    if (hipMemcpyAsync(all, static_cast<const char *>(d_ws) + w.stats, sizeof(all),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return FPTS_EDEVICE;
+    int ctr[kCounters] = {0};
+    if (hipMemcpyAsync(ctr, static_cast<const char *>(d_ws) + w.counters, sizeof(ctr),
                        hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return FPTS_EDEVICE;
     for (int k = 0; k < kStats; ++k)
-        v[k] = (pass != 2 ? both[k] : 0) + (pass != 1 ? both[kStats + k] : 0);
+        for (int q = 0; q < 3; ++q)
+            if (pass == 0 || pass == q + 1) v[k] += all[q * kStats + k];
+    out->overflow_points = ctr[kOverflowCount];
     out->pairs = (int64_t)v[0];
     out->passes = (int64_t)v[1];
     out->evals = (int64_t)v[2];
@@ -542,6 +622,7 @@ int fpts_profile_read(fpts_mesh *m, fpts_kernel_times *out)
     out->eval_bin_ms = ms[4];
     out->eval_ms = ms[5];
     out->advance_ms = ms[6];
+    out->face_ms = ms[7];
     out->find_calls = m->prof_find;
     out->eval_calls = m->prof_eval;
     out->lpt_calls = m->prof_lpt;
@@ -699,7 +780,7 @@ int fpts_lpt_step(fpts_mesh *m, const fpts_lpt_params *p, int64_t n, int first, 
         Span sp(m, 0, s);
         chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
         chk(launch_fill_i32(counters, kCounters, 0, s));
-        chk(launch_fill_i32(reinterpret_cast<int *>(stats), 4 * kStats, 0, s));
+        chk(launch_fill_i32(reinterpret_cast<int *>(stats), 6 * kStats, 0, s));
         chk(launch_hint(m, 0, n, d_code, d_elem, d_r, primary, elem_cnt, rank, nullptr, s));
         chk(launch_exclusive_scan(elem_cnt, elem_off, m->nel, 1, tmp, w.scan_blocks, s));
         chk(launch_exclusive_scan(elem_cnt, chunk_off, m->nel, kChunk, tmp, w.scan_blocks, s));

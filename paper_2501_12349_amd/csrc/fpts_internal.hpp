@@ -135,15 +135,42 @@ __device__ __forceinline__ int wave_inc(int *ctr, int key, bool active)
     return out;
 }
 
+// Box filter of one element record (eq. eq_AABB_test, then eq. eq_OBB_test);
+// `depth` receives ||A(x - c)||_inf, the point's OBB depth (smaller =
+// deeper).  Inclusive tests.
+template <int D, typename P>
+__device__ inline bool box_pass(P rec, const double *x, double &depth)
+{
+    bool in = true;
+#pragma unroll
+    for (int d = 0; d < D; ++d) in = in && ((x[d] - rec[d]) * (rec[D + d] - x[d]) >= 0.0);
+    double y[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) y[d] = x[d] - rec[2 * D + d];
+    double mx = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double t = 0.0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) t += rec[3 * D + a * D + b] * y[b];
+        mx = fmax(mx, fabs(t));
+    }
+    depth = mx;
+    return in && (mx <= 1.0);
+}
+
 struct FindWs {
     size_t cell_cnt, cell_poff, cell_choff, cellpt, pbin, ncand, primary, rank, bin_prim,
         elem_cnt, elem_off, chunk_off, sorted, ulist, uoff, ucnt, elem_cnt2, elem_fill2,
         elem_off2, chunk_off2, slot_pt, slot_elem, sorted2, res_r, res_dist, res_code,
-        task_cell, task_elem, task_elem2, scan_tmp, counters, stats, pts4, start, total;
+        task_cell, task_elem, task_elem2, scan_tmp, counters, stats, pts4, start, park_meta,
+        park_r, park_cnt, park_off, park_choff, park_rank, park_sorted, park_task, olist, ov_int,
+        ov_dbl, total;
     int64_t cap2;           // capacity for second-pass (point, candidate) pairs
     int64_t scan_blocks;
     int64_t ncell;
-    int64_t tb_cell, tb_elem, tb_elem2;   // task bounds
+    int64_t tb_cell, tb_elem, tb_elem2, tb_park;   // task bounds
+    int64_t ov_grid;        // blocks of the overflow search (its scratch)
 };
 
 struct EvalWs {
@@ -186,13 +213,43 @@ struct NewtonIO {
     // order, without a gather
     double *start;
     int64_t start_stride;
+    // optional (primary FP64 pass): a pair whose next pass needs second
+    // derivatives (a pass on a face, eq. eq_newton_hessian) leaves its wave
+    // and is parked: park_meta[k] = {item, list position, element, passes
+    // so far}, park_r[j * park_cap + k] = r_j (j < R) and the trust-region
+    // radius alpha (j = R); *park_count counts the parked pairs (at most
+    // park_cap, one per pair of the pass).  The face kernel resumes them,
+    // binned by element, with list = park indices.
+    int4 *park_meta;
+    double *park_r;
+    int64_t park_cap;
+    int *park_count;
+    // mixed mode, FP64 phase of a volume mesh: when the first FP64 Newton
+    // step from the FP32 result is below kPolishTol and off the faces, that
+    // step ends the iteration (one FP64 evaluation per pair)
+    int polish;
+    // overflow search (which & 8): list = overflowed points, *ocount of
+    // them; their cells and primaries; per-block scratch ov_int [3][grid]
+    // and ov_dbl [R + 1][grid]; code/elem/r/dist are the final outputs
+    const int *ocount;
+    const int *cellpt;
+    const int *primary;
+    int *ov_int;
+    double *ov_dbl;
 };
+
+// Largest first FP64 step from the FP32 result that ends the iteration in
+// mixed mode.  Newton converges quadratically: from a point within 1e-6 of
+// the solution one step leaves an error of order kappa * 1e-12, kappa the
+// element map's relative curvature (<< 1 for elements of a valid mesh).
+constexpr double kPolishTol = 1e-6;
 
 }  // namespace fpts
 
 // profiling spans: locate, nearest-node start, Newton (primary pass), select
-// (other candidates + selection), eval binning, eval
-constexpr int kSpans = 7;
+// (other candidates + selection), eval binning, eval, particle update, face
+// kernel (parked pairs, with their binning)
+constexpr int kSpans = 8;
 
 struct fpts_mesh {
     fpts_params p;
@@ -223,6 +280,22 @@ struct fpts_mesh {
 };
 
 namespace fpts {
+
+// The local map and box records of a mesh as kernels read them.
+inline HashView hash_view(const fpts_mesh *m)
+{
+    HashView h;
+    for (int d = 0; d < 3; ++d) {
+        h.lo[d] = d < m->D ? m->hlo[d] : 0.0;
+        h.hi[d] = d < m->D ? m->hhi[d] : 0.0;
+        h.del[d] = d < m->D ? m->hdel[d] : 1.0;
+    }
+    h.NL = m->NL;
+    h.cell_off = m->d_cell_off;
+    h.cell_el = m->d_cell_el;
+    h.box = m->d_box;
+    return h;
+}
 
 // host setup (setup.cpp)
 int host_setup(fpts_mesh *m, const double *h_nodes);
@@ -279,6 +352,12 @@ hipError_t launch_hint(const fpts_mesh *m, int pass, int64_t n, const int32_t *c
 // points of one cell), primary = deepest inside its OBB
 // task -> unit map of a task grid over nunit units with task offsets chunk_off
 hipError_t launch_task_map(const int *chunk_off, int64_t nunit, int *task_unit, hipStream_t s);
+// Parked pairs binned by element: pass 0 counts them per element (elem_cnt,
+// zeroed before) and keeps each one's rank, pass 1 writes park index k at
+// sorted[elem_off[elem] + rank[k]]; *count pairs (at most cap).
+hipError_t launch_park_bin(int pass, const int4 *meta, const int *count, int64_t cap,
+                           int *elem_cnt, const int *elem_off, int *rank, int *sorted, int cus,
+                           hipStream_t s);
 // (counts primaries per element; in bin order, bin_prim[i] and rank[i] are
 // the primary of the point at bin position i and its rank in that bucket)
 hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
@@ -306,9 +385,10 @@ hipError_t launch_unsettled(const fpts_mesh *m, int64_t n, const int *cellpt, co
                             int *ucount, hipStream_t s);
 hipError_t launch_resolve(const fpts_mesh *m, int pass, int64_t n, const double *pts,
                           const int *cellpt, const int *primary, const int *ulist,
-                          const int *ucount, int *uoff, int *ucnt, int *slot_total,
+                          const int *ucount, int *uoff, int *ucnt, unsigned long long *slot_total,
                           int *elem_cnt2, const int *elem_off2, int *elem_fill2, int *slot_pt,
-                          int *slot_elem, int *sorted2, hipStream_t s);
+                          int *slot_elem, int *sorted2, int64_t cap2, int *olist, int *ocount,
+                          hipStream_t s);
 hipError_t launch_select2(const fpts_mesh *m, int64_t n, const int *ulist, const int *ucount,
                           const int *uoff, const int *ucnt, const int *primary,
                           const int *slot_elem, int64_t cap2, const double *res_r,

@@ -123,29 +123,6 @@ __device__ inline int cell_of(const HashView &h, const double *x)
 
 typedef const __attribute__((address_space(4))) double cdouble;
 
-// Box filter of element e (eq. eq_AABB_test, then eq. eq_OBB_test); `depth`
-// receives ||A(x - c)||_inf, the point's OBB depth (smaller = deeper).
-template <int D, typename P>
-__device__ inline bool box_pass(P rec, const double *x, double &depth)
-{
-    bool in = true;
-#pragma unroll
-    for (int d = 0; d < D; ++d) in = in && ((x[d] - rec[d]) * (rec[D + d] - x[d]) >= 0.0);
-    double y[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) y[d] = x[d] - rec[2 * D + d];
-    double mx = 0.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        double t = 0.0;
-#pragma unroll
-        for (int b = 0; b < D; ++b) t += rec[3 * D + a * D + b] * y[b];
-        mx = fmax(mx, fabs(t));
-    }
-    depth = mx;
-    return in && (mx <= 1.0);
-}
-
 __device__ inline void write_not_found(int p, int n, int R, int32_t *code, int32_t *elem,
                                        double *r, double *dist)
 {
@@ -245,15 +222,23 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
         const int q1 = __builtin_amdgcn_readfirstlane(h.cell_off[c + 1]);
         int cnt = 0, prim = -1;
         double best = __builtin_huge_val();
-        for (int q = q0; q < q1; ++q) {
-            const int e = __builtin_amdgcn_readfirstlane(h.cell_el[q]);
-            cdouble *rec = (cdouble *)(h.box + (size_t)e * (3 * D + D * D));
-            double depth;
-            if (box_pass<D>(rec, x, depth)) {
-                ++cnt;
-                if (depth < best) {
-                    best = depth;
-                    prim = e;
+        // the cell's element ids, one per lane in one vector load; each
+        // candidate's id is then a lane read, and its box record load does
+        // not wait for a dependent id load
+        for (int qb = q0; qb < q1; qb += kWave) {
+            const int mine = qb + lane < q1 ? h.cell_el[qb + lane] : 0;
+            const int nb = min(kWave, q1 - qb);
+#pragma unroll 2
+            for (int j = 0; j < nb; ++j) {
+                const int e = __builtin_amdgcn_readlane(mine, j);
+                cdouble *rec = (cdouble *)(h.box + (size_t)e * (3 * D + D * D));
+                double depth;
+                if (box_pass<D>(rec, x, depth)) {
+                    ++cnt;
+                    if (depth < best) {
+                        best = depth;
+                        prim = e;
+                    }
                 }
             }
         }
@@ -375,18 +360,23 @@ __device__ __forceinline__ int wave_excl_sum(int v, int &total)
 }
 
 // Phase D over the listed points (grid-stride).  pass 0: count each point's
-// other candidates (and per element) and give the point a block of that many
-// slots, uoff[i] .. uoff[i] + ucnt[i] - 1 (one atomic per wavefront on
-// *slot_total); pass 1: write the slots (k-th other candidate in ascending
-// id at uoff[i] + k) and bucket them by element.
+// other candidates and give the point a block of that many slots, uoff[i] ..
+// uoff[i] + ucnt[i] - 1 (one atomic per wavefront on *slot_total), and count
+// them per element; a point whose block would end beyond the slot capacity
+// cap2 gets none (ucnt[i] = 0) and goes to the overflow list instead
+// (olist, *ocount: searched one point per wavefront).  pass 1: write the
+// slots (k-th other candidate in ascending id at uoff[i] + k) and bucket them
+// by element.
 template <int D>
 __global__ __launch_bounds__(256) void k_resolve(HashView h, int pass, int n, const double *pts,
                                                 const int *cellpt, const int *primary,
                                                 const int *ulist, const int *ucount,
-                                                int *uoff, int *ucnt, int *slot_total,
+                                                int *uoff, int *ucnt,
+                                                unsigned long long *slot_total,
                                                 int *elem_cnt2, const int *elem_off2,
                                                 int *elem_fill2, int *slot_pt, int *slot_elem,
-                                                int *sorted2)
+                                                int *sorted2, int64_t cap2, int *olist,
+                                                int *ocount)
 {
     const int cnt = *ucount;
     const int lane = threadIdx.x & 63;
@@ -394,39 +384,61 @@ __global__ __launch_bounds__(256) void k_resolve(HashView h, int pass, int n, co
     // the loop condition is wave-uniform (the stride is a multiple of 64)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i - lane < cnt; i += stride) {
         const bool act = i < cnt;
-        int k = 0;
+        int k = 0, p = 0, prim = -1, c = 0;
+        double x[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = 0.0;
         if (act) {
-            const int p = ulist[i];
-            const int prim = primary[p], c = cellpt[p];
-            const int s0 = pass ? uoff[i] : 0;
-            double x[D];
+            p = ulist[i];
+            prim = primary[p];
+            c = cellpt[p];
 #pragma unroll
             for (int d = 0; d < D; ++d) x[d] = pts[(size_t)d * n + p];
-            for (int q = h.cell_off[c]; q < h.cell_off[c + 1]; ++q) {
-                const int e = h.cell_el[q];
-                if (e == prim) continue;
-                double depth;
-                if (!box_pass<D>(h.box + (size_t)e * (3 * D + D * D), x, depth)) continue;
-                if (pass == 0) {
-                    atomicAdd(&elem_cnt2[e], 1);
-                } else {
-                    const int sl = s0 + k;
-                    slot_pt[sl] = p;
-                    slot_elem[sl] = e;
-                    sorted2[elem_off2[e] + atomicAdd(&elem_fill2[e], 1)] = sl;
-                }
-                ++k;
-            }
         }
         if (pass == 0) {
+            if (act) {
+                for (int q = h.cell_off[c]; q < h.cell_off[c + 1]; ++q) {
+                    const int e = h.cell_el[q];
+                    double depth;
+                    if (e != prim && box_pass<D>(h.box + (size_t)e * (3 * D + D * D), x, depth))
+                        ++k;
+                }
+            }
             int tot;
             const int ex = wave_excl_sum(k, tot);
-            int base = 0;
-            if (lane == 0 && tot > 0) base = atomicAdd(slot_total, tot);
+            unsigned long long base = 0;
+            if (lane == 0 && tot > 0) base = atomicAdd(slot_total, (unsigned long long)tot);
             base = __shfl(base, 0, 64);
+            const bool fits = base + (unsigned long long)(ex + k) <= (unsigned long long)cap2;
             if (act) {
-                uoff[i] = base + ex;
-                ucnt[i] = k;
+                uoff[i] = fits ? (int)(base + ex) : 0;
+                ucnt[i] = fits ? k : 0;
+            }
+            if (act && k > 0) {
+                if (fits) {
+                    for (int q = h.cell_off[c]; q < h.cell_off[c + 1]; ++q) {
+                        const int e = h.cell_el[q];
+                        double depth;
+                        if (e != prim &&
+                            box_pass<D>(h.box + (size_t)e * (3 * D + D * D), x, depth))
+                            atomicAdd(&elem_cnt2[e], 1);
+                    }
+                } else {
+                    olist[atomicAdd(ocount, 1)] = p;
+                }
+            }
+        } else if (act && ucnt[i] > 0) {
+            const int s0 = uoff[i];
+            for (int q = h.cell_off[c]; q < h.cell_off[c + 1]; ++q) {
+                const int e = h.cell_el[q];
+                double depth;
+                if (e == prim || !box_pass<D>(h.box + (size_t)e * (3 * D + D * D), x, depth))
+                    continue;
+                const int sl = s0 + k;
+                slot_pt[sl] = p;
+                slot_elem[sl] = e;
+                sorted2[elem_off2[e] + atomicAdd(&elem_fill2[e], 1)] = sl;
+                ++k;
             }
         }
     }
@@ -476,20 +488,6 @@ __global__ __launch_bounds__(256) void k_select2(int n, int R, const int *ulist,
 
 inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block); }
 
-HashView hash_view(const fpts_mesh *m)
-{
-    HashView h;
-    for (int d = 0; d < 3; ++d) {
-        h.lo[d] = d < m->D ? m->hlo[d] : 0.0;
-        h.hi[d] = d < m->D ? m->hhi[d] : 0.0;
-        h.del[d] = d < m->D ? m->hdel[d] : 1.0;
-    }
-    h.NL = m->NL;
-    h.cell_off = m->d_cell_off;
-    h.cell_el = m->d_cell_el;
-    h.box = m->d_box;
-    return h;
-}
 
 // Search hints (points that move a little between searches): pass 0 takes
 // the previous element of every point whose previous code was INTERIOR as
@@ -519,6 +517,29 @@ __global__ __launch_bounds__(256) void k_hint(int pass, int n, int nel, int R,
     }
 }
 
+// Parked pairs of the primary Newton pass, binned by element (their queue
+// for the face kernel).  A fixed grid strides over the *count records; the
+// loop bound is uniform per wavefront, as wave_inc needs.
+__global__ __launch_bounds__(256) void k_park_bin(int pass, const int4 *meta, const int *count,
+                                                 int cap, int *elem_cnt, const int *elem_off,
+                                                 int *rank, int *sorted)
+{
+    const int total = min(*count, cap);
+    const int lane = threadIdx.x & 63;
+    for (int k0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63); k0 < total;
+         k0 += gridDim.x * blockDim.x) {
+        const int k = k0 + lane;
+        const bool active = k < total;
+        const int e = active ? meta[k].z : 0;
+        if (pass == 0) {
+            const int rk = wave_inc(elem_cnt, e, active);
+            if (active) rank[k] = rk;
+        } else if (active) {
+            sorted[elem_off[e] + rank[k]] = k;
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_fill_i32(int *p, int64_t count, int value, hipStream_t s)
@@ -545,6 +566,17 @@ hipError_t launch_exclusive_scan(const int *in, int *out, int64_t n, int ceil_di
     if (tiles > 0)
         hipLaunchKernelGGL(k_scan_add, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, out, n,
                            tmp);
+    return hipGetLastError();
+}
+
+hipError_t launch_park_bin(int pass, const int4 *meta, const int *count, int64_t cap,
+                           int *elem_cnt, const int *elem_off, int *rank, int *sorted, int cus,
+                           hipStream_t s)
+{
+    if (cap <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>(grid_for(cap, 256), (int64_t)cus * 4);
+    hipLaunchKernelGGL(k_park_bin, dim3(grid), dim3(256), 0, s, pass, meta, count, (int)cap,
+                       elem_cnt, elem_off, rank, sorted);
     return hipGetLastError();
 }
 
@@ -629,16 +661,17 @@ static int list_grid(const fpts_mesh *m, int64_t n)
 
 hipError_t launch_resolve(const fpts_mesh *m, int pass, int64_t n, const double *pts,
                           const int *cellpt, const int *primary, const int *ulist,
-                          const int *ucount, int *uoff, int *ucnt, int *slot_total,
+                          const int *ucount, int *uoff, int *ucnt, unsigned long long *slot_total,
                           int *elem_cnt2, const int *elem_off2, int *elem_fill2, int *slot_pt,
-                          int *slot_elem, int *sorted2, hipStream_t s)
+                          int *slot_elem, int *sorted2, int64_t cap2, int *olist, int *ocount,
+                          hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     HashView h = hash_view(m);
     auto k = m->D == 2 ? k_resolve<2> : k_resolve<3>;
     hipLaunchKernelGGL(k, dim3(list_grid(m, n)), dim3(256), 0, s, h, pass, (int)n, pts, cellpt,
                        primary, ulist, ucount, uoff, ucnt, slot_total, elem_cnt2, elem_off2,
-                       elem_fill2, slot_pt, slot_elem, sorted2);
+                       elem_fill2, slot_pt, slot_elem, sorted2, cap2, olist, ocount);
     return hipGetLastError();
 }
 

@@ -75,13 +75,42 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Sum over the four lanes of a slot (lanes l, l^16, l^32, l^48).
+// Sum over the four lanes of a slot (lanes l, l^16, l^32, l^48) with the
+// gfx950 lane-swap instructions.  v_permlane16_swap of a copy of v with
+// itself leaves every lane with its own value in one result and its xor-16
+// partner's in the other (v_permlane32_swap likewise for xor 32), so adding
+// the two results sums each pair of lanes, with the same operands in both
+// lanes of the pair: the four lanes of a slot end with bit-identical sums.
+__device__ __forceinline__ float pair_sum16(float v)
+{
+    const unsigned u = __float_as_uint(v);
+    const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    return __uint_as_float(a[0]) + __uint_as_float(a[1]);
+}
+__device__ __forceinline__ float pair_sum32(float v)
+{
+    const unsigned u = __float_as_uint(v);
+    const auto a = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return __uint_as_float(a[0]) + __uint_as_float(a[1]);
+}
+__device__ __forceinline__ double pair_sum16(double v)
+{
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
+__device__ __forceinline__ double pair_sum32(double v)
+{
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+}
 template <typename T>
 __device__ __forceinline__ T slot_sum(T v)
 {
-    v += xor_shfl(v, 16);
-    v += xor_shfl(v, 32);
-    return v;
+    return pair_sum32(pair_sum16(v));
 }
 
 // Row of the 16x16 output tile held by lane quarter g in item qq: the FP64
@@ -480,6 +509,14 @@ __device__ __forceinline__ double point_coord(const NewtonArgs &a, int p, int c)
 
 enum { S_FREE = 0, S_INIT = 1, S_STEP = 2, S_WAIT = 3 };
 
+// Newton launches.  kPrimary: the primary candidates; in FP64 a pair whose
+// next pass needs second derivatives is parked (NewtonIO::park_*) and the
+// wave goes on with other pairs; in FP32 (mixed mode) such a pair ends the
+// FP32 phase.  kResolve: the other candidates of unsettled points, second
+// derivatives in the wave.  kFace: the parked pairs, resumed from their
+// saved point, radius and pass count, second derivatives in the wave.
+enum { kPrimary = 0, kResolve = 1, kFace = 2 };
+
 // per-slot counters are kept by the slot's leader lane, per-wave (sweep)
 // counters by lane 0
 struct Counters {
@@ -493,7 +530,7 @@ struct Counters {
 // mode).  Each trip evaluates either sweep 1 at the slots' query points
 // (start points of new pairs, trial points of the others) or, when enough
 // slots wait for it, sweep 2 at the waiting slots' current points.
-template <typename T, int D, int R, int N, bool FINAL>
+template <typename T, int D, int R, int N, bool FINAL, int KIND>
 __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, int q1,
                                             const T *xl, T *tab, T *cache, int *citem, int lane,
                                             int max_iter, T tol, const double *shift,
@@ -537,8 +574,13 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
             cend = min(q1, head + kCache);
             const int idx = cstart + lane;
             if (lane < kCache && idx < cend) {
+                // kFace: the list holds park indices; the point, the saved
+                // iterate and the rest of the pair's state come from the
+                // park record
                 const int it = io.list[idx];
-                const int p = io.slot_pt ? io.slot_pt[it] : it;
+                int p;
+                if constexpr (KIND == kFace) p = io.park_meta[it].x;
+                else p = io.slot_pt ? io.slot_pt[it] : it;
                 citem[lane] = it;
 #pragma unroll
                 for (int c = 0; c < D; ++c)
@@ -547,12 +589,15 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                 // agent-scope loads: in mixed mode the FP32 phase of this
                 // wave stored these values moments ago
 #pragma unroll
-                for (int k = 0; k < R; ++k)
-                    cache[(D + k) * kCache + lane] = T(__hip_atomic_load(
-                        io.start ? io.start + (size_t)k * io.start_stride + idx
-                                 : io.r + (size_t)k * io.ostride + it,
-                        __ATOMIC_RELAXED,
-                        __HIP_MEMORY_SCOPE_AGENT));
+                for (int k = 0; k < R; ++k) {
+                    const double *src;
+                    if constexpr (KIND == kFace) src = io.park_r + (size_t)k * io.park_cap + it;
+                    else
+                        src = io.start ? io.start + (size_t)k * io.start_stride + idx
+                                       : io.r + (size_t)k * io.ostride + it;
+                    cache[(D + k) * kCache + lane] =
+                        T(__hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                }
             }
             wave_lds_sync();
         }
@@ -578,7 +623,17 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                 pass = 0;
                 alpha = T(1);
                 hb_ok = false;
-                if (leader && FINAL) cn.pairs++;
+                if constexpr (KIND == kFace) {
+                    // resumed where it was parked: same point, radius and
+                    // pass count (the pair was counted by the primary pass)
+                    const int4 mt = io.park_meta[item];
+                    pass = mt.w;
+                    alpha = T(io.park_r[(size_t)R * io.park_cap + item]);
+                    item = mt.x;
+                    pos = mt.y;
+                } else if (leader && FINAL) {
+                    cn.pairs++;
+                }
             }
         }
         head = min(head + nfree, cend);
@@ -618,6 +673,36 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
     };
     const int guard = (q1 - q0 + 16) * (2 * max_iter + 4);
     for (int trip = 0; trip < guard; ++trip) {
+        if constexpr (KIND == kPrimary) {
+            // pairs whose next pass needs second derivatives leave the wave:
+            // FP64 parks them (the face kernel resumes them, many to a wave),
+            // FP32 ends its phase there (the FP64 phase takes over)
+            const unsigned long long pm = __ballot(leader && state == S_WAIT);
+            if (pm) {
+                // (a launch without a park buffer -- the hinted search of
+                // particle tracking -- ends such pairs unconverged)
+                if (FINAL && io.park_meta) {
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(io.park_count, __popcll(pm));
+                    base = __shfl(base, 0);
+                    if (state == S_WAIT) {
+                        // park_cap is the pass's pair count: every pair is
+                        // parked at most once, so k < park_cap
+                        const int k = base + __popcll(pm & ((1ull << slot) - 1));
+                        if (leader && k < io.park_cap) {
+                            io.park_meta[k] = make_int4(item, pos, e, pass);
+#pragma unroll
+                            for (int j = 0; j < R; ++j)
+                                io.park_r[(size_t)j * io.park_cap + k] = (double)r[j];
+                            io.park_r[(size_t)R * io.park_cap + k] = (double)alpha;
+                        }
+                        state = S_FREE;
+                    }
+                } else {
+                    if (state == S_WAIT) finish(false);
+                }
+            }
+        }
         refill();
         const unsigned long long waitm = __ballot(leader && state == S_WAIT);
         const unsigned long long stepm = __ballot(leader && (state == S_STEP || state == S_INIT));
@@ -625,8 +710,7 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
         // a slot that waits for second derivatives gets them at once: holding
         // it back to batch more waiting slots (4 or 8) costs more in idle
         // slots than the batching saves (measured on hex48)
-        const bool do_s2 = waitm != 0;
-        if (do_s2) {
+        if (KIND != kPrimary && waitm != 0) {
             T Sn[kSym<R>];
             sweep2<T, D, R, N>(xl, tab, lane, r, dx, Sn);
             if (lane == 0) {
@@ -700,6 +784,20 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                     cur.f = fmax(cur.f - pred, T(0));
                     finish(true);
                     ended = true;
+                } else if (KIND == kPrimary && FINAL && R == D && io.polish && pass == 0 &&
+                           dmax <= T(kPolishTol) && !on_face(r) && !on_face(q)) {
+                    // mixed mode: the first FP64 step from the FP32 result
+                    // is small and stays inside, so the start is within
+                    // about kPolishTol of the solution and Newton's step
+                    // leaves an error of second order in it; that step ends
+                    // the iteration, with the model residual f - pred
+                    ++pass;
+                    if (leader) cn.passes++;
+#pragma unroll
+                    for (int k = 0; k < R; ++k) r[k] = q[k];
+                    cur.f = fmax(cur.f - pred, T(0));
+                    finish(true);
+                    ended = true;
                 }
             }
         }
@@ -723,7 +821,9 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
             for (int c = 0; c < D; ++c) dx[c] = dxn[c];
             hb_ok = false;
             state = S_STEP;
-            if (leader) {
+            // a resumed pair re-evaluates the point it was parked at (the
+            // same values as before): not a new evaluation of the iteration
+            if (leader && KIND != kFace) {
                 if (FINAL) cn.evals++;
                 else cn.evals32++;
             }
@@ -963,8 +1063,8 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
 // (no counter).  The other candidates of unsettled points are a few pairs
 // scattered over many elements; a counter would be stepped once per element
 // of the mesh, mostly past empty queues, one same-address atomic after the
-// other.
-template <typename T, int D, int R, int N, bool TASKS>
+// other.  The parked pairs of the face kernel are likewise spread thinly.
+template <typename T, int D, int R, int N, bool TASKS, int KIND>
 __device__ __forceinline__ void newton_body(const NewtonArgs &a)
 {
     typedef Shape<D, R, N> S;
@@ -1002,12 +1102,13 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &a)
         __syncthreads();
         if constexpr (FINAL) {
             stage<double, D * S::NP>(xl, a.nodes + (size_t)e * D * S::NP, lane);
-            run_element<double, D, R, N, true>(a, e, q0, q1, xl, tab, cache, citem, lane,
-                                               a.max_iter, a.tol, nullptr, cn);
+            run_element<double, D, R, N, true, KIND>(a, e, q0, q1, xl, tab, cache, citem, lane,
+                                                     a.max_iter, a.tol, nullptr, cn);
         } else {
             stage<float, D * S::NP>(xl, a.nodes32 + (size_t)e * D * S::NP, lane);
-            run_element<float, D, R, N, false>(a, e, q0, q1, xl, tab, cache, citem, lane,
-                                               a.max_iter32, a.tol32, a.xc + (size_t)e * D, cn);
+            run_element<float, D, R, N, false, KIND>(a, e, q0, q1, xl, tab, cache, citem, lane,
+                                                     a.max_iter32, a.tol32,
+                                                     a.xc + (size_t)e * D, cn);
         }
     }
     unsigned long long v[10] = {cn.pairs,  cn.passes,        cn.evals,  cn.evals_h2,
@@ -1038,31 +1139,179 @@ __global__ __launch_bounds__(64) void k_nearest_resolve(NewtonArgs a)
 template <int D, int R, int N>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_newton(NewtonArgs a)
 {
-    newton_body<double, D, R, N, false>(a);
+    newton_body<double, D, R, N, false, kPrimary>(a);
 }
 template <int D, int R, int N>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 k_newton_resolve(NewtonArgs a)
 {
-    newton_body<double, D, R, N, true>(a);
+    newton_body<double, D, R, N, true, kResolve>(a);
+}
+template <int D, int R, int N>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+k_newton_face(NewtonArgs a)
+{
+    newton_body<double, D, R, N, true, kFace>(a);
 }
 template <int D, int R, int N>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 k_newton32(NewtonArgs a)
 {
-    newton_body<float, D, R, N, false>(a);
+    newton_body<float, D, R, N, false, kPrimary>(a);
 }
+
+// Phase D for the points whose other candidates found no room in the slot
+// array (more candidate pairs than the workspace holds): one wavefront per
+// point, its other candidates in ascending id order, each started from its
+// nearest node (squared distances to every node of the element, ties to the
+// lowest index) and iterated by the same code as the pass kernels, on a
+// one-pair queue; then the selection rule of Section 3.2 over the primary
+// and them.  One pair per wavefront: a path for rare overloads only.
 template <int D, int R, int N>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
-k_newton32_resolve(NewtonArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+k_resolve_overflow(NewtonArgs a, HashView h)
 {
-    newton_body<float, D, R, N, true>(a);
+    typedef Shape<D, R, N> S;
+    constexpr gll::Table<N> GT = gll::Nodes<N>::t;
+    extern __shared__ double lds_raw[];
+    int *citem = reinterpret_cast<int *>(reinterpret_cast<char *>(lds_raw) +
+                                         Lds<double, D, R, N>::bytes() - sizeof(int) * kCache);
+    double *xl = lds_raw;
+    double *tab = xl + Lds<double, D, R, N>::NODES;
+    double *cache = tab + 2 * Lds<double, D, R, N>::TAB;
+    const int lane = threadIdx.x, b = blockIdx.x, G = gridDim.x;
+    const NewtonIO &io = a.io;
+    const int cnt = *io.ocount;
+    // this block's one-pair queue: item b of the scratch outputs
+    int *ov_item = io.ov_int, *ov_pt = io.ov_int + G, *ov_code = io.ov_int + 2 * G;
+    NewtonArgs la = a;
+    la.io.list = ov_item;
+    la.io.slot_pt = ov_pt;
+    la.io.code = ov_code;
+    la.io.elem = nullptr;
+    la.io.r = io.ov_dbl;
+    la.io.ostride = G;
+    la.io.dist = io.ov_dbl + (size_t)R * G;
+    la.io.start = nullptr;
+    la.io.rs = nullptr;
+    la.io.conv = nullptr;
+    la.io.park_meta = nullptr;
+    la.io.polish = 0;
+    if (lane == 0) ov_item[b] = b;
+    Counters cn;
+    for (int i = b; i < cnt; i += G) {
+        const int p = io.list[i];
+        const int prim = io.primary[p], c = io.cellpt[p];
+        double x[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = point_coord<D>(a, p, d);
+        if (lane == 0) ov_pt[b] = p;
+        // the primary's result is the best so far
+        int bcode = io.code[p], belem = prim;
+        double bdist = io.dist[p], br[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) br[k] = io.r[(size_t)k * io.ostride + p];
+        bool changed = false;
+        for (int q = h.cell_off[c]; q < h.cell_off[c + 1]; ++q) {
+            const int e = h.cell_el[q];
+            double depth;
+            if (e == prim || !box_pass<D>(h.box + (size_t)e * (3 * D + D * D), x, depth))
+                continue;
+            __syncthreads();
+            stage<double, D * S::NP>(xl, a.nodes + (size_t)e * D * S::NP, lane);
+            // nearest node: squared distance, lowest index among equals
+            double bd = __builtin_huge_val();
+            int bi = 0;
+            for (int j = lane; j < S::NP; j += kWave) {
+                double d2 = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const double t = x[d] - xl[d * S::NP + j];
+                    d2 = fma(t, t, d2);
+                }
+                if (d2 < bd) {
+                    bd = d2;
+                    bi = j;
+                }
+            }
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const double od = __shfl_xor(bd, o);
+                const int oi = __shfl_xor(bi, o);
+                if (od < bd || (od == bd && oi < bi)) {
+                    bd = od;
+                    bi = oi;
+                }
+            }
+            if (lane == 0) {
+                const int ii[3] = {bi % N, (bi / N) % N, bi / (N * N)};
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    double v = GT.z[0];
+#pragma unroll
+                    for (int m = 1; m < N; ++m)
+                        if (ii[k] == m) v = GT.z[m];
+                    la.io.r[(size_t)k * G + b] = v;
+                }
+            }
+            // lane 0 wrote the queue entry and the start and reads them back
+            // in the refill (same lane, program order)
+            run_element<double, D, R, N, true, kResolve>(la, e, b, b + 1, xl, tab, cache, citem,
+                                                        lane, a.max_iter, a.tol, nullptr, cn);
+            // slot 0's leader (lane 0) wrote the result
+            int cd = 0;
+            double dd = 0.0, rr[R];
+            if (lane == 0) {
+                cd = ov_code[b];
+                dd = la.io.dist[b];
+            }
+#pragma unroll
+            for (int k = 0; k < R; ++k) rr[k] = lane == 0 ? la.io.r[(size_t)k * G + b] : 0.0;
+            cd = __shfl(cd, 0);
+            dd = __shfl(dd, 0);
+#pragma unroll
+            for (int k = 0; k < R; ++k) rr[k] = __shfl(rr[k], 0);
+            // Section 3.2: the lowest-id INTERIOR candidate, else the
+            // smallest distance, the lower id on ties
+            bool take;
+            if (bcode == FPTS_INTERIOR) take = cd == FPTS_INTERIOR && e < belem;
+            else if (cd == FPTS_INTERIOR) take = true;
+            else take = dd < bdist || (dd == bdist && e < belem);
+            if (take) {
+                bcode = cd;
+                belem = e;
+                bdist = dd;
+#pragma unroll
+                for (int k = 0; k < R; ++k) br[k] = rr[k];
+                changed = true;
+            }
+        }
+        if (lane == 0 && changed) {
+            io.code[p] = bcode;
+            io.elem[p] = belem;
+            io.dist[p] = bdist;
+#pragma unroll
+            for (int k = 0; k < R; ++k) io.r[(size_t)k * io.ostride + p] = br[k];
+        }
+    }
+    unsigned long long v[10] = {cn.pairs,  cn.passes,        cn.evals,  cn.evals_h2,
+                                cn.passes32, cn.evals32,     cn.evals_h2_exec,
+                                cn.sweeps, cn.sweeps_h2, cn.sweeps32};
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        unsigned long long xv = v[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) xv += __shfl_xor(xv, o);
+        if (lane == 0 && xv) atomicAdd(&io.stats[k], xv);
+    }
 }
 
 typedef void (*KernelFn)(NewtonArgs);
+typedef void (*OverflowFn)(NewtonArgs, HashView);
 
 struct Kernels {
-    KernelFn nearest = nullptr, newton32 = nullptr, newton = nullptr;
+    KernelFn nearest = nullptr, newton32 = nullptr, newton = nullptr, face = nullptr;
+    OverflowFn overflow = nullptr;
     size_t lds_nearest = 0, lds_newton32 = 0, lds_newton = 0;
 };
 
@@ -1075,7 +1324,9 @@ Kernels pick_kernels(int N, bool resolve)
     case NN:                                                                                \
         k.nearest = resolve ? k_nearest_resolve<D, R, NN, MIXED> : k_nearest<D, R, NN, MIXED>; \
         k.newton = resolve ? k_newton_resolve<D, R, NN> : k_newton<D, R, NN>;               \
-        if (MIXED) k.newton32 = resolve ? k_newton32_resolve<D, R, NN> : k_newton32<D, R, NN>; \
+        k.face = k_newton_face<D, R, NN>;                                                   \
+        k.overflow = k_resolve_overflow<D, R, NN>;                                          \
+        if (MIXED && !resolve) k.newton32 = k_newton32<D, R, NN>;                           \
         k.lds_nearest = NearLds<TN, D, R, NN>::bytes();                                     \
         k.lds_newton32 = Lds<float, D, R, NN>::bytes();                                     \
         k.lds_newton = Lds<double, D, R, NN>::bytes();                                      \
@@ -1100,9 +1351,12 @@ Kernels pick_kernels(int N, bool resolve)
 // Launches on the caller's stream: nearest nodes (which & 1; task grid of
 // 64-pair tasks over io.chunk_off, io.task_elem), then Newton (which & 2; element
 // tasks: in mixed mode the FP32 phase, counter io.counter[9], then the FP64
-// kernel, counter io.counter[8]).  io.counter[0..15] must be zero.  A list
-// with io.slot_pt set (other candidates) selects the *_resolve kernels, whose
-// Newton strides over the 64-pair tasks like the nearest-node kernel.
+// kernel, counter io.counter[8]); which & 4 runs the face kernel over the
+// parked pairs (io.list = park indices binned by element, io.elem_off /
+// chunk_off / task_elem their buckets and tasks).  io.counter[0..15] must be
+// zero.  A list with io.slot_pt set (other candidates) selects the *_resolve
+// kernels, whose Newton strides over the 64-pair tasks like the nearest-node
+// kernel.
 template <int D, int R>
 hipError_t launch_newton_kind(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
                               const NewtonIO &io, int which, hipStream_t s)
@@ -1140,6 +1394,20 @@ hipError_t launch_newton_kind(const fpts_mesh *m, bool mixed, int64_t n, const d
             if (e != hipSuccess) return e;
         }
         hipLaunchKernelGGL(k.newton, dim3(m->cus * 8), dim3(64), k.lds_newton, s, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (which & 4) {
+        if (!k.face) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k.face, dim3(m->cus * 8), dim3(64), k.lds_newton, s, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (which & 8) {
+        // grid = the scratch's block count (io.task_bound)
+        if (!k.overflow || io.task_bound < 1) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k.overflow, dim3((unsigned)io.task_bound), dim3(64), k.lds_newton, s,
+                           a, hash_view(m));
         return hipGetLastError();
     }
     return hipSuccess;

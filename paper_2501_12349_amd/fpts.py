@@ -48,7 +48,8 @@ class FindStats(ctypes.Structure):
                 ("evals", ctypes.c_int64), ("evals_h2", ctypes.c_int64),
                 ("passes_fp32", ctypes.c_int64), ("evals_fp32", ctypes.c_int64),
                 ("evals_h2_exec", ctypes.c_int64), ("sweeps", ctypes.c_int64),
-                ("sweeps_h2", ctypes.c_int64), ("sweeps_fp32", ctypes.c_int64)]
+                ("sweeps_h2", ctypes.c_int64), ("sweeps_fp32", ctypes.c_int64),
+                ("overflow_points", ctypes.c_int64)]
 
 
 class KernelTimes(ctypes.Structure):
@@ -56,7 +57,7 @@ class KernelTimes(ctypes.Structure):
                 ("newton_ms", ctypes.c_double),
                 ("select_ms", ctypes.c_double), ("eval_bin_ms", ctypes.c_double),
                 ("eval_ms", ctypes.c_double), ("advance_ms", ctypes.c_double),
-                ("find_calls", ctypes.c_int64), ("eval_calls", ctypes.c_int64),
+                ("face_ms", ctypes.c_double), ("find_calls", ctypes.c_int64), ("eval_calls", ctypes.c_int64),
                 ("lpt_calls", ctypes.c_int64)]
 
 
@@ -254,7 +255,8 @@ class Mesh:
 
     def find_stats(self, stream=None, newton_pass=0):
         """Counters of the last find (synchronises the stream); newton_pass 1 =
-        primary candidates, 2 = other candidates, 0 = both."""
+        primary candidates, 2 = other candidates, 3 = face passes of primary
+        pairs, 0 = all."""
         wsb, n = self._last_find_ws
         st = FindStats()
         _check(load_library().fpts_find_stats_get(self._h, n, _dptr(wsb), int(newton_pass),

@@ -111,3 +111,35 @@ def test_sphere_every_point(sphere, precision):
     n = wl["pts"].shape[1]
     rep = _check_sample(wl, om, precision, np.arange(n), surface=True)
     assert rep["n"] == 1 << 22
+
+
+def test_hex48_1e8_points_one_call(hex48):
+    """10^8 points (the largest point count of the paper's Find runs) found
+    and interpolated on the 48^3 mesh in one fpts_find_eval call; a seeded
+    sample of 20 000 points checked against the oracle."""
+    from paper_2501_12349_amd import fpts
+    wl, om = hex48
+    n = 100_000_000
+    gm = fpts.Mesh(wl["nodes"], wl["N"])
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1_000_003)
+    pts = torch.rand((3, n), generator=g, dtype=torch.float64, device="cuda")
+    fields = torch.from_numpy(wl["fields"]).cuda()
+    wsb = gm.find_eval_workspace_bytes(n)
+    print("1e8 points: workspace %.2f GB (%.0f B per point)" % (wsb / 1e9, wsb / n), flush=True)
+    res, u = gm.find_eval(pts, fields)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(79).choice(n, 20000, replace=False))
+    ti = torch.from_numpy(idx).cuda()
+    sp = np.ascontiguousarray(pts[:, ti].cpu().numpy())
+    gsub = {k: (v[:, ti] if v.dim() == 2 else v[ti]).cpu().numpy() for k, v in res.items()}
+    us = u[:, ti].cpu().numpy()
+    orc = om.find(sp)
+    rep = compare_find(om, sp, orc, gsub, wl["h"], max_ambiguous=1e-3)
+    uo = om.eval(orc, wl["fields"])
+    same = gsub["elem"] == orc["elem"]
+    rep["eval_rel"] = compare_eval(uo[:, same], us[:, same], orc["code"][same])
+    codes = torch.bincount(res["code"].long(), minlength=3).cpu().tolist()
+    print("1e8 points:", rep, "codes", codes, flush=True)
+    assert codes[0] == n
+    assert wsb / n < 400

@@ -140,3 +140,26 @@ def test_deterministic_bitwise():
     for k in ("code", "elem", "r", "dist"):
         assert np.array_equal(a[1][k], b[1][k], equal_nan=True), k
     assert np.array_equal(a[2], b[2], equal_nan=True)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_second_search_overflow(precision):
+    """Boxes expanded fivefold overlap so much that the points outside the
+    domain have far more candidates than the second search's slots hold
+    (one per point): the overflowing points go through the one-point-per-
+    wavefront path, and every result still meets the parity bars."""
+    wl = W.quad2d(n_pts=6000, seed=2077)
+    rng = np.random.default_rng(2078)
+    pts = rng.uniform(-0.15, 1.15, (2, 6000))
+    fpts = _fpts()
+    gm = fpts.Mesh(wl["nodes"], wl["N"], bbox_tol=4.0)
+    om = oracle.Mesh(wl["nodes"], 2, 2, wl["N"], bbox_tol=4.0)
+    orc = om.find(pts)
+    res = gm.find(torch.from_numpy(pts).cuda(), precision=precision)
+    st = gm.find_stats()
+    torch.cuda.synchronize()
+    gpu = to_np(res)
+    rep = compare_find(om, pts, orc, gpu, wl["h"])
+    print(precision, rep, "overflow points", st["overflow_points"])
+    assert st["overflow_points"] > 100
+    assert (orc["code"] == oracle.BORDER).sum() > 1000
