@@ -197,6 +197,26 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
                    int field_nodes_1d, const double *d_field, double *d_out, void *d_ws,
                    size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * as fpts_find_eval, with the workspace taken from a fixed array the library
+ * holds on each device until the process ends (FPTS_NOALLOC_SCRATCH_BYTES
+ * bytes; its address is looked up when the first mesh is set up on that
+ * device).  The call allocates nothing.  It returns FPTS_ENOMEM, without
+ * doing anything, when fpts_find_eval_workspace_size(m, n) exceeds
+ * FPTS_NOALLOC_SCRATCH_BYTES (about 240 bytes per point plus the
+ * mesh-sized arrays: some 2.2 million points on a 48^3 mesh with N = 8).  Every call on one device shares that device's
+ * array: calls that overlap on one device -- on different streams, or
+ * from different threads -- race and corrupt each other's results; they
+ * must be ordered (one stream, or events).  The array keeps the last call's
+ * contents; each call clears what it needs itself.  Other arguments and
+ * errors as fpts_find_eval. */
+#define FPTS_NOALLOC_SCRATCH_BYTES ((size_t)512 << 20)
+int fpts_find_eval_noalloc(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code,
+                           int32_t *d_elem, double *d_r, double *d_dist, int precision,
+                           int n_fields, int field_nodes_1d, const double *d_field,
+                           double *d_out, void *stream);
+
 /* Counters of the last fpts_find that used workspace d_ws (read back with a
  * device-to-host copy on `stream`, which is synchronised) for one Newton
  * launch: pass 1 = primary candidates, 2 = the other candidates of points the

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "fpts_internal.hpp"
@@ -32,6 +33,36 @@ bool sticky_error()
     return e != hipSuccess;
 }
 
+// Fixed scratch of fpts_find_eval_noalloc: one copy per device, held until
+// the process ends.  Host code never uses the array's name as an address:
+// the device address of each device's copy is looked up once, with that
+// device current (fpts_setup on it), and kept in noalloc_ptr[device].
+constexpr int kMaxDevices = 64;
+void *noalloc_ptr[kMaxDevices] = {nullptr};
+std::mutex noalloc_mu;
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[FPTS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// Device address of this device's scratch copy (device `dev` current);
+// nullptr when the lookup failed.
+void *noalloc_scratch(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> g(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        noalloc_ptr[dev] = p;
+    }
+    return noalloc_ptr[dev];
+}
 
 template <class T>
 T *at(void *base, size_t off)
@@ -425,6 +456,12 @@ int fpts_setup(const fpts_params *p, const double *h_nodes, void *stream, fpts_m
     if (hipGetDevice(&m->device) != hipSuccess ||
         hipDeviceGetAttribute(&m->cus, hipDeviceAttributeMultiprocessorCount, m->device) !=
             hipSuccess) {
+        delete m;
+        return FPTS_EDEVICE;
+    }
+    // set-up of the allocation-free entry point: this device's scratch
+    // address, looked up once with the device current
+    if (!noalloc_scratch(m->device)) {
         delete m;
         return FPTS_EDEVICE;
     }
@@ -882,6 +919,21 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
     }
     if (m->profiling) m->prof_eval++;
     return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;
+}
+
+int fpts_find_eval_noalloc(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code,
+                           int32_t *d_elem, double *d_r, double *d_dist, int precision,
+                           int n_fields, int field_nodes_1d, const double *d_field,
+                           double *d_out, void *stream)
+{
+    if (!m || n < 0 || n > INT32_MAX - 1) return FPTS_EINVAL;
+    const size_t need = fpts_find_eval_workspace_size(m, n);
+    if (need == 0) return FPTS_EINVAL;
+    if (need > (size_t)FPTS_NOALLOC_SCRATCH_BYTES) return FPTS_ENOMEM;
+    void *ws = m->device >= 0 && m->device < kMaxDevices ? noalloc_ptr[m->device] : nullptr;
+    if (!ws) return FPTS_EDEVICE;
+    return fpts_find_eval(m, n, d_pts, d_code, d_elem, d_r, d_dist, precision, n_fields,
+                          field_nodes_1d, d_field, d_out, ws, need, stream);
 }
 
 }  // extern "C"

@@ -19,7 +19,8 @@ EXPORTS = ("fpts_params_default", "fpts_setup", "fpts_destroy", "fpts_update_nod
            "fpts_find_workspace_size", "fpts_find", "fpts_eval_workspace_size",
            "fpts_eval", "fpts_eval_order", "fpts_find_eval_workspace_size", "fpts_find_eval",
            "fpts_find_stats_get", "fpts_profile", "fpts_profile_read",
-           "fpts_get_boxes", "fpts_get_hash", "fpts_get_cells", "fpts_status_string")
+           "fpts_get_boxes", "fpts_get_hash", "fpts_get_cells", "fpts_status_string",
+           "fpts_find_eval_noalloc")
 
 # Entry points declared in include/fpts_lpt.h.
 LPT_EXPORTS = ("fpts_lpt_workspace_size", "fpts_lpt_step")
@@ -107,6 +108,7 @@ def load_library(path=LIB_PATH):
     L.fpts_find_eval_workspace_size.restype = ctypes.c_size_t
     L.fpts_find_eval.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, i32, i32, vp, vp, vp,
                                  ctypes.c_size_t, vp]
+    L.fpts_find_eval_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp, i32, i32, i32, vp, vp, vp]
     L.fpts_find_stats_get.argtypes = [vp, i64, vp, i32, ctypes.POINTER(FindStats), vp]
     L.fpts_profile.argtypes = [vp, i32]
     L.fpts_profile_read.argtypes = [vp, ctypes.POINTER(KernelTimes)]
