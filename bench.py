@@ -455,7 +455,8 @@ def main():
     # separate calls, fpts_find (its layout starts the same way)
     ws_f = torch.empty(gm.find_eval_workspace_bytes(n), dtype=torch.uint8, device=dev)
     ws_e = torch.empty(gm.eval_workspace_bytes(n), dtype=torch.uint8, device=dev)
-    log("workspace find+eval %.2f GB, eval %.2f GB" % (ws_f.numel() / 1e9, ws_e.numel() / 1e9))
+    log("workspace find+eval %.2f GB (%.0f B per point), eval %.2f GB" % (
+        ws_f.numel() / 1e9, ws_f.numel() / n, ws_e.numel() / 1e9))
 
     def step(prec):
         # one pass of the path: Find and Interpolate of every point
@@ -525,6 +526,7 @@ def main():
     log("%s, fpts_find + fpts_eval as two calls: %.3f ms/step  %.1f Mpts/s" % (
         main_mode, dt_sep * 1e3, n / dt_sep / 1e6))
     achieved = r0["flops"] / (r0["newton_ms"] * 1e-3) / 1e12
+    kt0 = r0["kt"]
     # HBM bytes per k_newton launch from the committed counter summary of this
     # workload (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated); None when
     # the Newton sources changed since the counters were taken
@@ -557,6 +559,8 @@ def main():
                      "kernel_ms": round(r0["newton_ms"], 4),
                      "flops_per_launch": r0["flops"],
                      "slot_use": slot_use(r0["stats"])},
+        "workspace_bytes_per_point": round(gm.find_eval_workspace_bytes(n) / n, 1),
+        "newton_total_ms": round((kt0["newton_ms"] + kt0["face_ms"]) / max(kt0["find_calls"], 1), 4),
         "setup_s": round(t_setup, 3),
         "setup_device_s": round(t_setup_dev, 4) if t_setup_dev is not None else None,
         "codes": dict(zip(("interior", "border", "not_found"), r0["codes"])),

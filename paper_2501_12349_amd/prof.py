@@ -2,9 +2,12 @@
 
     python -m paper_2501_12349_amd.prof stats  <dir>/run_kernel_stats.csv  "<command>" "<title>"
     python -m paper_2501_12349_amd.prof traffic <fetch_dir> <write_dir> "<commands>" "<title>"
+    python -m paper_2501_12349_amd.prof sq <dir1> <dir2> "<commands>" "<title>"
 
 `stats` turns a --kernel-trace --stats run into a table of kernels (calls,
-average and total time).  `traffic` combines a --pmc FETCH_SIZE run and a
+average and total time).  `sq` summarises two --pmc runs of SQ counters
+(instruction counts, MFMA busy cycles, waits, LDS bank conflicts) per
+dispatch of the Newton and nearest-node kernels.  `traffic` combines a --pmc FETCH_SIZE run and a
 --pmc WRITE_SIZE run (same program, one pass each) into HBM bytes per
 dispatch.  Each counter is scaled by what it reads for a plain device copy of
 known size in the same run (bench.py --calib-copy: 1 GiB), because the raw
@@ -92,6 +95,24 @@ def traffic(fetch_csv, write_csv):
     return out, fr, fw
 
 
+def sq_counters(paths, match=("k_newton", "k_nearest")):
+    """kernel -> {counter: value per dispatch} over the --pmc runs."""
+    agg = OrderedDict()
+    for path in paths:
+        disp = {}
+        for r in csv.DictReader(open(path)):
+            k = short_name(r["Kernel_Name"])
+            if not any(k.startswith(m) for m in match):
+                continue
+            d = agg.setdefault(k, OrderedDict())
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            disp.setdefault(k, {}).setdefault(r["Counter_Name"], set()).add(r["Dispatch_Id"])
+        for k, cs in disp.items():
+            for c, ids in cs.items():
+                agg[k][c] /= len(ids)
+    return agg
+
+
 def main(argv):
     if len(argv) >= 2 and argv[0] == "stats":
         cmd = argv[2] if len(argv) > 2 else ""
@@ -129,6 +150,28 @@ def main(argv):
             print("\n%s: %s bytes=%d read=%d write=%d source=%s" % (
                 TRAFFIC_TAG, kn[0], int(v["read"] + v["write"]), int(v["read"]),
                 int(v["write"]), newton_source_hash()))
+        return 0
+    if len(argv) >= 3 and argv[0] == "sq":
+        cmd = argv[3] if len(argv) > 3 else ""
+        title = argv[4] if len(argv) > 4 else "SQ counters per dispatch"
+        agg = sq_counters([os.path.join(argv[1], "run_counter_collection.csv"),
+                           os.path.join(argv[2], "run_counter_collection.csv")])
+        print("# %s\n\nCommands (run from /tmp with TMPDIR=/tmp on the GPU host; REPO = the "
+              "repository root), eight SQ counters per run:\n\n    %s\n"
+              % (title, cmd.replace(" ;; ", "\n    ")))
+        print("Per dispatch.  SQ_WAVE_CYCLES and SQ_WAIT_INST_ANY count 4-cycle units summed "
+              "over waves; SQ_VALU_MFMA_BUSY_CYCLES and SQ_LDS_BANK_CONFLICT are cycles summed "
+              "over SIMDs / CUs.\n")
+        names = []
+        for d in agg.values():
+            for c in d:
+                if c not in names:
+                    names.append(c)
+        print("| Counter | " + " | ".join("`%s`" % k for k in agg) + " |")
+        print("|---|" + "---:|" * len(agg))
+        for c in names:
+            print("| %s | %s |" % (c, " | ".join("%.4g" % agg[k].get(c, float("nan"))
+                                                 for k in agg)))
         return 0
     print(__doc__)
     return 2
