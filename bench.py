@@ -378,6 +378,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4000000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--mixed-tol", type=float, default=None,
+                    help="step size that ends the FP32 phase of mixed mode (default: the "
+                         "library's, fpts_params_default)")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests per serving run (0: no serving measurement)")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
@@ -427,7 +430,7 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    gm = fpts.Mesh(wl["nodes"], N, dim=D, ref_dim=R)
+    gm = fpts.Mesh(wl["nodes"], N, dim=D, ref_dim=R, mixed_tol=args.mixed_tol)
     t_setup = time.perf_counter() - t0
     log("setup %.2f s (host boxes + map, upload)" % t_setup)
     # setup on the device from nodes already there (fpts_update_nodes, the

@@ -128,6 +128,27 @@ struct Shape {
     static constexpr int KS = (N + 3) / 4;              // 4-wide K steps
 };
 
+// Where node (coordinate c, contraction row `row`, first index i) of the
+// element sits in LDS.  The 16 lanes of a lane quarter read the A operand
+// from 16 consecutive rows at one i; with rows of an even number of values
+// stored back to back those reads share a few LDS banks (N = 8 doubles: two
+// banks pairs for 16 lanes).  Rows of an odd length P = N + 1 spread them
+// over 16; FP64 with N = 8 instead rotates each row by row / 2 positions
+// (no padding: the wave's LDS stays within 20 KB, eight waves per CU).
+template <typename T, int D, int R, int N>
+struct NodeLds {
+    typedef Shape<D, R, N> S;
+    static constexpr bool ROT = std::is_same<T, double>::value && N == 8;
+    static constexpr int P = (ROT || N % 2) ? N : N + 1;
+    static constexpr int RP = S::ROWS * P;               // per coordinate
+    static constexpr int SIZE = D * RP;
+    static constexpr bool PLAIN = !ROT && P == N;        // the global layout
+    __device__ static __forceinline__ int at(int c, int row, int i)
+    {
+        return c * RP + row * P + (ROT ? ((i + (row >> 1)) & (N - 1)) : i);
+    }
+};
+
 // Packed symmetric R x R matrices: diagonal first, then the upper triangle.
 template <int R> constexpr int kSym = R * (R + 1) / 2;
 template <int R>
@@ -204,7 +225,7 @@ constexpr int kCache = 32;
 // tables of directions 1 and 2 (s, t): [2][3][N][16] of type T.
 template <typename T, int D, int R, int N>
 struct Lds {
-    static constexpr int NODES = D * Shape<D, R, N>::NP;
+    static constexpr int NODES = NodeLds<T, D, R, N>::SIZE;
     static constexpr int TAB = 3 * N * 16;
     // pair cache: kCache x (point coordinates D, start r R) of type T, then
     // kCache item ids
@@ -271,7 +292,7 @@ __device__ __forceinline__ void sweep1(const T *xl, T *tab, int lane, const T (&
                 // out-of-range A entries meet a zero B entry (ai >= N) or
                 // land in output rows that are dropped (arow >= ROWS); the
                 // clamped address keeps the read inside the node block
-                const T a = xl[aok ? c * S::NP + ai + N * arow : 0];
+                const T a = xl[aok ? NodeLds<T, D, R, N>::at(c, arow, ai) : 0];
                 acc0[c] = mfma16(a, b0[ks], acc0[c]);
                 acc1[c] = mfma16(a, b1[ks], acc1[c]);
             }
@@ -355,7 +376,7 @@ __device__ __forceinline__ void sweep2(const T *xl, T *tab, int lane, const T (&
             const bool aok = ((N % 4 == 0) && (S::ROWS % 16 == 0)) || (arow < S::ROWS && ai < N);
 #pragma unroll
             for (int c = 0; c < D; ++c) {
-                const T a = xl[aok ? c * S::NP + ai + N * arow : 0];
+                const T a = xl[aok ? NodeLds<T, D, R, N>::at(c, arow, ai) : 0];
                 acc0 = mfma16(a, dx[c] * b0[ks], acc0);
                 acc1 = mfma16(a, dx[c] * b1[ks], acc1);
                 acc2 = mfma16(a, dx[c] * b2[ks], acc2);
@@ -901,6 +922,40 @@ __device__ __forceinline__ void stage(T *lds, const T *src, int lane)
     __syncthreads();
 }
 
+// Copies an element's node block [D][NP] (rows of N values) from global
+// memory to LDS in the NodeLds layout, then waits for the workgroup.
+template <typename T, int D, int R, int N>
+__device__ __forceinline__ void stage_nodes(T *lds, const T *src, int lane)
+{
+    typedef NodeLds<T, D, R, N> L;
+    constexpr int NP = Shape<D, R, N>::NP;
+    if constexpr (L::PLAIN) {
+        stage<T, D * NP>(lds, src, lane);
+    } else {
+        constexpr int COUNT = D * NP;
+        constexpr int BATCH = 8;
+#pragma unroll 1
+        for (int v0 = 0; v0 < COUNT; v0 += BATCH * kWave) {
+            T v[BATCH];
+#pragma unroll
+            for (int k = 0; k < BATCH; ++k) {
+                const int idx = v0 + k * kWave + lane;
+                if (idx < COUNT) v[k] = src[idx];
+            }
+#pragma unroll
+            for (int k = 0; k < BATCH; ++k) {
+                const int idx = v0 + k * kWave + lane;
+                if (idx < COUNT) {
+                    const int c = idx / NP, rem = idx - c * NP;
+                    const int row = rem / N, i = rem - row * N;
+                    lds[L::at(c, row, i)] = v[k];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Nearest-node contraction operands: B rows [4][NPAD] (-2 x_j, -2 y_j,
 // -2 z_j, |x_j|^2 of every node j, element-local; padding columns score a
 // large constant) and A rows [4][64] (x, y, z, 1 of each pair).  FP64 reads
@@ -1101,11 +1156,11 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &a)
         }
         __syncthreads();
         if constexpr (FINAL) {
-            stage<double, D * S::NP>(xl, a.nodes + (size_t)e * D * S::NP, lane);
+            stage_nodes<double, D, R, N>(xl, a.nodes + (size_t)e * D * S::NP, lane);
             run_element<double, D, R, N, true, KIND>(a, e, q0, q1, xl, tab, cache, citem, lane,
                                                      a.max_iter, a.tol, nullptr, cn);
         } else {
-            stage<float, D * S::NP>(xl, a.nodes32 + (size_t)e * D * S::NP, lane);
+            stage_nodes<float, D, R, N>(xl, a.nodes32 + (size_t)e * D * S::NP, lane);
             run_element<float, D, R, N, false, KIND>(a, e, q0, q1, xl, tab, cache, citem, lane,
                                                      a.max_iter32, a.tol32,
                                                      a.xc + (size_t)e * D, cn);
@@ -1218,7 +1273,7 @@ k_resolve_overflow(NewtonArgs a, HashView h)
             if (e == prim || !box_pass<D>(h.box + (size_t)e * (3 * D + D * D), x, depth))
                 continue;
             __syncthreads();
-            stage<double, D * S::NP>(xl, a.nodes + (size_t)e * D * S::NP, lane);
+            stage_nodes<double, D, R, N>(xl, a.nodes + (size_t)e * D * S::NP, lane);
             // nearest node: squared distance, lowest index among equals
             double bd = __builtin_huge_val();
             int bi = 0;
@@ -1226,7 +1281,7 @@ k_resolve_overflow(NewtonArgs a, HashView h)
                 double d2 = 0.0;
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    const double t = x[d] - xl[d * S::NP + j];
+                    const double t = x[d] - xl[NodeLds<double, D, R, N>::at(d, j / N, j % N)];
                     d2 = fma(t, t, d2);
                 }
                 if (d2 < bd) {
