@@ -214,7 +214,7 @@ def pcie_inclusive(gm, wl, fields, ws_f, ws_e, mode, steps):
                 steps=steps, precision=mode, bytes_over_pcie=int(moved))
 
 
-def serving(n_req, budget):
+def serving(n_req, budget, n_streams=4, max_batch=1 << 22):
     """The request loop over four resident curved hex meshes (p = 3, 5, 7,
     9; 46^3, 36^3, 27^3, 22^3 elements), Poisson arrivals of find + eval
     requests with 10^U(3,6) points, mixed precision; p50/p99 latency at
@@ -226,7 +226,7 @@ def serving(n_req, budget):
     sizes, mids, pts = SV.make_requests(n_req)
     log("serving: 4 meshes + %d requests (%d points) ready in %.1f s" % (
         n_req, int(sizes.sum()), time.perf_counter() - t0))
-    srv = fpts.Server(budget, n_streams=4, max_batch_points=1 << 22)
+    srv = fpts.Server(budget, n_streams=n_streams, max_batch_points=max_batch)
     ids = [srv.add_mesh(m, f) for _, m, f in meshes]
     rep = SV.sweep(srv, ids, sizes, mids, pts)
     srv.close()
@@ -235,7 +235,8 @@ def serving(n_req, budget):
             r["load"], r["rate_req_s"], r["p50_ms"], r["p99_ms"], r["mpts_s"]))
     rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
     return dict(meshes=[wl["name"] for wl, _, _ in meshes], requests=n_req,
-                points=int(sizes.sum()), precision="mixed", budget_bytes=budget, n_streams=4,
+                points=int(sizes.sum()), precision="mixed", budget_bytes=budget,
+                n_streams=n_streams, max_batch_points=max_batch,
                 saturation=rnd(rep["saturation"]),
                 saturated_rate_req_s=round(rep["saturated_rate_req_s"], 2),
                 loads=[rnd(r) for r in rep["loads"]], batches=rep["batches"],
@@ -384,6 +385,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests per serving run (0: no serving measurement)")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-max-batch", type=int, default=1 << 22)
     ap.add_argument("--pcie-steps", type=int, default=3,
                     help="steps of the host-to-host measurement (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -399,7 +402,7 @@ def main():
     ap.add_argument("--line-level", type=int, default=8,
                     help="refinement level of the 2D line-mesh run (84 x 2^level elements; "
                          "-1: skip)")
-    ap.add_argument("--only", choices=("lpt", "line"),
+    ap.add_argument("--only", choices=("lpt", "line", "serve"),
                     help="run only the particle-tracking or the line-mesh leg and print its "
                          "object (for profiling those kernels; not the benchmark line)")
     args = ap.parse_args()
@@ -415,6 +418,10 @@ def main():
     if args.only == "lpt":
         print(json.dumps(particle_tracking([float(r) for r in args.lpt_ratios.split(",")],
                                            args.lpt_steps, args.warmup, "fp64")), flush=True)
+        return
+    if args.only == "serve":
+        print(json.dumps(serving(args.serve_requests, int(args.serve_budget_gb * (1 << 30)),
+                                 args.serve_streams, args.serve_max_batch)), flush=True)
         return
     if args.only == "line":
         print(json.dumps(line_surface(max(args.line_level, 0), args.steps, args.warmup)),
@@ -596,7 +603,8 @@ def main():
     if args.line_level >= 0:
         line["line_mesh_2d"] = line_surface(args.line_level, 5, 1)
     if args.serve_requests > 0:
-        line["serving"] = serving(args.serve_requests, int(args.serve_budget_gb * (1 << 30)))
+        line["serving"] = serving(args.serve_requests, int(args.serve_budget_gb * (1 << 30)),
+                                  args.serve_streams, args.serve_max_batch)
     if not args.no_cpu:
         rep, om, orc, uo = cpu_baseline(wl, min(args.cpu_sample, n), log)
         line["cpu_baseline"] = rep
