@@ -15,9 +15,10 @@
 //     16 MFMA columns are the 16 slots and lane l receives four rows of each
 //     16-row tile (which four depends on the instruction) for its own slot.
 //   stage 2+3 (VALU): each lane weights its rows with phi_j(s) phi_k(t) (and
-//     derivatives) of its slot, read from a per-slot LDS table, and the four
-//     lanes of a slot are summed with two xor-shuffles.  Floating-point
-//     addition is commutative, so the four lanes end with bit-identical sums
+//     derivatives) of its slot, read from a per-slot LDS table (for N = 4, 8
+//     summed over k first, then weighted per j), and the four lanes of a
+//     slot are summed by lane swaps, four values at a time.  Each sum is
+//     formed once and broadcast, so the four lanes hold bit-identical values
 //     and run the Newton update redundantly and in step.
 // Second derivatives (beta = 1 passes on faces/edges, eq. eq_newton_hessian)
 // are computed in a separate sweep contracted with the slot's residual dx,
@@ -75,50 +76,105 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Sum over the four lanes of a slot (lanes l, l^16, l^32, l^48) with the
-// gfx950 lane-swap instructions.  v_permlane16_swap of a copy of v with
-// itself leaves every lane with its own value in one result and its xor-16
-// partner's in the other (v_permlane32_swap likewise for xor 32), so adding
-// the two results sums each pair of lanes, with the same operands in both
-// lanes of the pair: the four lanes of a slot end with bit-identical sums.
-__device__ __forceinline__ float pair_sum16(float v)
+// The two results of v_permlane16_swap (v_permlane32_swap) applied to (x, y):
+// the instruction trades rows (16-lane rows; 32-lane halves) between its two
+// registers, so each result holds, row by row, values of x from one row of
+// a row pair and values of y from the same row.  Used only in sums that
+// come out the same whichever half of a pair moves.
+template <typename T> struct Two { T a, b; };
+__device__ __forceinline__ Two<float> swap16(float x, float y)
 {
-    const unsigned u = __float_as_uint(v);
-    const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-    return __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                    false);
+    return {__uint_as_float(r[0]), __uint_as_float(r[1])};
 }
-__device__ __forceinline__ float pair_sum32(float v)
+__device__ __forceinline__ Two<float> swap32(float x, float y)
 {
-    const unsigned u = __float_as_uint(v);
-    const auto a = __builtin_amdgcn_permlane32_swap(u, u, false, false);
-    return __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false,
+                                                    false);
+    return {__uint_as_float(r[0]), __uint_as_float(r[1])};
 }
-__device__ __forceinline__ double pair_sum16(double v)
+__device__ __forceinline__ Two<double> swap16(double x, double y)
 {
-    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
-    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(x),
+                                                     (unsigned)__double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(x),
+                                                     (unsigned)__double2hiint(y), false, false);
+    return {__hiloint2double((int)hi[0], (int)lo[0]), __hiloint2double((int)hi[1], (int)lo[1])};
 }
-__device__ __forceinline__ double pair_sum32(double v)
+__device__ __forceinline__ Two<double> swap32(double x, double y)
 {
-    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
-    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-    return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(x),
+                                                     (unsigned)__double2loint(y), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(x),
+                                                     (unsigned)__double2hiint(y), false, false);
+    return {__hiloint2double((int)hi[0], (int)lo[0]), __hiloint2double((int)hi[1], (int)lo[1])};
 }
+
+// Sum of v over the four lanes of a slot (lanes l, l^16, l^32, l^48): the
+// swap of v with itself gives every lane its own value and its partner's, in
+// the same order in both lanes of the pair, so the four lanes end with
+// bit-identical sums.
 template <typename T>
 __device__ __forceinline__ T slot_sum(T v)
 {
-    return pair_sum32(pair_sum16(v));
+    Two<T> p = swap16(v, v);
+    v = p.a + p.b;
+    p = swap32(v, v);
+    return p.a + p.b;
 }
 
-// Row of the 16x16 output tile held by lane quarter g in item qq: the FP64
-// instruction interleaves rows (g + 4 qq), the FP32 one gives each quarter
-// four consecutive rows (4 g + qq); both checked on gfx950.
-template <typename T> __device__ __forceinline__ int out_row(int g, int qq);
-template <> __device__ __forceinline__ int out_row<double>(int g, int qq) { return g + 4 * qq; }
-template <> __device__ __forceinline__ int out_row<float>(int g, int qq) { return 4 * g + qq; }
+// slot_sum of K values, four at a time by transposition: the 16-lane swap of
+// (v0, v1) followed by an add leaves the row-pair sums of v0 in one row of
+// each pair and those of v1 in the other; the 32-lane swap of two such
+// results (v0/v1 and v2/v3) and an add complete the sums, the total of one
+// value per row.  The same swaps of a total with itself then broadcast each
+// row's total to the four rows.  Each total is formed once (bit-identical in
+// the four lanes), with 9 swaps per four values instead of 16.
+template <typename T, int K>
+__device__ __forceinline__ void slot_sum_all(T (&v)[K])
+{
+    constexpr int Q = K / 4;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        Two<T> p = swap16(v[4 * i], v[4 * i + 1]);
+        const T w01 = p.a + p.b;
+        p = swap16(v[4 * i + 2], v[4 * i + 3]);
+        const T w23 = p.a + p.b;
+        p = swap32(w01, w23);
+        const T z = p.a + p.b;
+        p = swap32(z, z);
+        const Two<T> h0 = swap16(p.a, p.a), h1 = swap16(p.b, p.b);
+        v[4 * i] = h0.a;
+        v[4 * i + 1] = h0.b;
+        v[4 * i + 2] = h1.a;
+        v[4 * i + 3] = h1.b;
+    }
+    if constexpr (K % 4 >= 2) {
+        constexpr int i = 4 * Q;
+        Two<T> p = swap16(v[i], v[i + 1]);
+        T w = p.a + p.b;
+        p = swap32(w, w);
+        w = p.a + p.b;
+        p = swap16(w, w);
+        v[i] = p.a;
+        v[i + 1] = p.b;
+    }
+    if constexpr (K % 2 == 1) v[K - 1] = slot_sum(v[K - 1]);
+}
+
+// Contraction row of the 16x16 output tile m held by lane quarter g in item
+// qq: 16 m + g + 4 qq.  The FP64 instruction interleaves the tile's rows that
+// way (item qq of quarter g is tile row g + 4 qq); the FP32 one gives each
+// quarter four consecutive tile rows (4 g + qq), so the FP32 A operand
+// supplies the rows transposed (a_row) to land on the same contraction rows.
+// Both layouts checked on gfx950.
+__device__ __forceinline__ int out_row(int m, int g, int qq) { return 16 * m + g + 4 * qq; }
+template <typename T>
+__device__ __forceinline__ int a_row(int m, int slot)
+{
+    return 16 * m + (std::is_same<T, double>::value ? slot : (slot >> 2) + 4 * (slot & 3));
+}
 
 template <int D, int R, int N>
 struct Shape {
@@ -236,12 +292,23 @@ struct Lds {
     }
 };
 
+// Stage 2+3 factored by j for hexes whose 16-row tiles hold whole (j, k)
+// blocks (N = 4, 8): a lane's rows 16 m + g + 4 qq have j = g + 4 (qq % NJ)
+// whatever m is, so the k-weights are summed per j first and the j-weights
+// applied once at the end.
+template <int R, int N>
+struct Factor {
+    static constexpr bool ON = R == 3 && (N == 4 || N == 8);
+    static constexpr int NJ = N / 4 > 0 ? N / 4 : 1;   // the lane's distinct j
+};
+
 // Sweep 1 for all 16 slots: x(q) and G = dx/dr of each slot's point.
 template <typename T, int D, int R, int N>
 __device__ __forceinline__ void sweep1(const T *xl, T *tab, int lane, const T (&q)[R], T (&X)[D],
                                        T (&G)[D][R])
 {
     typedef Shape<D, R, N> S;
+    typedef Factor<R, N> F;
     typedef typename V4<T>::type v4;
     const int slot = lane & 15, g = lane >> 4;
     // per-slot tables [direction][kind][i][slot] (kinds phi, phi'): lane
@@ -267,11 +334,20 @@ __device__ __forceinline__ void sweep1(const T *xl, T *tab, int lane, const T (&
         b0[ks] = i < N ? tr[(0 * N + i) * 16 + slot] : T(0);
         b1[ks] = i < N ? tr[(1 * N + i) * 16 + slot] : T(0);
     }
+    // the lane's partial sums: X, G directly, or (factored) per j the
+    // k-weighted sums Zv = sum_k C0 t_k, Zd = sum_k C1 t_k, Zt = sum_k C0 t'_k
+    T Zv[F::NJ][D], Zd[F::NJ][D], Zt[F::NJ][D];
 #pragma unroll
     for (int c = 0; c < D; ++c) {
         X[c] = T(0);
 #pragma unroll
         for (int a = 0; a < R; ++a) G[c][a] = T(0);
+#pragma unroll
+        for (int js = 0; js < F::NJ; ++js) {
+            Zv[js][c] = T(0);
+            Zd[js][c] = T(0);
+            Zt[js][c] = T(0);
+        }
     }
     constexpr bool kFullA = (N % 4 == 0) && (S::ROWS % 16 == 0);
 #pragma unroll 1
@@ -282,7 +358,7 @@ __device__ __forceinline__ void sweep1(const T *xl, T *tab, int lane, const T (&
             acc0[c] = v4{0, 0, 0, 0};
             acc1[c] = v4{0, 0, 0, 0};
         }
-        const int arow = 16 * m + slot;     // A-operand row of this lane
+        const int arow = a_row<T>(m, slot);   // A-operand row of this lane
 #pragma unroll
         for (int ks = 0; ks < S::KS; ++ks) {
             const int ai = 4 * ks + g;      // A-operand column (node index i)
@@ -297,12 +373,20 @@ __device__ __forceinline__ void sweep1(const T *xl, T *tab, int lane, const T (&
                 acc1[c] = mfma16(a, b1[ks], acc1[c]);
             }
         }
-        // rows 4g + qq of tile m belong to this lane's slot
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
-            const int row = 16 * m + out_row<T>(g, qq);
+            const int row = out_row(m, g, qq);
             if (S::ROWS % 16 != 0 && row >= S::ROWS) continue;
-            if constexpr (R == 3) {
+            if constexpr (F::ON) {
+                const int k = (16 * m + 4 * qq) / N, js = qq % F::NJ;   // row / N (g < 4)
+                const T tv = tt[(0 * N + k) * 16 + slot], td = tt[(1 * N + k) * 16 + slot];
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    Zv[js][c] = fma(acc0[c][qq], tv, Zv[js][c]);
+                    Zd[js][c] = fma(acc1[c][qq], tv, Zd[js][c]);
+                    Zt[js][c] = fma(acc0[c][qq], td, Zt[js][c]);
+                }
+            } else if constexpr (R == 3) {
                 const int j = row % N, k = row / N;
                 const T sv = ts[(0 * N + j) * 16 + slot], sd = ts[(1 * N + j) * 16 + slot];
                 const T tv = tt[(0 * N + k) * 16 + slot], td = tt[(1 * N + k) * 16 + slot];
@@ -326,11 +410,33 @@ __device__ __forceinline__ void sweep1(const T *xl, T *tab, int lane, const T (&
             }
         }
     }
+    if constexpr (F::ON) {
+#pragma unroll
+        for (int js = 0; js < F::NJ; ++js) {
+            const int j = g + 4 * js;
+            const T sv = ts[(0 * N + j) * 16 + slot], sd = ts[(1 * N + j) * 16 + slot];
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                X[c] = fma(Zv[js][c], sv, X[c]);
+                G[c][0] = fma(Zd[js][c], sv, G[c][0]);
+                G[c][1] = fma(Zv[js][c], sd, G[c][1]);
+                G[c][2] = fma(Zt[js][c], sv, G[c][2]);
+            }
+        }
+    }
+    T v[D * (R + 1)];
 #pragma unroll
     for (int c = 0; c < D; ++c) {
-        X[c] = slot_sum(X[c]);
+        v[c] = X[c];
 #pragma unroll
-        for (int a = 0; a < R; ++a) G[c][a] = slot_sum(G[c][a]);
+        for (int a = 0; a < R; ++a) v[D + c * R + a] = G[c][a];
+    }
+    slot_sum_all(v);
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        X[c] = v[c];
+#pragma unroll
+        for (int a = 0; a < R; ++a) G[c][a] = v[D + c * R + a];
     }
 }
 
@@ -340,6 +446,7 @@ __device__ __forceinline__ void sweep2(const T *xl, T *tab, int lane, const T (&
                                        const T (&dx)[D], T (&Sout)[kSym<R>])
 {
     typedef Shape<D, R, N> S;
+    typedef Factor<R, N> F;
     typedef typename V4<T>::type v4;
     const int slot = lane & 15, g = lane >> 4;
     T b0[S::KS], b1[S::KS], b2[S::KS];
@@ -361,15 +468,23 @@ __device__ __forceinline__ void sweep2(const T *xl, T *tab, int lane, const T (&
         basis_table<T, N, true>(x, tab + (g == 2 ? 3 * N * 16 : 0), slot, w);
     }
     wave_lds_sync();
+    const T *tt = tab + 3 * N * 16;
     T Sa[kSym<R>];
+    // factored: per j, Z[0..5] = sum_k of C2 t, C0 t, C0 t'', C1 t, C1 t',
+    // C0 t' (then times s, s'', s, s', s, s' of j)
+    T Z[F::NJ][6];
 #pragma unroll
     for (int a = 0; a < kSym<R>; ++a) Sa[a] = T(0);
+#pragma unroll
+    for (int js = 0; js < F::NJ; ++js)
+#pragma unroll
+        for (int a = 0; a < 6; ++a) Z[js][a] = T(0);
 #pragma unroll 1
     for (int m = 0; m < S::MT; ++m) {
         // the slot's residual enters the B operand, so one accumulator per
         // basis kind collects sum_c dx_c C_c[row][slot] over the coordinates
         v4 acc0 = v4{0, 0, 0, 0}, acc1 = v4{0, 0, 0, 0}, acc2 = v4{0, 0, 0, 0};
-        const int arow = 16 * m + slot;
+        const int arow = a_row<T>(m, slot);
 #pragma unroll
         for (int ks = 0; ks < S::KS; ++ks) {
             const int ai = 4 * ks + g;
@@ -384,14 +499,23 @@ __device__ __forceinline__ void sweep2(const T *xl, T *tab, int lane, const T (&
         }
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
-            const int row = 16 * m + out_row<T>(g, qq);
+            const int row = out_row(m, g, qq);
             if (S::ROWS % 16 != 0 && row >= S::ROWS) continue;
             const T C0 = acc0[qq], C1 = acc1[qq], C2 = acc2[qq];
-            if constexpr (R == 3) {
+            if constexpr (F::ON) {
+                const int k = (16 * m + 4 * qq) / N, js = qq % F::NJ;
+                const T tv = tt[(0 * N + k) * 16 + slot], td = tt[(1 * N + k) * 16 + slot];
+                const T tdd = tt[(2 * N + k) * 16 + slot];
+                Z[js][0] = fma(C2, tv, Z[js][0]);
+                Z[js][1] = fma(C0, tv, Z[js][1]);
+                Z[js][2] = fma(C0, tdd, Z[js][2]);
+                Z[js][3] = fma(C1, tv, Z[js][3]);
+                Z[js][4] = fma(C1, td, Z[js][4]);
+                Z[js][5] = fma(C0, td, Z[js][5]);
+            } else if constexpr (R == 3) {
                 const int j = row % N, k = row / N;
                 const T sv = tab[(0 * N + j) * 16 + slot], sd = tab[(1 * N + j) * 16 + slot];
                 const T sdd = tab[(2 * N + j) * 16 + slot];
-                const T *tt = tab + 3 * N * 16;
                 const T tv = tt[(0 * N + k) * 16 + slot], td = tt[(1 * N + k) * 16 + slot];
                 const T tdd = tt[(2 * N + k) * 16 + slot];
                 Sa[0] = fma(C2, sv * tv, Sa[0]);    // rr
@@ -410,8 +534,23 @@ __device__ __forceinline__ void sweep2(const T *xl, T *tab, int lane, const T (&
             }
         }
     }
+    if constexpr (F::ON) {
 #pragma unroll
-    for (int a = 0; a < kSym<R>; ++a) Sout[a] = slot_sum(Sa[a]);
+        for (int js = 0; js < F::NJ; ++js) {
+            const int j = g + 4 * js;
+            const T sv = tab[(0 * N + j) * 16 + slot], sd = tab[(1 * N + j) * 16 + slot];
+            const T sdd = tab[(2 * N + j) * 16 + slot];
+            Sa[0] = fma(Z[js][0], sv, Sa[0]);    // rr
+            Sa[1] = fma(Z[js][1], sdd, Sa[1]);   // ss
+            Sa[2] = fma(Z[js][2], sv, Sa[2]);    // tt
+            Sa[3] = fma(Z[js][3], sd, Sa[3]);    // rs
+            Sa[4] = fma(Z[js][4], sv, Sa[4]);    // rt
+            Sa[5] = fma(Z[js][5], sd, Sa[5]);    // st
+        }
+    }
+    slot_sum_all(Sa);
+#pragma unroll
+    for (int a = 0; a < kSym<R>; ++a) Sout[a] = Sa[a];
 }
 
 // Objective at a point: f = |x* - x|^2, g = G^T dx, Hgn = G^T G (packed).
@@ -460,7 +599,7 @@ __device__ __forceinline__ bool solve_free(const T (&H)[kSym<R>], const T (&g)[R
         for (int c = 0; c < R; ++c)
             A[a][c] = (held[a] || held[c]) ? (a == c ? T(1) : T(0)) : H[sym<R>(a, c)];
     }
-    T L[R][R], d[R];
+    T L[R][R], d[R], inv[R];
     bool ok = true;
 #pragma unroll
     for (int a = 0; a < R; ++a) {
@@ -469,13 +608,13 @@ __device__ __forceinline__ bool solve_free(const T (&H)[kSym<R>], const T (&g)[R
         for (int k = 0; k < a; ++k) s -= L[a][k] * L[a][k] * d[k];
         d[a] = s;
         ok = ok && (s > T(0));
-        const T inv = T(1) / s;
+        inv[a] = T(1) / s;   // one division per pivot
 #pragma unroll
         for (int c = a + 1; c < R; ++c) {
             T t = A[c][a];
 #pragma unroll
             for (int k = 0; k < a; ++k) t -= L[c][k] * L[a][k] * d[k];
-            L[c][a] = t * inv;
+            L[c][a] = t * inv[a];
         }
     }
     T y[R];
@@ -488,7 +627,7 @@ __device__ __forceinline__ bool solve_free(const T (&H)[kSym<R>], const T (&g)[R
     }
 #pragma unroll
     for (int a = R - 1; a >= 0; --a) {
-        T s = y[a] / d[a];
+        T s = y[a] * inv[a];
 #pragma unroll
         for (int k = a + 1; k < R; ++k) s -= L[k][a] * x[k];
         x[a] = s;
