@@ -140,15 +140,33 @@ __device__ __forceinline__ double contract(P u, const double (&v0)[N], const dou
 // otherwise they are read with scalar loads.  Staging wins when an element
 // holds few points (its values are cold, and scalar loads of them stall on
 // latency); when many tasks share an element its values stay in the scalar
-// cache and the scalar operands save the LDS reads.
+// cache and the scalar operands save the LDS reads.  The staged loads are
+// software-pipelined: the values of the next field (or of the next task's
+// first field) are loaded into registers while the current field is
+// contracted, so their latency hides behind the arithmetic.
 template <int R, int N, bool LDS>
 __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
 {
     constexpr int NP = (R == 3) ? N * N * N : (R == 2) ? N * N : N;
+    constexpr int PER = (NP + 63) / 64;   // staged values per lane
     extern __shared__ double ldsu[];   // [NP] (LDS staging)
     const int lane = threadIdx.x;
     const int total = a.chunk_off[a.nel];
-    for (int t = task_of_block(); t < total; t += gridDim.x) {
+    const int G = gridDim.x;
+    double pre[PER];
+    // the nodal values of field f of element e into pre
+    auto fetch = [&](int e, int f) {
+        const double *src = a.field + ((size_t)f * a.nel + e) * NP;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int j = lane + 64 * k;
+            pre[k] = (NP % 64 == 0 || j < NP) ? src[j] : 0.0;
+        }
+    };
+    int t = task_of_block();
+    if (LDS && t < total && a.n_fields > 0)
+        fetch(__builtin_amdgcn_readfirstlane(a.task_elem[t]), 0);
+    for (; t < total; t += G) {
         const int e = __builtin_amdgcn_readfirstlane(a.task_elem[t]);
         const int beg = a.elem_off[e] + (t - a.chunk_off[e]) * kChunk;
         const int end = min(a.elem_off[e + 1], beg + kChunk);
@@ -165,15 +183,21 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
         if (R >= 2) basis_v<N>(has ? rr[1] : 0.0, a.basis.z, a.basis.w, v1);
         if (R == 3) basis_v<N>(has ? rr[2] : 0.0, a.basis.z, a.basis.w, v2);
         for (int f = 0; f < a.n_fields; ++f) {
-            const double *src = a.field + ((size_t)f * a.nel + e) * NP;
             double acc;
             if constexpr (LDS) {
                 __syncthreads();   // the previous field's reads come first
-                for (int j = lane; j < NP; j += 64) ldsu[j] = src[j];
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int j = lane + 64 * k;
+                    if (NP % 64 == 0 || j < NP) ldsu[j] = pre[k];
+                }
                 __syncthreads();
+                if (f + 1 < a.n_fields) fetch(e, f + 1);
+                else if (t + G < total) fetch(__builtin_amdgcn_readfirstlane(a.task_elem[t + G]), 0);
                 acc = contract<R, N>((const double *)ldsu, v0, v1, v2);
             } else {
-                acc = contract<R, N>((cdouble *)src, v0, v1, v2);
+                acc = contract<R, N>((cdouble *)(a.field + ((size_t)f * a.nel + e) * NP), v0, v1,
+                                     v2);
             }
             if (has) a.out[(size_t)f * a.n + p] = acc;
         }

@@ -1106,7 +1106,7 @@ struct NearLds {
     static constexpr bool B_IN_LDS = std::is_same<T, float>::value;
     static constexpr size_t bytes()
     {
-        return sizeof(T) * 4 * ((B_IN_LDS ? NPAD : 0) + 64) + sizeof(int) * 64;
+        return sizeof(T) * (4 * ((B_IN_LDS ? NPAD : 0) + 64) + 64) + sizeof(int) * 64;
     }
 };
 
@@ -1117,6 +1117,26 @@ struct NearLds {
 // (x, y, z, 1) with (-2 x_j, -2 y_j, -2 z_j, |x_j|^2): one 16 x 16 x 4 MFMA
 // scores 16 pairs against 16 nodes.  Coordinates are element-local (node
 // block minus the element centre) to keep the cancellation small.
+// FP64: the accumulator starts at |x|^2, so the MFMA yields the squared
+// distance itself (non-negative), and the node index replaces the low
+// kNodeBits mantissa bits; one minimum per score then keeps the nearest node
+// with ties (equal to 2^-42 relative) to the lowest index.
+constexpr int kNodeBits = 10;   // node indices below 1024 (N <= 10)
+__device__ __forceinline__ double with_node(double d, int node)
+{
+    constexpr unsigned m = (1u << kNodeBits) - 1;
+    const unsigned lo = ((unsigned)__double2loint(d) & ~m) | ((unsigned)node & m);   // v_bfi
+    return __hiloint2double(__double2hiint(d), (int)lo);
+}
+// min of two keys: the keys are finite or +inf (never NaN), so the plain
+// instruction serves; fmin() would first quiet both operands, which the
+// compiler cannot prove to be ordinary numbers after the bit insertion.
+__device__ __forceinline__ double key_min(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 template <int D, int R, int N, bool MIXED>
 __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
 {
@@ -1130,7 +1150,8 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
     extern __shared__ double lds_raw[];
     T *Bt = reinterpret_cast<T *>(lds_raw);                  // [4][NPAD] (FP32)
     T *Pt = Bt + (L::B_IN_LDS ? 4 * L::NPAD : 0);            // [4][64]
-    int *items = reinterpret_cast<int *>(Pt + 4 * 64);       // [64]
+    T *Xx = Pt + 4 * 64;                                     // [64] |x|^2
+    int *items = reinterpret_cast<int *>(Xx + 64);           // [64]
     const int lane = threadIdx.x, col = lane & 15, g = lane >> 4;
     const NewtonIO &io = a.io;
     const int total = io.chunk_off[a.nel];
@@ -1173,76 +1194,126 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
             for (int c = 0; c < D; ++c)
                 pa[c] = has ? T(point_coord<D>(a, p, c) - xc[c]) : T(0);
             pa[D] = T(1);
+            T xx = T(0);
+#pragma unroll
+            for (int c = 0; c < D; ++c) xx = fma(pa[c], pa[c], xx);
 #pragma unroll
             for (int k = 0; k < 4; ++k) Pt[k * 64 + lane] = pa[k];
+            Xx[lane] = xx;
         }
         wave_lds_sync();
         const int ntile = (cnt + 15) >> 4;   // pair tiles of this task (wave-uniform)
-        T av[4], best[4][4];
-        int bix[4][4];
+        // the start of the pair at task position pl: node bi's reference point
+        auto write_start = [&](int bi, int pl) {
+            const int item = items[pl];
+            const int ii[3] = {bi % N, (bi / N) % N, bi / (N * N)};
 #pragma unroll
-        for (int pt = 0; pt < 4; ++pt) {
-            av[pt] = Pt[g * 64 + 16 * pt + col];
+            for (int k = 0; k < R; ++k) {
+                double v = GT.z[0];
 #pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-                best[pt][qq] = T(__builtin_huge_valf());
-                bix[pt][qq] = 0;
+                for (int m = 1; m < N; ++m)
+                    if (ii[k] == m) v = GT.z[m];
+                if (io.start)
+                    io.start[(size_t)k * io.start_stride + beg + pl] = v;
+                else
+                    io.r[(size_t)k * io.ostride + item] = v;
             }
-        }
-        // node tiles outside, pair tiles inside: each B value is read once
-        // per task and scores every pair tile
-#pragma unroll 2
-        for (int nt = 0; nt < NT; ++nt) {
-            const T bv = L::B_IN_LDS ? Bt[g * L::NPAD + 16 * nt + col]
-                                     : T(a.near[((size_t)e * 4 + g) * L::NPAD + 16 * nt + col]);
-            const int node = 16 * nt + col;
+        };
+        if constexpr (!MIXED) {
+            v4 seed[4];
+            double av[4], best[4][4];
 #pragma unroll
             for (int pt = 0; pt < 4; ++pt) {
-                if (pt < ntile) {
-                    const v4 d = mfma16(av[pt], bv, v4{0, 0, 0, 0});
+                av[pt] = Pt[g * 64 + 16 * pt + col];
 #pragma unroll
-                    for (int qq = 0; qq < 4; ++qq) {
-                        const bool lt = d[qq] < best[pt][qq];
-                        bix[pt][qq] = lt ? node : bix[pt][qq];
-                        best[pt][qq] = lt ? d[qq] : best[pt][qq];
+                for (int qq = 0; qq < 4; ++qq) {
+                    seed[pt][qq] = Xx[16 * pt + g + 4 * qq];   // pair of output row g + 4 qq
+                    best[pt][qq] = __builtin_huge_val();
+                }
+            }
+#pragma unroll 2
+            for (int nt = 0; nt < NT; ++nt) {
+                const double bv = a.near[((size_t)e * 4 + g) * L::NPAD + 16 * nt + col];
+                const int node = 16 * nt + col;
+#pragma unroll
+                for (int pt = 0; pt < 4; ++pt) {
+                    if (pt < ntile) {
+                        const v4 d = mfma16(av[pt], bv, seed[pt]);
+#pragma unroll
+                        for (int qq = 0; qq < 4; ++qq)
+                            best[pt][qq] = key_min(best[pt][qq], with_node(d[qq], node));
                     }
                 }
             }
-        }
 #pragma unroll
-        for (int pt = 0; pt < 4; ++pt) {
-            if (pt >= ntile) break;
-            // lexicographic (score, node) minimum over the 16 lanes of a row
+            for (int pt = 0; pt < 4; ++pt) {
+                if (pt >= ntile) break;
 #pragma unroll
-            for (int o = 1; o < 16; o <<= 1) {
+                for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+                    for (int qq = 0; qq < 4; ++qq)
+                        best[pt][qq] = key_min(best[pt][qq], __shfl_xor(best[pt][qq], o));
+                // lane `col` < 4 writes the pair of output row g + 4 col
+                const double bk = col == 0 ? best[pt][0]
+                                  : col == 1 ? best[pt][1]
+                                  : col == 2 ? best[pt][2]
+                                             : best[pt][3];
+                const int pl = 16 * pt + g + 4 * col;
+                if (col < 4 && pl < cnt)
+                    write_start(__double2loint(bk) & ((1 << kNodeBits) - 1), pl);
+            }
+        } else {
+            T av[4], best[4][4];
+            int bix[4][4];
+#pragma unroll
+            for (int pt = 0; pt < 4; ++pt) {
+                av[pt] = Pt[g * 64 + 16 * pt + col];
 #pragma unroll
                 for (int qq = 0; qq < 4; ++qq) {
-                    const T so = __shfl_xor(best[pt][qq], o);
-                    const int io2 = __shfl_xor(bix[pt][qq], o);
-                    const bool take =
-                        so < best[pt][qq] || (so == best[pt][qq] && io2 < bix[pt][qq]);
-                    bix[pt][qq] = take ? io2 : bix[pt][qq];
-                    best[pt][qq] = take ? so : best[pt][qq];
+                    best[pt][qq] = T(__builtin_huge_valf());
+                    bix[pt][qq] = 0;
                 }
             }
-            // lane `col` < 4 writes the pair of its row group held in item qq = col
-            int bi = bix[pt][0] * (col == 0) + bix[pt][1] * (col == 1) +
-                     bix[pt][2] * (col == 2) + bix[pt][3] * (col == 3);
-            const int pl = 16 * pt + (MIXED ? 4 * g + col : g + 4 * col);
-            if (col < 4 && pl < cnt) {
-                const int item = items[pl];
-                const int ii[3] = {bi % N, (bi / N) % N, bi / (N * N)};
+            // node tiles outside, pair tiles inside: each B value is read once
+            // per task and scores every pair tile
+#pragma unroll 2
+            for (int nt = 0; nt < NT; ++nt) {
+                const T bv = Bt[g * L::NPAD + 16 * nt + col];
+                const int node = 16 * nt + col;
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    double v = GT.z[0];
+                for (int pt = 0; pt < 4; ++pt) {
+                    if (pt < ntile) {
+                        const v4 d = mfma16(av[pt], bv, v4{0, 0, 0, 0});
 #pragma unroll
-                    for (int m = 1; m < N; ++m)
-                        if (ii[k] == m) v = GT.z[m];
-                    if (io.start)
-                        io.start[(size_t)k * io.start_stride + beg + pl] = v;
-                    else
-                        io.r[(size_t)k * io.ostride + item] = v;
+                        for (int qq = 0; qq < 4; ++qq) {
+                            const bool lt = d[qq] < best[pt][qq];
+                            bix[pt][qq] = lt ? node : bix[pt][qq];
+                            best[pt][qq] = lt ? d[qq] : best[pt][qq];
+                        }
+                    }
                 }
+            }
+#pragma unroll
+            for (int pt = 0; pt < 4; ++pt) {
+                if (pt >= ntile) break;
+                // lexicographic (score, node) minimum over the 16 lanes of a row
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) {
+#pragma unroll
+                    for (int qq = 0; qq < 4; ++qq) {
+                        const T so = __shfl_xor(best[pt][qq], o);
+                        const int io2 = __shfl_xor(bix[pt][qq], o);
+                        const bool take =
+                            so < best[pt][qq] || (so == best[pt][qq] && io2 < bix[pt][qq]);
+                        bix[pt][qq] = take ? io2 : bix[pt][qq];
+                        best[pt][qq] = take ? so : best[pt][qq];
+                    }
+                }
+                // lane `col` < 4 writes the pair of its row group held in item qq = col
+                int bi = bix[pt][0] * (col == 0) + bix[pt][1] * (col == 1) +
+                         bix[pt][2] * (col == 2) + bix[pt][3] * (col == 3);
+                const int pl = 16 * pt + 4 * g + col;   // FP32 output layout
+                if (col < 4 && pl < cnt) write_start(bi, pl);
             }
         }
     }
@@ -1320,13 +1391,18 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &a)
 // The primary pass and the pass over the other candidates of unsettled
 // points run the same code under two kernel names, so that a kernel trace
 // reports them apart.
+// (at least two waves per SIMD: the register budget then stays within the
+// 256 VGPRs, and the compiler gives the MFMA results VGPRs, not AGPRs that
+// the selection would first have to copy out)
 template <int D, int R, int N, bool MIXED>
-__global__ __launch_bounds__(64) void k_nearest(NewtonArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void
+k_nearest(NewtonArgs a)
 {
     nearest_body<D, R, N, MIXED>(a);
 }
 template <int D, int R, int N, bool MIXED>
-__global__ __launch_bounds__(64) void k_nearest_resolve(NewtonArgs a)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void
+k_nearest_resolve(NewtonArgs a)
 {
     nearest_body<D, R, N, MIXED>(a);
 }
