@@ -895,27 +895,38 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
     }
     {
         // the rest (settled by the second search, BORDER, NOT_FOUND): the
-        // plain interpolation path restricted to them
-        // (they are few and scattered: elements holding at most a few of
-        // them have their points interpolated one lane per point)
+        // plain interpolation path restricted to them.  They are few and
+        // scattered; on line meshes, elements holding at most a few of them
+        // have their points interpolated one lane per point (the per-lane
+        // arithmetic of the element tasks); the other meshes interpolate
+        // every point on the matrix cores, as fpts_eval does, so both calls
+        // give the same bits
+        const bool split = m->R == 1;
         Span sp(m, 4, s);
         chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
         chk(launch_fill_i32(scount, 1, 0, s));
         chk(launch_eval_bin(m, 0, n, d_code, d_elem, d_r, primary, n_fields, d_out, elem_cnt,
                             nullptr, erank, nullptr, s));
-        chk(launch_eval_split(m, n, d_elem, erank, elem_cnt, nullptr, nullptr, nullptr, nullptr,
-                              0, s));
+        if (split)
+            chk(launch_eval_split(m, n, d_elem, erank, elem_cnt, nullptr, nullptr, nullptr,
+                                  nullptr, 0, s));
         chk(launch_exclusive_scan(elem_cnt, eoff, m->nel, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt, choff, m->nel, kChunk, tmp, tb, s));
         chk(launch_task_map(choff, m->nel, etask, s));
-        chk(launch_eval_split(m, n, d_elem, erank, elem_cnt, eoff, esorted, slist, scount, 1, s));
+        if (split)
+            chk(launch_eval_split(m, n, d_elem, erank, elem_cnt, eoff, esorted, slist, scount, 1,
+                                  s));
+        else
+            chk(launch_eval_bin(m, 1, n, d_code, d_elem, d_r, primary, n_fields, d_out, nullptr,
+                                eoff, erank, esorted, s));
     }
     {
         Span sp(m, 5, s);
         chk(launch_eval(m, n, d_r, n_fields, field_nodes_1d, d_field, d_out, esorted, eoff,
                         choff, etask, v.tb_elem, s));
-        chk(launch_eval_sparse(m, n, d_r, n_fields, field_nodes_1d, d_field, d_out, d_elem, slist,
-                               scount, s));
+        if (m->R == 1)
+            chk(launch_eval_sparse(m, n, d_r, n_fields, field_nodes_1d, d_field, d_out, d_elem,
+                                   slist, scount, s));
     }
     if (m->profiling) m->prof_eval++;
     return e == hipSuccess ? FPTS_OK : FPTS_EDEVICE;

@@ -5,10 +5,15 @@
 // grouping by element the paper's CPU code uses, Section 5 remark), then a
 // wavefront takes up to 64 points of ONE element, stages the element's nodal
 // values in LDS (once per wave, not once per point) and each lane contracts
-// them sum-factorised: N^3 + N^2 + N FMAs per field and point.
+// them sum-factorised: N^3 + N^2 + N FMAs per field and point.  On quad, hex
+// and surface meshes the first contraction runs on the matrix cores, 16
+// points at a time (k_eval_mfma): every lane reading the same staged value
+// (a broadcast, 64 copies per read) left the per-lane form bound by LDS
+// bandwidth.  Line meshes keep the per-lane form.
 // Also: the FP32 element-local node copy used by mixed-precision Newton.
 #include "fpts_internal.hpp"
 #include "gll_table.hpp"
+#include "newton_mfma.hpp"
 
 namespace fpts {
 namespace {
@@ -97,6 +102,7 @@ struct EvalArgs {
     // fused mode (rs != null): `sorted` is the primary list of Find and
     // r comes from rs[k * n + list position]; NaN there skips the point
     const double *rs;
+    int f0;                 // first field of this launch (k_eval_mfma)
 };
 
 typedef const __attribute__((address_space(4))) double cdouble;
@@ -204,11 +210,164 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
     }
 }
 
-// Points of elements that hold at most kSparseMax of the points to
-// interpolate, one lane per point: a wavefront per element task would run
-// the whole element's contraction for one or two points.  Each lane reads
-// its own element's nodal values (global loads), with the arithmetic of
-// k_eval, so both give the same bits.  Grid-stride over the list.
+// Interpolation with the first contraction on the matrix cores (quad, hex
+// and surface meshes; FC fields a0.f0 .. a.f0 + FC - 1 per launch).  One
+// wavefront per task of up to 64 points of one element (task grid): the FC
+// fields of the element are staged in LDS (layout of the Newton kernels'
+// node block, one field per coordinate slot), and the points are taken 16 at
+// a time, one per slot of four lanes (slot = lane % 16, quarter g = lane /
+// 16).  Quarter g builds the bases of direction g of its slot's point; then
+// C_f[row][s] = sum_i u_f[i][row] phi_i(r_s) by v_mfma_f64_16x16x4 (A = the
+// element's values, row = (j, k) or j; B = the slots' phi_i), each lane
+// weights its four rows of each tile with phi_j(s) phi_k(t) of its slot
+// (hexes with N = 4, 8: summed over k first, then weighted per j), and the
+// four lanes of a slot are summed.  A point's value depends on its own
+// coordinates and element only, not on the group it lands in.
+// (at least two waves per SIMD: the register budget then stays within the
+// 256 VGPRs and the MFMA results land in VGPRs, not in AGPRs to copy out)
+template <int R, int N, int FC>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void
+k_eval_mfma(EvalArgs a)
+{
+    typedef newton::Shape<3, R, N> S;
+    typedef newton::NodeLds<double, FC, R, N> L;
+    typedef newton::Factor<R, N> F;
+    typedef newton::V4<double>::type v4;
+    constexpr int NP = S::NP, MT = S::MT, KS = S::KS, ROWS = S::ROWS;
+    constexpr int PER = (NP + 63) / 64;
+    constexpr bool kFullA = (N % 4 == 0) && (ROWS % 16 == 0);
+    extern __shared__ double lds_eval[];
+    double *xl = lds_eval;        // the FC fields, NodeLds layout
+    double *tab = xl + L::SIZE;   // [R][N][16] bases of the group's points
+    const int lane = threadIdx.x, slot = lane & 15, g = lane >> 4;
+    const int total = a.chunk_off[a.nel];
+    for (int t = task_of_block(); t < total; t += gridDim.x) {
+        const int e = __builtin_amdgcn_readfirstlane(a.task_elem[t]);
+        const int beg = a.elem_off[e] + (t - a.chunk_off[e]) * kChunk;
+        const int end = min(a.elem_off[e + 1], beg + kChunk);
+        const int idx = beg + lane;
+        bool has = idx < end;
+        const int p = has ? a.sorted[idx] : 0;
+        double rr[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (has) rr[k] = a.rs ? a.rs[(size_t)k * a.n + idx] : a.r[(size_t)k * a.n + p];
+        if (a.rs) has = has && !__builtin_isnan(rr[0]);
+        // stage the element's FC fields (every load issued before the stores)
+        {
+            double v[FC][PER];
+#pragma unroll
+            for (int f = 0; f < FC; ++f) {
+                const double *src = a.field + ((size_t)(a.f0 + f) * a.nel + e) * NP;
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int j = lane + 64 * k;
+                    v[f][k] = (NP % 64 == 0 || j < NP) ? src[j] : 0.0;
+                }
+            }
+            __syncthreads();   // the previous task's reads come first
+#pragma unroll
+            for (int f = 0; f < FC; ++f)
+#pragma unroll
+                for (int k = 0; k < PER; ++k) {
+                    const int j = lane + 64 * k;
+                    if (NP % 64 == 0 || j < NP) xl[L::at(f, j / N, j % N)] = v[f][k];
+                }
+            __syncthreads();
+        }
+        const int ngrp = (end - beg + 15) >> 4;
+        for (int grp = 0; grp < ngrp; ++grp) {
+            const int pl = 16 * grp + slot;   // task position of this slot's point
+            // coordinate g of that point (each coordinate shuffled, then the
+            // quarter's one selected)
+            const double c0 = __shfl(rr[0], pl);
+            const double c1 = R >= 2 ? __shfl(rr[1], pl) : 0.0;
+            const double c2 = R == 3 ? __shfl(rr[2], pl) : 0.0;
+            const double x = g == 0 ? c0 : g == 1 ? c1 : c2;
+            newton::wave_lds_sync();   // the previous group's table reads come first
+            if (g < R) {
+                double pv[N];
+                pv[0] = 1.0;
+#pragma unroll
+                for (int i = 1; i < N; ++i) pv[i] = pv[i - 1] * (x - a.basis.z[i - 1]);
+                double sv = 1.0;
+#pragma unroll
+                for (int i = N - 1; i >= 0; --i) {
+                    tab[(g * N + i) * 16 + slot] = a.basis.w[i] * (pv[i] * sv);
+                    sv *= x - a.basis.z[i];
+                }
+            }
+            newton::wave_lds_sync();
+            const double *ts = tab + N * 16, *tt = tab + 2 * N * 16;
+            double b0[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int i = 4 * ks + g;
+                b0[ks] = i < N ? tab[i * 16 + slot] : 0.0;
+            }
+            double X[FC], Z[F::NJ][FC];
+#pragma unroll
+            for (int f = 0; f < FC; ++f) {
+                X[f] = 0.0;
+#pragma unroll
+                for (int js = 0; js < F::NJ; ++js) Z[js][f] = 0.0;
+            }
+#pragma unroll(MT <= 4 ? MT : 1)
+            for (int m = 0; m < MT; ++m) {
+                v4 acc[FC];
+#pragma unroll
+                for (int f = 0; f < FC; ++f) acc[f] = v4{0, 0, 0, 0};
+                const int arow = 16 * m + slot;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    const int ai = 4 * ks + g;
+                    const bool aok = kFullA || (arow < ROWS && ai < N);
+#pragma unroll
+                    for (int f = 0; f < FC; ++f)
+                        acc[f] = newton::mfma16(xl[aok ? L::at(f, arow, ai) : 0], b0[ks], acc[f]);
+                }
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq) {
+                    const int row = newton::out_row(m, g, qq);
+                    if (ROWS % 16 != 0 && row >= ROWS) continue;
+                    if constexpr (F::ON) {
+                        const int k = (16 * m + 4 * qq) / N, js = qq % F::NJ;
+                        const double tv = tt[k * 16 + slot];
+#pragma unroll
+                        for (int f = 0; f < FC; ++f) Z[js][f] = fma(acc[f][qq], tv, Z[js][f]);
+                    } else {
+                        const double w = R == 3 ? ts[(row % N) * 16 + slot] * tt[(row / N) * 16 + slot]
+                                                : ts[row * 16 + slot];
+#pragma unroll
+                        for (int f = 0; f < FC; ++f) X[f] = fma(acc[f][qq], w, X[f]);
+                    }
+                }
+            }
+            if constexpr (F::ON) {
+#pragma unroll
+                for (int js = 0; js < F::NJ; ++js) {
+                    const double sv = ts[(g + 4 * js) * 16 + slot];
+#pragma unroll
+                    for (int f = 0; f < FC; ++f) X[f] = fma(Z[js][f], sv, X[f]);
+                }
+            }
+            newton::slot_sum_all(X);
+            const bool hp = __shfl((int)has, pl) != 0;
+            const int pp = __shfl(p, pl);
+            // quarter g writes field g of its slot's point
+#pragma unroll
+            for (int f = 0; f < FC; ++f)
+                if (hp && g == f) a.out[(size_t)(a.f0 + f) * a.n + pp] = X[f];
+        }
+    }
+}
+
+// Line meshes: points of elements that hold at most kSparseMax of the
+// points to interpolate, one lane per point: a wavefront per element task
+// would run the whole element's contraction for one or two points.  Each
+// lane reads its own element's nodal values (global loads), with the
+// arithmetic of k_eval, so both give the same bits.  Grid-stride over the
+// list.
 template <int R, int N>
 __global__ __launch_bounds__(256) void k_eval_sparse(EvalArgs a, const int32_t *elem,
                                                     const int *list, const int *count)
@@ -358,10 +517,39 @@ SparseFn pick_sparse(int N)
     }
 }
 
+template <int R, int FC>
+EvalFn pick_eval_mfma(int N, size_t *lds)
+{
+    switch (N) {
+#define FPTS_CASE(NN)                                                                      \
+    case NN:                                                                               \
+        *lds = sizeof(double) * (newton::NodeLds<double, FC, R, NN>::SIZE + R * NN * 16);  \
+        return k_eval_mfma<R, NN, FC>;
+        FPTS_CASE(2)
+        FPTS_CASE(3)
+        FPTS_CASE(4)
+        FPTS_CASE(5)
+        FPTS_CASE(6)
+        FPTS_CASE(7)
+        FPTS_CASE(8)
+        FPTS_CASE(9)
+        FPTS_CASE(10)
+#undef FPTS_CASE
+    default: return nullptr;
+    }
+}
+
+template <int R>
+EvalFn pick_eval_mfma_fc(int N, int fc, size_t *lds)
+{
+    return fc == 3 ? pick_eval_mfma<R, 3>(N, lds)
+                   : fc == 2 ? pick_eval_mfma<R, 2>(N, lds) : pick_eval_mfma<R, 1>(N, lds);
+}
+
 template <bool LDS>
 EvalFn pick_eval_r(int R, int N)
 {
-    return R == 3 ? pick_eval<3, LDS>(N) : R == 2 ? pick_eval<2, LDS>(N) : pick_eval<1, LDS>(N);
+    return R == 1 ? pick_eval<1, LDS>(N) : nullptr;   // line meshes
 }
 
 }  // namespace
@@ -383,10 +571,6 @@ hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fie
                        const int *chunk_off, const int *task_elem, int64_t task_bound,
                        hipStream_t s, const double *rs)
 {
-    // stage in LDS unless elements hold many points (several tasks each)
-    const bool lds = n <= (int64_t)4 * kChunk * m->nel;
-    EvalFn fn = lds ? pick_eval_r<true>(m->R, field_n) : pick_eval_r<false>(m->R, field_n);
-    if (!fn) return hipErrorInvalidValue;
     EvalArgs a;
     a.r = r;
     a.n = (int)n;
@@ -399,12 +583,29 @@ hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fie
     a.chunk_off = chunk_off;
     a.task_elem = task_elem;
     a.rs = rs;
+    a.f0 = 0;
     if (field_n == m->N) a.basis = m->basis;
     else gll::fill(field_n, a.basis.z, a.basis.w);
-    int npf = field_n;   // LDS: one field of one element
-    for (int k = 1; k < m->R; ++k) npf *= field_n;
-    hipLaunchKernelGGL(fn, dim3(task_grid(task_bound, m->cus)), dim3(64),
-                       lds ? sizeof(double) * npf : 0, s, a);
+    const dim3 grid(task_grid(task_bound, m->cus));
+    if (m->R >= 2) {
+        // matrix cores, up to three fields per launch
+        for (int f0 = 0; f0 < n_fields; f0 += 3) {
+            size_t lds = 0;
+            const int fc = std::min(3, n_fields - f0);
+            EvalFn fn = m->R == 3 ? pick_eval_mfma_fc<3>(field_n, fc, &lds)
+                                  : pick_eval_mfma_fc<2>(field_n, fc, &lds);
+            if (!fn) return hipErrorInvalidValue;
+            a.f0 = f0;
+            hipLaunchKernelGGL(fn, grid, dim3(64), lds, s, a);
+        }
+        return hipGetLastError();
+    }
+    // line meshes: stage in LDS unless elements hold many points (several
+    // tasks each)
+    const bool lds = n <= (int64_t)4 * kChunk * m->nel;
+    EvalFn fn = lds ? pick_eval_r<true>(m->R, field_n) : pick_eval_r<false>(m->R, field_n);
+    if (!fn) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fn, grid, dim3(64), lds ? sizeof(double) * field_n : 0, s, a);
     return hipGetLastError();
 }
 
@@ -430,8 +631,9 @@ hipError_t launch_eval_sparse(const fpts_mesh *m, int64_t n, const double *r, in
                               hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    SparseFn fn = m->R == 3 ? pick_sparse<3>(field_n)
-                : m->R == 2 ? pick_sparse<2>(field_n) : pick_sparse<1>(field_n);
+    // line meshes only: the other meshes interpolate every point on the
+    // matrix cores (the same bits in both calls need the same arithmetic)
+    SparseFn fn = m->R == 1 ? pick_sparse<1>(field_n) : nullptr;
     if (!fn) return hipErrorInvalidValue;
     EvalArgs a{};
     a.r = r;
