@@ -76,7 +76,8 @@ def slot_use(stats):
     if stats["sweeps_h2"]:
         out["sweep2"] = round(stats["evals_h2"] / (16.0 * stats["sweeps_h2"]), 4)
     if stats["sweeps_fp32"]:
-        out["fp32"] = round(stats["evals_fp32"] / (16.0 * stats["sweeps_fp32"]), 4)
+        swept = stats["evals_fp32"] - stats.get("evals_fp32_node", 0)
+        out["fp32"] = round(swept / (16.0 * stats["sweeps_fp32"]), 4)
     return out
 
 

@@ -245,6 +245,10 @@ typedef struct fpts_find_stats {
                                  not fit the workspace's slots and were
                                  searched one point per wavefront (any
                                  pass) */
+    int64_t evals_fp32_node;  /* of evals_fp32: evaluations at a start that
+                                 is a GLL node, taken from the element's
+                                 nodes and differentiation matrix rows
+                                 without a sweep */
 } fpts_find_stats;
 
 int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws,

@@ -628,6 +628,7 @@ int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws, int pas
     out->sweeps = (int64_t)v[7];
     out->sweeps_h2 = (int64_t)v[8];
     out->sweeps_fp32 = (int64_t)v[9];
+    out->evals_fp32_node = (int64_t)v[10];
     return FPTS_OK;
 }
 

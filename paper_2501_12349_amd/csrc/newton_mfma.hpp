@@ -284,13 +284,51 @@ struct Lds {
     static constexpr int NODES = NodeLds<T, D, R, N>::SIZE;
     static constexpr int TAB = 3 * N * 16;
     // pair cache: kCache x (point coordinates D, start r R) of type T, then
-    // kCache item ids
+    // kCache item ids and kCache start-node indices
     static constexpr int CACHE = kCache * (D + R);
     static constexpr size_t bytes()
     {
-        return sizeof(T) * (NODES + 2 * TAB + CACHE) + sizeof(int) * kCache;
+        return sizeof(T) * (NODES + 2 * TAB + CACHE) + sizeof(int) * 2 * kCache;
+    }
+    __device__ static int *citem(void *lds)
+    {
+        return reinterpret_cast<int *>(reinterpret_cast<char *>(lds) + bytes() -
+                                       sizeof(int) * 2 * kCache);
     }
 };
+
+// Rows of the differentiation matrix at the GLL nodes: v[a][m] = phi_m'(z_a),
+// by the same prefix/suffix product rule as the sweeps' bases (compile time).
+template <typename T, int N>
+struct DiffRows {
+    T v[N][N];
+};
+template <typename T, int N>
+constexpr DiffRows<T, N> make_diff()
+{
+    constexpr gll::Table<N> G = gll::Nodes<N>::t;
+    DiffRows<T, N> d{};
+    for (int a = 0; a < N; ++a) {
+        const double x = G.z[a];
+        double pv[N] = {}, pd[N] = {};
+        pv[0] = 1.0;
+        for (int i = 1; i < N; ++i) {
+            const double t = x - G.z[i - 1];
+            pd[i] = pd[i - 1] * t + pv[i - 1];
+            pv[i] = pv[i - 1] * t;
+        }
+        double sv = 1.0, sd = 0.0;
+        for (int i = N - 1; i >= 0; --i) {
+            d.v[a][i] = T(G.w[i] * (pd[i] * sv + pv[i] * sd));
+            const double t = x - G.z[i];
+            sd = sd * t + sv;
+            sv = sv * t;
+        }
+    }
+    return d;
+}
+template <typename T, int N>
+__device__ const DiffRows<T, N> kDiff = make_diff<T, N>();
 
 // Stage 2+3 factored by j for hexes whose 16-row tiles hold whole (j, k)
 // blocks (N = 4, 8): a lane's rows 16 m + g + 4 qq have j = g + 4 (qq % NJ)
@@ -681,7 +719,8 @@ enum { kPrimary = 0, kResolve = 1, kFace = 2 };
 // counters by lane 0
 struct Counters {
     unsigned long long pairs = 0, passes = 0, evals = 0, evals_h2 = 0, passes32 = 0,
-                       evals32 = 0, evals_h2_exec = 0, sweeps = 0, sweeps_h2 = 0, sweeps32 = 0;
+                       evals32 = 0, evals_h2_exec = 0, sweeps = 0, sweeps_h2 = 0, sweeps32 = 0,
+                       evals32_node = 0;
 };
 
 // Run the iteration of Section 3.2.1 for every pair of element e (its queue
@@ -700,6 +739,16 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
     const bool leader = lane < 16;
     const NewtonIO &io = a.io;
     int state = S_FREE, item = 0, pass = 0, pos = 0;
+    // start node of the slot's pair (packed index, -1: the start is not a
+    // node or not used); fresh: the slot's start was evaluated at its node
+    // this trip.  Only the FP32 phase of mixed mode evaluates starts at their
+    // nodes: its pairs take about two evaluations, so the start is half of
+    // them; in FP64 (three to four) the extra refill-and-plan round per trip
+    // cost more than the sweeps it saved (measured on hex48).
+    constexpr bool kNodeStart = KIND != kFace && !FINAL;
+    int nodeix = -1;
+    bool fresh = false;
+    int *cnode = citem + kCache;
     T xs[D], r[R], q[R], dx[D], Hs[kSym<R>], alpha = T(1), pred = T(0), dmax = T(0),
         xnorm = T(0);
     Obj<T, D, R> cur;
@@ -758,6 +807,26 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                     cache[(D + k) * kCache + lane] =
                         T(__hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
                 }
+                // a start that is a GLL node (every nearest-node start): its
+                // packed index, so that the start is evaluated from the node
+                // block directly (kFace resumes from parked iterates)
+                int node = -1;
+                if constexpr (kNodeStart) {
+                    constexpr gll::Table<N> G = gll::Nodes<N>::t;
+                    int mul = 1;
+                    node = 0;
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        const T v = cache[(D + k) * kCache + lane];
+                        int ik = -1;
+#pragma unroll
+                        for (int m = 0; m < N; ++m)
+                            if (v == T(G.z[m])) ik = m;
+                        node = (node < 0 || ik < 0) ? -1 : node + mul * ik;
+                        mul *= N;
+                    }
+                }
+                cnode[lane] = node;
             }
             wave_lds_sync();
         }
@@ -767,6 +836,7 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
             if (idx < cend) {
                 const int c0 = idx - cstart;
                 item = citem[c0];
+                nodeix = cnode[c0];
                 pos = idx;
 #pragma unroll
                 for (int c = 0; c < D; ++c) xs[c] = cache[c * kCache + c0];
@@ -831,65 +901,71 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
         }
         state = S_FREE;
     };
-    const int guard = (q1 - q0 + 16) * (2 * max_iter + 4);
-    for (int trip = 0; trip < guard; ++trip) {
-        if constexpr (KIND == kPrimary) {
-            // pairs whose next pass needs second derivatives leave the wave:
-            // FP64 parks them (the face kernel resumes them, many to a wave),
-            // FP32 ends its phase there (the FP64 phase takes over)
-            const unsigned long long pm = __ballot(leader && state == S_WAIT);
-            if (pm) {
-                // (a launch without a park buffer -- the hinted search of
-                // particle tracking -- ends such pairs unconverged)
-                if (FINAL && io.park_meta) {
-                    int base = 0;
-                    if (lane == 0) base = atomicAdd(io.park_count, __popcll(pm));
-                    base = __shfl(base, 0);
-                    if (state == S_WAIT) {
-                        // park_cap is the pass's pair count: every pair is
-                        // parked at most once, so k < park_cap
-                        const int k = base + __popcll(pm & ((1ull << slot) - 1));
-                        if (leader && k < io.park_cap) {
-                            io.park_meta[k] = make_int4(item, pos, e, pass);
+    // Slots whose new pair starts at a GLL node: the map there is the node
+    // itself and dx/dr_d = sum_m phi_m'(z_{a_d}) x[.. m ..] (an N-term sum
+    // along direction d through the node), read from the node block: no
+    // sweep.  Quarter g < R sums direction g, quarter R reads the node; the
+    // slot's four lanes are then summed (three of each four terms are zero).
+    // Such slots go to S_STEP with the objective at the start, as an
+    // evaluation by sweep 1 would leave them.  Returns whether any did.
+    auto node_init = [&]() -> bool {
+        if constexpr (!kNodeStart) {
+            return false;
+        } else {
+            typedef NodeLds<T, D, R, N> NL;
+            const bool mine = state == S_INIT && nodeix >= 0;
+            if (!__ballot(leader && mine)) return false;
+            const int g = lane >> 4;
+            const int a0 = nodeix % N, a1 = (nodeix / N) % N, a2 = R == 3 ? nodeix / (N * N) : 0;
+            T v[D * (R + 1)];
 #pragma unroll
-                            for (int j = 0; j < R; ++j)
-                                io.park_r[(size_t)j * io.park_cap + k] = (double)r[j];
-                            io.park_r[(size_t)R * io.park_cap + k] = (double)alpha;
-                        }
-                        state = S_FREE;
-                    }
-                } else {
-                    if (state == S_WAIT) finish(false);
+            for (int k = 0; k < D * (R + 1); ++k) v[k] = T(0);
+            if (mine && g < R) {
+                const int ag = g == 0 ? a0 : g == 1 ? a1 : a2;
+                T dphi[N];
+#pragma unroll
+                for (int m = 0; m < N; ++m) dphi[m] = kDiff<T, N>.v[ag][m];
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    const int ii = g == 0 ? m : a0, jj = g == 1 ? m : a1, kk = g == 2 ? m : a2;
+                    const int base = NL::at(0, R == 3 ? jj + N * kk : jj, ii);
+#pragma unroll
+                    for (int c = 0; c < D; ++c)
+                        v[D + c * R + g] = fma(dphi[m], xl[base + c * NL::RP], v[D + c * R + g]);
+                }
+            } else if (mine && g == R) {
+                const int base = NL::at(0, R == 3 ? a1 + N * a2 : a1, a0);
+#pragma unroll
+                for (int c = 0; c < D; ++c) v[c] = xl[base + c * NL::RP];
+            }
+            slot_sum_all(v);
+            if (mine) {
+                T X[D], Gm[D][R];
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    X[c] = v[c];
+#pragma unroll
+                    for (int k = 0; k < R; ++k) Gm[c][k] = v[D + c * R + k];
+                }
+                objective<T, D, R>(xs, X, Gm, cur, dx);
+                hb_ok = false;
+                state = S_STEP;
+                fresh = true;
+                if (leader) {
+                    cn.evals32++;
+                    cn.evals32_node++;
                 }
             }
+            return true;
         }
-        refill();
-        const unsigned long long waitm = __ballot(leader && state == S_WAIT);
-        const unsigned long long stepm = __ballot(leader && (state == S_STEP || state == S_INIT));
-        if (!waitm && !stepm) break;
-        // a slot that waits for second derivatives gets them at once: holding
-        // it back to batch more waiting slots (4 or 8) costs more in idle
-        // slots than the batching saves (measured on hex48)
-        if (KIND != kPrimary && waitm != 0) {
-            T Sn[kSym<R>];
-            sweep2<T, D, R, N>(xl, tab, lane, r, dx, Sn);
-            if (lane == 0) {
-                if (FINAL) cn.sweeps_h2++;
-                else cn.sweeps32++;
-            }
-            if (state == S_WAIT) {
-#pragma unroll
-                for (int k = 0; k < kSym<R>; ++k) Hs[k] = Sn[k];
-                hb_ok = true;
-                state = S_STEP;
-                if (leader && FINAL) cn.evals_h2++;
-            }
-            if (leader && FINAL && state != S_FREE) cn.evals_h2_exec++;
-            continue;
-        }
-        // trial points of the stepping slots
+    };
+    // Trial point of each stepping slot (only the fresh ones when asked):
+    // the Newton step of Section 3.2.1 on the free coordinates, clipped to
+    // the trust region and the box; a step below the tolerance ends the
+    // iteration.  Returns, per lane, whether its slot's pair ended.
+    auto plan = [&](bool only_fresh) -> bool {
         bool ended = false;
-        if (state == S_STEP) {
+        if (state == S_STEP && (!only_fresh || fresh)) {
             const bool beta = (pass > 0) && on_face(r);
             if (beta && !hb_ok) {
                 // a face pass needs second derivatives at r: dx at r is
@@ -961,7 +1037,88 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                 }
             }
         }
-        if (__ballot(leader && ended)) refill();
+        return ended;
+    };
+    const int guard = (q1 - q0 + 16) * (2 * max_iter + 4);
+    for (int trip = 0; trip < guard; ++trip) {
+        if constexpr (KIND == kPrimary) {
+            // pairs whose next pass needs second derivatives leave the wave:
+            // FP64 parks them (the face kernel resumes them, many to a wave),
+            // FP32 ends its phase there (the FP64 phase takes over)
+            const unsigned long long pm = __ballot(leader && state == S_WAIT);
+            if (pm) {
+                // (a launch without a park buffer -- the hinted search of
+                // particle tracking -- ends such pairs unconverged)
+                if (FINAL && io.park_meta) {
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(io.park_count, __popcll(pm));
+                    base = __shfl(base, 0);
+                    if (state == S_WAIT) {
+                        // park_cap is the pass's pair count: every pair is
+                        // parked at most once, so k < park_cap
+                        const int k = base + __popcll(pm & ((1ull << slot) - 1));
+                        if (leader && k < io.park_cap) {
+                            io.park_meta[k] = make_int4(item, pos, e, pass);
+#pragma unroll
+                            for (int j = 0; j < R; ++j)
+                                io.park_r[(size_t)j * io.park_cap + k] = (double)r[j];
+                            io.park_r[(size_t)R * io.park_cap + k] = (double)alpha;
+                        }
+                        state = S_FREE;
+                    }
+                } else {
+                    if (state == S_WAIT) finish(false);
+                }
+            }
+        }
+        // free slots take new pairs (those starting at a node are evaluated
+        // there), then the trial points of the stepping slots; the slots
+        // whose pairs that ends take new pairs at once, and those starting
+        // at a node get their first trial point too (a second round), so no
+        // slot idles in this trip's sweep.  One copy of each step.
+        bool done = false, h2 = false;
+        for (int round = 0;; round = 1) {
+            refill();
+            fresh = false;
+            const bool any = node_init();
+            if (round == 0) {
+                const unsigned long long waitm = __ballot(leader && state == S_WAIT);
+                const unsigned long long stepm =
+                    __ballot(leader && (state == S_STEP || state == S_INIT));
+                if (!waitm && !stepm) {
+                    done = true;
+                    break;
+                }
+                // a slot that waits for second derivatives gets them at
+                // once: holding it back to batch more waiting slots (4 or
+                // 8) costs more in idle slots than the batching saves
+                // (measured on hex48)
+                if (KIND != kPrimary && waitm != 0) {
+                    T Sn[kSym<R>];
+                    sweep2<T, D, R, N>(xl, tab, lane, r, dx, Sn);
+                    if (lane == 0) {
+                        if (FINAL) cn.sweeps_h2++;
+                        else cn.sweeps32++;
+                    }
+                    if (state == S_WAIT) {
+#pragma unroll
+                        for (int k = 0; k < kSym<R>; ++k) Hs[k] = Sn[k];
+                        hb_ok = true;
+                        state = S_STEP;
+                        if (leader && FINAL) cn.evals_h2++;
+                    }
+                    if (leader && FINAL && state != S_FREE) cn.evals_h2_exec++;
+                    h2 = true;
+                    break;
+                }
+            } else if (!any) {
+                break;
+            }
+            const bool ended = plan(round == 1);
+            if (round == 1 || !__ballot(leader && ended)) break;
+        }
+        if (done) break;
+        if (h2) continue;
         if (state != S_INIT && state != S_STEP) {
 #pragma unroll
             for (int k = 0; k < R; ++k) q[k] = r[k];
@@ -1335,8 +1492,7 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &a)
     typedef Shape<D, R, N> S;
     constexpr bool FINAL = std::is_same<T, double>::value;
     extern __shared__ double lds_raw[];
-    int *citem = reinterpret_cast<int *>(reinterpret_cast<char *>(lds_raw) +
-                                         Lds<T, D, R, N>::bytes() - sizeof(int) * kCache);
+    int *citem = Lds<T, D, R, N>::citem(lds_raw);
     const int lane = threadIdx.x;
     const NewtonIO &io = a.io;
     T *xl = reinterpret_cast<T *>(lds_raw);
@@ -1376,11 +1532,11 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &a)
                                                      a.xc + (size_t)e * D, cn);
         }
     }
-    unsigned long long v[10] = {cn.pairs,  cn.passes,        cn.evals,  cn.evals_h2,
+    unsigned long long v[11] = {cn.pairs,  cn.passes,        cn.evals,  cn.evals_h2,
                                 cn.passes32, cn.evals32,     cn.evals_h2_exec,
-                                cn.sweeps, cn.sweeps_h2, cn.sweeps32};
+                                cn.sweeps, cn.sweeps_h2, cn.sweeps32, cn.evals32_node};
 #pragma unroll
-    for (int k = 0; k < 10; ++k) {
+    for (int k = 0; k < 11; ++k) {
         unsigned long long x = v[k];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
@@ -1444,8 +1600,7 @@ k_resolve_overflow(NewtonArgs a, HashView h)
     typedef Shape<D, R, N> S;
     constexpr gll::Table<N> GT = gll::Nodes<N>::t;
     extern __shared__ double lds_raw[];
-    int *citem = reinterpret_cast<int *>(reinterpret_cast<char *>(lds_raw) +
-                                         Lds<double, D, R, N>::bytes() - sizeof(int) * kCache);
+    int *citem = Lds<double, D, R, N>::citem(lds_raw);
     double *xl = lds_raw;
     double *tab = xl + Lds<double, D, R, N>::NODES;
     double *cache = tab + 2 * Lds<double, D, R, N>::TAB;
@@ -1564,11 +1719,11 @@ k_resolve_overflow(NewtonArgs a, HashView h)
             for (int k = 0; k < R; ++k) io.r[(size_t)k * io.ostride + p] = br[k];
         }
     }
-    unsigned long long v[10] = {cn.pairs,  cn.passes,        cn.evals,  cn.evals_h2,
+    unsigned long long v[11] = {cn.pairs,  cn.passes,        cn.evals,  cn.evals_h2,
                                 cn.passes32, cn.evals32,     cn.evals_h2_exec,
-                                cn.sweeps, cn.sweeps_h2, cn.sweeps32};
+                                cn.sweeps, cn.sweeps_h2, cn.sweeps32, cn.evals32_node};
 #pragma unroll
-    for (int k = 0; k < 10; ++k) {
+    for (int k = 0; k < 11; ++k) {
         unsigned long long xv = v[k];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) xv += __shfl_xor(xv, o);

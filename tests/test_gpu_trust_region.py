@@ -127,3 +127,27 @@ def test_pass_counts_single_curved_element(D, N):
     for precision in ("fp64", "mixed"):
         gpu, _ = _gpu_find(nodes, D, pts, precision)
         compare_find(om, pts, orc, gpu, 1.0)
+
+
+@pytest.mark.parametrize("D,N", [(2, 5), (3, 8)])
+def test_fp32_phase_evaluates_starts_at_their_nodes(D, N):
+    """Mixed mode: every FP32 pair starts at its nearest node, and that first
+    evaluation is taken from the element's nodes and differentiation matrix
+    rows instead of a sweep; the results still match the oracle."""
+    nodes = _curved_element(D, N, 91 + D * 10 + N)
+    rng = np.random.default_rng(17 + N)
+    pts = rng.uniform(-0.1, 1.1, (D, 3000))
+    om = oracle.Mesh(nodes, D, D, N)
+    orc = om.find(pts)
+    gpu, st = _gpu_find(nodes, D, pts, "mixed")
+    compare_find(om, pts, orc, gpu, 1.0)
+    fpts = _fpts()
+    gm = fpts.Mesh(nodes, N, dim=D, ref_dim=D)
+    tp = torch.from_numpy(np.ascontiguousarray(pts)).cuda()
+    gm.find(tp, precision="mixed")
+    primary = gm.find_stats(newton_pass=1)
+    print(D, N, primary)
+    assert primary["evals_fp32_node"] == primary["pairs"] > 0
+    # the swept evaluations fit the sweeps' slots
+    swept = primary["evals_fp32"] - primary["evals_fp32_node"]
+    assert 0 < swept <= 16 * primary["sweeps_fp32"]
