@@ -1302,7 +1302,7 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
     typedef typename std::conditional<MIXED, float, double>::type T;
     typedef typename V4<T>::type v4;
     constexpr gll::Table<N> GT = gll::Nodes<N>::t;
-    constexpr int NT = L::NPAD / 16;
+    constexpr int NT = L::NPAD / 16;   // node tiles (even)
     const T kBig = MIXED ? T(1e30f) : T(1e300);
     extern __shared__ double lds_raw[];
     T *Bt = reinterpret_cast<T *>(lds_raw);                  // [4][NPAD] (FP32)
@@ -1312,10 +1312,34 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
     const int lane = threadIdx.x, col = lane & 15, g = lane >> 4;
     const NewtonIO &io = a.io;
     const int total = io.chunk_off[a.nel];
-    for (int t = task_of_block(); t < total; t += gridDim.x) {
-        const int e = __builtin_amdgcn_readfirstlane(io.task_elem[t]);
-        const int beg = io.elem_off[e] + (t - io.chunk_off[e]) * kChunk;
-        const int cnt = min(io.elem_off[e + 1] - beg, kChunk);
+    const int G = gridDim.x;
+    // A task's inputs arrive through a chain of dependent loads (task ->
+    // element offsets -> pair ids -> point coordinates).  The chain of the
+    // wave's next task is started level by level while the current one is
+    // scored, so that its latency hides behind the MFMA work.
+    auto task_of = [&](int t, int &e, int &beg, int &cnt) __attribute__((always_inline)) {
+        e = __builtin_amdgcn_readfirstlane(io.task_elem[t]);
+        beg = io.elem_off[e] + (t - io.chunk_off[e]) * kChunk;
+        cnt = min(io.elem_off[e + 1] - beg, kChunk);
+    };
+    auto pair_of = [&](int beg, int cnt) __attribute__((always_inline)) { return lane < cnt ? io.list[beg + lane] : 0; };
+    auto coords_of = [&](int cnt, int item, double (&x)[D]) __attribute__((always_inline)) {
+        const int p = io.slot_pt ? io.slot_pt[item] : item;
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[c] = lane < cnt ? point_coord<D>(a, p, c) : 0.0;
+    };
+    int t = task_of_block();
+    if (t >= total) return;
+    int e, beg, cnt;
+    task_of(t, e, beg, cnt);
+    int item = pair_of(beg, cnt);
+    double px[D];
+    coords_of(cnt, item, px);
+    for (;;) {
+        const int tn = t + G;
+        const bool more = tn < total;
+        int en = 0, begn = 0, cntn = 0;
+        if (more) task_of(tn, en, begn, cntn);   // next task, level 1
         double xc[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) xc[c] = a.xc[(size_t)e * D + c];
@@ -1343,13 +1367,10 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
         // A rows of the pairs
         {
             const bool has = lane < cnt;
-            const int item = has ? io.list[beg + lane] : 0;
-            const int p = has ? (io.slot_pt ? io.slot_pt[item] : item) : 0;
             items[lane] = item;
             T pa[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-            for (int c = 0; c < D; ++c)
-                pa[c] = has ? T(point_coord<D>(a, p, c) - xc[c]) : T(0);
+            for (int c = 0; c < D; ++c) pa[c] = has ? T(px[c] - xc[c]) : T(0);
             pa[D] = T(1);
             T xx = T(0);
 #pragma unroll
@@ -1359,10 +1380,11 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
             Xx[lane] = xx;
         }
         wave_lds_sync();
+        const int itemn = more ? pair_of(begn, cntn) : 0;   // next task, level 2
         const int ntile = (cnt + 15) >> 4;   // pair tiles of this task (wave-uniform)
         // the start of the pair at task position pl: node bi's reference point
-        auto write_start = [&](int bi, int pl) {
-            const int item = items[pl];
+        auto write_start = [&](int bi, int pl) __attribute__((always_inline)) {
+            const int it = items[pl];
             const int ii[3] = {bi % N, (bi / N) % N, bi / (N * N)};
 #pragma unroll
             for (int k = 0; k < R; ++k) {
@@ -1373,9 +1395,10 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
                 if (io.start)
                     io.start[(size_t)k * io.start_stride + beg + pl] = v;
                 else
-                    io.r[(size_t)k * io.ostride + item] = v;
+                    io.r[(size_t)k * io.ostride + it] = v;
             }
         };
+        double pxn[D];
         if constexpr (!MIXED) {
             v4 seed[4];
             double av[4], best[4][4];
@@ -1390,6 +1413,7 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
             }
 #pragma unroll 2
             for (int nt = 0; nt < NT; ++nt) {
+                if (nt == NT / 2 && more) coords_of(cntn, itemn, pxn);   // next task, level 3
                 const double bv = a.near[((size_t)e * 4 + g) * L::NPAD + 16 * nt + col];
                 const int node = 16 * nt + col;
 #pragma unroll
@@ -1411,13 +1435,13 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
                     for (int qq = 0; qq < 4; ++qq)
                         best[pt][qq] = key_min(best[pt][qq], __shfl_xor(best[pt][qq], o));
                 // lane `col` < 4 writes the pair of output row g + 4 col
-                const double bk = col == 0 ? best[pt][0]
-                                  : col == 1 ? best[pt][1]
-                                  : col == 2 ? best[pt][2]
-                                             : best[pt][3];
+                // (the node index is in the low word; masks, not a select
+                // chain, which the compiler would turn into a stack array)
+                int lo = 0;
+#pragma unroll
+                for (int qq = 0; qq < 4; ++qq) lo |= __double2loint(best[pt][qq]) & -(col == qq);
                 const int pl = 16 * pt + g + 4 * col;
-                if (col < 4 && pl < cnt)
-                    write_start(__double2loint(bk) & ((1 << kNodeBits) - 1), pl);
+                if (col < 4 && pl < cnt) write_start(lo & ((1 << kNodeBits) - 1), pl);
             }
         } else {
             T av[4], best[4][4];
@@ -1435,6 +1459,7 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
             // per task and scores every pair tile
 #pragma unroll 2
             for (int nt = 0; nt < NT; ++nt) {
+                if (nt == NT / 2 && more) coords_of(cntn, itemn, pxn);   // next task, level 3
                 const T bv = Bt[g * L::NPAD + 16 * nt + col];
                 const int node = 16 * nt + col;
 #pragma unroll
@@ -1473,6 +1498,14 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
                 if (col < 4 && pl < cnt) write_start(bi, pl);
             }
         }
+        if (!more) break;
+        t = tn;
+        e = en;
+        beg = begn;
+        cnt = cntn;
+        item = itemn;
+#pragma unroll
+        for (int c = 0; c < D; ++c) px[c] = pxn[c];
     }
 }
 
@@ -1547,17 +1580,17 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &a)
 // The primary pass and the pass over the other candidates of unsettled
 // points run the same code under two kernel names, so that a kernel trace
 // reports them apart.
-// (at least two waves per SIMD: the register budget then stays within the
+// (at least three waves per SIMD: the register budget then stays within the
 // 256 VGPRs, and the compiler gives the MFMA results VGPRs, not AGPRs that
 // the selection would first have to copy out)
 template <int D, int R, int N, bool MIXED>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void
 k_nearest(NewtonArgs a)
 {
     nearest_body<D, R, N, MIXED>(a);
 }
 template <int D, int R, int N, bool MIXED>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void
 k_nearest_resolve(NewtonArgs a)
 {
     nearest_body<D, R, N, MIXED>(a);
