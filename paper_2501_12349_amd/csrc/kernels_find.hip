@@ -190,10 +190,24 @@ __global__ __launch_bounds__(256) void k_task_map(const int *chunk_off, int nuni
 }
 
 // Phase B: one wavefront per task of up to 64 points of one cell (task
-// grid).  The cell's candidate list and each candidate's box record are
-// wave-uniform and read with scalar loads; every lane tests its own point.
+// grid); every lane tests its own point against the cell's candidates.  The
+// candidates' box records are loaded into registers with vector loads, up to
+// kLocChunk at a time (lane j holds the first half of candidate j's record,
+// lane 32 + j the second), and each candidate's record is then broadcast to
+// scalar registers with lane reads.  A task's inputs come through dependent
+// loads (task -> cell -> point ids and candidate ids -> coordinates and
+// records): those of the wave's next task are issued while the current one
+// is tested, level by level, so that their latency hides behind the tests.
 // Per point: number of candidates, primary candidate (smallest OBB depth,
 // lowest id on ties), and the primary's bucket count.
+constexpr int kLocChunk = 32;
+
+__device__ __forceinline__ double read_lane(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
 template <int D, bool PACKED>
 __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, const double *pts,
                                                     const double *pts4,
@@ -204,34 +218,86 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
                                                     int *bin_prim, int32_t *code, int32_t *elem,
                                                     double *r, double *dist)
 {
+    constexpr int RS = 3 * D + D * D;   // doubles per box record
+    constexpr int HR = (RS + 1) / 2;    // record doubles per lane (half a record)
     const int lane = threadIdx.x;
     const int total = cell_choff[ncell];
-    for (int t = task_of_block(); t < total; t += gridDim.x) {
-        const int c = __builtin_amdgcn_readfirstlane(task_cell[t]);
-        const int beg = cell_poff[c] + (t - cell_choff[c]) * kChunk;
-        const int end = min(cell_poff[c + 1], beg + kChunk);
-        const bool has = beg + lane < end;
-        const int p = has ? pbin[beg + lane] : 0;
-        double x[D];
+    const int G = gridDim.x;
+    struct Task {
+        int c, beg, end, q0, q1;
+    };
+    // level 1: the task's cell, its points' range and its candidates' range
+    auto task_of = [&](int t) __attribute__((always_inline)) {
+        Task k;
+        k.c = __builtin_amdgcn_readfirstlane(task_cell[t]);
+        k.beg = cell_poff[k.c] + (t - cell_choff[k.c]) * kChunk;
+        k.end = min(cell_poff[k.c + 1], k.beg + kChunk);
+        k.q0 = __builtin_amdgcn_readfirstlane(h.cell_off[k.c]);
+        k.q1 = __builtin_amdgcn_readfirstlane(h.cell_off[k.c + 1]);
+        return k;
+    };
+    // level 2: this lane's point id and candidate id (candidate qb + lane % 32)
+    auto ids_of = [&](const Task &k, int qb, int &p, int &mine) __attribute__((always_inline)) {
+        p = k.beg + lane < k.end ? pbin[k.beg + lane] : 0;
+        const int j = lane & (kLocChunk - 1);
+        mine = j < min(kLocChunk, k.q1 - qb) ? h.cell_el[qb + j] : 0;
+    };
+    // level 3: the point's coordinates and this lane's half record
+    auto data_of = [&](const Task &k, int qb, int p, int mine, double (&x)[D],
+                       double (&rv)[HR]) __attribute__((always_inline)) {
+        const bool has = k.beg + lane < k.end;
 #pragma unroll
         for (int d = 0; d < D; ++d)
             x[d] = !has    ? 0.0
                    : PACKED ? pts4[(size_t)p * pt_stride(D) + d]
                             : pts[(size_t)d * n + p];
-        const int q0 = __builtin_amdgcn_readfirstlane(h.cell_off[c]);
-        const int q1 = __builtin_amdgcn_readfirstlane(h.cell_off[c + 1]);
+        const bool live = (lane & (kLocChunk - 1)) < min(kLocChunk, k.q1 - qb);
+        const int f0 = (lane >> 5) * HR;
+        const double *src = h.box + (size_t)mine * RS + f0;
+#pragma unroll
+        for (int u = 0; u < HR; ++u) rv[u] = (live && f0 + u < RS) ? src[u] : 0.0;
+    };
+    int t = task_of_block();
+    if (t >= total) return;
+    Task cur = task_of(t);
+    int p, mine;
+    double x[D], rv[HR];
+    ids_of(cur, cur.q0, p, mine);
+    data_of(cur, cur.q0, p, mine, x, rv);
+    for (;;) {
+        const int tn = t + G;
+        const bool more = tn < total;
+        Task nxt = cur;
+        if (more) nxt = task_of(tn);   // next task, level 1
+        int pn = 0, minen = 0;
+        double xn[D], rvn[HR];
+        bool l2 = !more, l3 = !more;
+        const bool has = cur.beg + lane < cur.end;
         int cnt = 0, prim = -1;
         double best = __builtin_huge_val();
-        // the cell's element ids, one per lane in one vector load; each
-        // candidate's id is then a lane read, and its box record load does
-        // not wait for a dependent id load
-        for (int qb = q0; qb < q1; qb += kWave) {
-            const int mine = qb + lane < q1 ? h.cell_el[qb + lane] : 0;
-            const int nb = min(kWave, q1 - qb);
-#pragma unroll 2
+        for (int qb = cur.q0; qb < cur.q1; qb += kLocChunk) {
+            const int nb = min(kLocChunk, cur.q1 - qb);
+            if (qb != cur.q0) {
+                // more candidates than one chunk: the next chunk, loaded now
+                int pq;
+                double xq[D];
+                ids_of(cur, qb, pq, mine);
+                data_of(cur, qb, pq, mine, xq, rv);
+            }
+            if (!l2) {
+                ids_of(nxt, nxt.q0, pn, minen);   // next task, level 2
+                l2 = true;
+            }
             for (int j = 0; j < nb; ++j) {
+                if (!l3 && j == nb / 2) {
+                    data_of(nxt, nxt.q0, pn, minen, xn, rvn);   // next task, level 3
+                    l3 = true;
+                }
+                // candidate j's record, broadcast to scalar registers
+                double rec[RS];
+#pragma unroll
+                for (int f = 0; f < RS; ++f) rec[f] = read_lane(rv[f % HR], j + 32 * (f / HR));
                 const int e = __builtin_amdgcn_readlane(mine, j);
-                cdouble *rec = (cdouble *)(h.box + (size_t)e * (3 * D + D * D));
                 double depth;
                 if (box_pass<D>(rec, x, depth)) {
                     ++cnt;
@@ -242,6 +308,8 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
                 }
             }
         }
+        if (!l2) ids_of(nxt, nxt.q0, pn, minen);   // a cell without candidates
+        if (!l3) data_of(nxt, nxt.q0, pn, minen, xn, rvn);
         if (has) {
             ncand[p] = cnt;
             primary[p] = prim;
@@ -250,9 +318,18 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
         const int k = wave_inc(elem_cnt, prim, has && prim >= 0);
         // primary and rank in bin order (coalesced), for the scatter by bins
         if (has) {
-            bin_prim[beg + lane] = prim;
-            rank[beg + lane] = k;
+            bin_prim[cur.beg + lane] = prim;
+            rank[cur.beg + lane] = k;
         }
+        if (!more) break;
+        t = tn;
+        cur = nxt;
+        p = pn;
+        mine = minen;
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = xn[d];
+#pragma unroll
+        for (int u = 0; u < HR; ++u) rv[u] = rvn[u];
     }
 }
 
