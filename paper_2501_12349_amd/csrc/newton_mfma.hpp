@@ -713,7 +713,9 @@ enum { S_FREE = 0, S_INIT = 1, S_STEP = 2, S_WAIT = 3 };
 // FP32 phase.  kResolve: the other candidates of unsettled points, second
 // derivatives in the wave.  kFace: the parked pairs, resumed from their
 // saved point, radius and pass count, second derivatives in the wave.
-enum { kPrimary = 0, kResolve = 1, kFace = 2 };
+// kPolish: the primary candidates in the FP64 phase of mixed mode (as
+// kPrimary, with the polish step and the double-batch refill).
+enum { kPrimary = 0, kResolve = 1, kFace = 2, kPolish = 3 };
 
 // per-slot counters are kept by the slot's leader lane, per-wave (sweep)
 // counters by lane 0
@@ -773,100 +775,110 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
     int head = q0, cstart = q0, cend = q0;
     // Refill free slots from the element's queue, through a cache of the
     // next kCache pairs (one coalesced load per kCache pairs).  Wave-uniform.
+    // When the staged batch runs out before every free slot has a pair, the
+    // next batch is staged at once where pairs take one or two evaluations
+    // (the FP32 phase and the polish phase of mixed mode: their slots turn
+    // over every trip); with three to four evaluations per pair (FP64) the
+    // slot waits for the next trip instead (the loop cost more there than
+    // the idle slots, measured on hex48).
+    constexpr int batches = (!FINAL || KIND == kPolish) ? 2 : 1;
     auto refill = [&]() {
-        const unsigned long long freem = __ballot(leader && state == S_FREE);
-        const int nfree = __popcll(freem);
-        if (!nfree || head >= q1) return;
-        if (head >= cend) {
-            wave_lds_sync();   // earlier reads of the cache come first
-            cstart = head;
-            cend = min(q1, head + kCache);
-            const int idx = cstart + lane;
-            if (lane < kCache && idx < cend) {
-                // kFace: the list holds park indices; the point, the saved
-                // iterate and the rest of the pair's state come from the
-                // park record
-                const int it = io.list[idx];
-                int p;
-                if constexpr (KIND == kFace) p = io.park_meta[it].x;
-                else p = io.slot_pt ? io.slot_pt[it] : it;
-                citem[lane] = it;
+#pragma unroll 1
+        for (int round = 0; round < batches; ++round) {
+            const unsigned long long freem = __ballot(leader && state == S_FREE);
+            const int nfree = __popcll(freem);
+            if (!nfree || head >= q1) return;
+            if (head >= cend) {
+                wave_lds_sync();   // earlier reads of the cache come first
+                cstart = head;
+                cend = min(q1, head + kCache);
+                const int idx = cstart + lane;
+                if (lane < kCache && idx < cend) {
+                    // kFace: the list holds park indices; the point, the saved
+                    // iterate and the rest of the pair's state come from the
+                    // park record
+                    const int it = io.list[idx];
+                    int p;
+                    if constexpr (KIND == kFace) p = io.park_meta[it].x;
+                    else p = io.slot_pt ? io.slot_pt[it] : it;
+                    citem[lane] = it;
 #pragma unroll
-                for (int c = 0; c < D; ++c)
-                    cache[c * kCache + lane] =
-                        T(point_coord<D>(a, p, c) - (shift ? shift[c] : 0.0));
-                // agent-scope loads: in mixed mode the FP32 phase of this
-                // wave stored these values moments ago
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const double *src;
-                    if constexpr (KIND == kFace) src = io.park_r + (size_t)k * io.park_cap + it;
-                    else
-                        src = io.start ? io.start + (size_t)k * io.start_stride + idx
-                                       : io.r + (size_t)k * io.ostride + it;
-                    cache[(D + k) * kCache + lane] =
-                        T(__hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                }
-                // a start that is a GLL node (every nearest-node start): its
-                // packed index, so that the start is evaluated from the node
-                // block directly (kFace resumes from parked iterates)
-                int node = -1;
-                if constexpr (kNodeStart) {
-                    constexpr gll::Table<N> G = gll::Nodes<N>::t;
-                    int mul = 1;
-                    node = 0;
+                    for (int c = 0; c < D; ++c)
+                        cache[c * kCache + lane] =
+                            T(point_coord<D>(a, p, c) - (shift ? shift[c] : 0.0));
+                    // agent-scope loads: in mixed mode the FP32 phase of this
+                    // wave stored these values moments ago
 #pragma unroll
                     for (int k = 0; k < R; ++k) {
-                        const T v = cache[(D + k) * kCache + lane];
-                        int ik = -1;
+                        const double *src;
+                        if constexpr (KIND == kFace) src = io.park_r + (size_t)k * io.park_cap + it;
+                        else
+                            src = io.start ? io.start + (size_t)k * io.start_stride + idx
+                                           : io.r + (size_t)k * io.ostride + it;
+                        cache[(D + k) * kCache + lane] =
+                            T(__hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    }
+                    // a start that is a GLL node (every nearest-node start): its
+                    // packed index, so that the start is evaluated from the node
+                    // block directly (kFace resumes from parked iterates)
+                    int node = -1;
+                    if constexpr (kNodeStart) {
+                        constexpr gll::Table<N> G = gll::Nodes<N>::t;
+                        int mul = 1;
+                        node = 0;
 #pragma unroll
-                        for (int m = 0; m < N; ++m)
-                            if (v == T(G.z[m])) ik = m;
-                        node = (node < 0 || ik < 0) ? -1 : node + mul * ik;
-                        mul *= N;
+                        for (int k = 0; k < R; ++k) {
+                            const T v = cache[(D + k) * kCache + lane];
+                            int ik = -1;
+#pragma unroll
+                            for (int m = 0; m < N; ++m)
+                                if (v == T(G.z[m])) ik = m;
+                            node = (node < 0 || ik < 0) ? -1 : node + mul * ik;
+                            mul *= N;
+                        }
+                    }
+                    cnode[lane] = node;
+                }
+                wave_lds_sync();
+            }
+            if (state == S_FREE) {
+                const int rank = __popcll(freem & ((1ull << slot) - 1));
+                const int idx = head + rank;
+                if (idx < cend) {
+                    const int c0 = idx - cstart;
+                    item = citem[c0];
+                    nodeix = cnode[c0];
+                    pos = idx;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) xs[c] = cache[c * kCache + c0];
+#pragma unroll
+                    for (int k = 0; k < R; ++k) {
+                        r[k] = cache[(D + k) * kCache + c0];
+                        q[k] = r[k];
+                    }
+                    T xn = T(0);
+#pragma unroll
+                    for (int c = 0; c < D; ++c) xn = fma(xs[c], xs[c], xn);
+                    xnorm = sqrt(xn);
+                    state = S_INIT;
+                    pass = 0;
+                    alpha = T(1);
+                    hb_ok = false;
+                    if constexpr (KIND == kFace) {
+                        // resumed where it was parked: same point, radius and
+                        // pass count (the pair was counted by the primary pass)
+                        const int4 mt = io.park_meta[item];
+                        pass = mt.w;
+                        alpha = T(io.park_r[(size_t)R * io.park_cap + item]);
+                        item = mt.x;
+                        pos = mt.y;
+                    } else if (leader && FINAL) {
+                        cn.pairs++;
                     }
                 }
-                cnode[lane] = node;
             }
-            wave_lds_sync();
+            head = min(head + nfree, cend);
         }
-        if (state == S_FREE) {
-            const int rank = __popcll(freem & ((1ull << slot) - 1));
-            const int idx = head + rank;
-            if (idx < cend) {
-                const int c0 = idx - cstart;
-                item = citem[c0];
-                nodeix = cnode[c0];
-                pos = idx;
-#pragma unroll
-                for (int c = 0; c < D; ++c) xs[c] = cache[c * kCache + c0];
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    r[k] = cache[(D + k) * kCache + c0];
-                    q[k] = r[k];
-                }
-                T xn = T(0);
-#pragma unroll
-                for (int c = 0; c < D; ++c) xn = fma(xs[c], xs[c], xn);
-                xnorm = sqrt(xn);
-                state = S_INIT;
-                pass = 0;
-                alpha = T(1);
-                hb_ok = false;
-                if constexpr (KIND == kFace) {
-                    // resumed where it was parked: same point, radius and
-                    // pass count (the pair was counted by the primary pass)
-                    const int4 mt = io.park_meta[item];
-                    pass = mt.w;
-                    alpha = T(io.park_r[(size_t)R * io.park_cap + item]);
-                    item = mt.x;
-                    pos = mt.y;
-                } else if (leader && FINAL) {
-                    cn.pairs++;
-                }
-            }
-        }
-        head = min(head + nfree, cend);
     };
     // A pair is done: results out, slot free.
     auto finish = [&](bool converged) {
@@ -1020,7 +1032,7 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                     cur.f = fmax(cur.f - pred, T(0));
                     finish(true);
                     ended = true;
-                } else if (KIND == kPrimary && FINAL && R == D && io.polish && pass == 0 &&
+                } else if (KIND == kPolish && R == D && io.polish && pass == 0 &&
                            dmax <= T(kPolishTol) && !on_face(r) && !on_face(q)) {
                     // mixed mode: the first FP64 step from the FP32 result
                     // is small and stays inside, so the start is within
@@ -1041,7 +1053,7 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
     };
     const int guard = (q1 - q0 + 16) * (2 * max_iter + 4);
     for (int trip = 0; trip < guard; ++trip) {
-        if constexpr (KIND == kPrimary) {
+        if constexpr (KIND == kPrimary || KIND == kPolish) {
             // pairs whose next pass needs second derivatives leave the wave:
             // FP64 parks them (the face kernel resumes them, many to a wave),
             // FP32 ends its phase there (the FP64 phase takes over)
@@ -1093,7 +1105,7 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                 // once: holding it back to batch more waiting slots (4 or
                 // 8) costs more in idle slots than the batching saves
                 // (measured on hex48)
-                if (KIND != kPrimary && waitm != 0) {
+                if (KIND != kPrimary && KIND != kPolish && waitm != 0) {
                     T Sn[kSym<R>];
                     sweep2<T, D, R, N>(xl, tab, lane, r, dx, Sn);
                     if (lane == 0) {
@@ -1602,6 +1614,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 }
 template <int D, int R, int N>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+k_newton_polish(NewtonArgs a)
+{
+    newton_body<double, D, R, N, false, kPolish>(a);
+}
+template <int D, int R, int N>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 k_newton_resolve(NewtonArgs a)
 {
     newton_body<double, D, R, N, true, kResolve>(a);
@@ -1784,7 +1802,10 @@ Kernels pick_kernels(int N, bool resolve)
         k.newton = resolve ? k_newton_resolve<D, R, NN> : k_newton<D, R, NN>;               \
         k.face = k_newton_face<D, R, NN>;                                                   \
         k.overflow = k_resolve_overflow<D, R, NN>;                                          \
-        if (MIXED && !resolve) k.newton32 = k_newton32<D, R, NN>;                           \
+        if (MIXED && !resolve) {                                                            \
+            k.newton32 = k_newton32<D, R, NN>;                                              \
+            k.newton = k_newton_polish<D, R, NN>;                                           \
+        }                                                                                   \
         k.lds_nearest = NearLds<TN, D, R, NN>::bytes();                                     \
         k.lds_newton32 = Lds<float, D, R, NN>::bytes();                                     \
         k.lds_newton = Lds<double, D, R, NN>::bytes();                                      \
