@@ -212,10 +212,11 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
 
 // Interpolation with the first contraction on the matrix cores (quad, hex
 // and surface meshes; FC fields a0.f0 .. a.f0 + FC - 1 per launch).  One
-// wavefront per task of up to 64 points of one element (task grid): the FC
-// fields of the element are staged in LDS (layout of the Newton kernels'
-// node block, one field per coordinate slot), and the points are taken 16 at
-// a time, one per slot of four lanes (slot = lane % 16, quarter g = lane /
+// wavefront per element (the first of its 64-point tasks in the task grid;
+// the element's other tasks are skipped): the FC fields of the element are
+// staged in LDS once (layout of the Newton kernels' node block, one field
+// per coordinate slot), and its points are taken 64 and then 16 at a time,
+// one per slot of four lanes (slot = lane % 16, quarter g = lane /
 // 16).  Quarter g builds the bases of direction g of its slot's point; then
 // C_f[row][s] = sum_i u_f[i][row] phi_i(r_s) by v_mfma_f64_16x16x4 (A = the
 // element's values, row = (j, k) or j; B = the slots' phi_i), each lane
@@ -223,10 +224,11 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
 // (hexes with N = 4, 8: summed over k first, then weighted per j), and the
 // four lanes of a slot are summed.  A point's value depends on its own
 // coordinates and element only, not on the group it lands in.
-// (at least two waves per SIMD: the register budget then stays within the
-// 256 VGPRs and the MFMA results land in VGPRs, not in AGPRs to copy out)
+// (four waves per SIMD: the register budget of 128 VGPRs holds the kernel
+// with one spilled lane id, and the MFMA results land in VGPRs, not in
+// AGPRs to copy out)
 template <int R, int N, int FC>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void
 k_eval_mfma(EvalArgs a)
 {
     typedef newton::Shape<3, R, N> S;
@@ -243,16 +245,9 @@ k_eval_mfma(EvalArgs a)
     const int total = a.chunk_off[a.nel];
     for (int t = task_of_block(); t < total; t += gridDim.x) {
         const int e = __builtin_amdgcn_readfirstlane(a.task_elem[t]);
-        const int beg = a.elem_off[e] + (t - a.chunk_off[e]) * kChunk;
-        const int end = min(a.elem_off[e + 1], beg + kChunk);
-        const int idx = beg + lane;
-        bool has = idx < end;
-        const int p = has ? a.sorted[idx] : 0;
-        double rr[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-        for (int k = 0; k < R; ++k)
-            if (has) rr[k] = a.rs ? a.rs[(size_t)k * a.n + idx] : a.r[(size_t)k * a.n + p];
-        if (a.rs) has = has && !__builtin_isnan(rr[0]);
+        // the element's first task takes all its points, so that its fields
+        // are staged once (the other tasks of the element have nothing to do)
+        if (t != a.chunk_off[e]) continue;
         // stage the element's FC fields (every load issued before the stores)
         {
             double v[FC][PER];
@@ -275,6 +270,17 @@ k_eval_mfma(EvalArgs a)
                 }
             __syncthreads();
         }
+        const int eend = a.elem_off[e + 1];
+        for (int beg = a.elem_off[e]; beg < eend; beg += kChunk) {
+        const int end = min(eend, beg + kChunk);
+        const int idx = beg + lane;
+        bool has = idx < end;
+        const int p = has ? a.sorted[idx] : 0;
+        double rr[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if (has) rr[k] = a.rs ? a.rs[(size_t)k * a.n + idx] : a.r[(size_t)k * a.n + p];
+        if (a.rs) has = has && !__builtin_isnan(rr[0]);
         const int ngrp = (end - beg + 15) >> 4;
         for (int grp = 0; grp < ngrp; ++grp) {
             const int pl = 16 * grp + slot;   // task position of this slot's point
@@ -358,6 +364,7 @@ k_eval_mfma(EvalArgs a)
 #pragma unroll
             for (int f = 0; f < FC; ++f)
                 if (hp && g == f) a.out[(size_t)(a.f0 + f) * a.n + pp] = X[f];
+        }
         }
     }
 }
