@@ -56,6 +56,34 @@ template <typename T> __device__ inline T eps_of();
 template <> __device__ inline double eps_of<double>() { return DBL_EPSILON; }
 template <> __device__ inline float eps_of<float>() { return FLT_EPSILON; }
 
+// 1/x for a positive normal x (an LDL^T pivot): the hardware reciprocal,
+// refined by two Newton steps in FP64 (its first guess is good to about 23
+// bits) and used as it is in FP32 (1 ulp).  A step direction needs no
+// correctly rounded quotient, and this is a third of the division sequence.
+template <typename T> __device__ T rcp_pos(T x);
+template <> __device__ __forceinline__ double rcp_pos<double>(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+template <> __device__ __forceinline__ float rcp_pos<float>(float x)
+{
+    return __builtin_amdgcn_rcpf(x);
+}
+
+// Square root to about 23 bits (one hardware instruction): only for the
+// rounding-noise threshold of the trust-region test, a scale, not a result.
+template <typename T> __device__ T sqrt_scale(T x);
+template <> __device__ __forceinline__ double sqrt_scale<double>(double x)
+{
+    return __builtin_amdgcn_sqrt(x);
+}
+template <> __device__ __forceinline__ float sqrt_scale<float>(float x)
+{
+    return __builtin_amdgcn_sqrtf(x);
+}
+
 template <typename T> __device__ __forceinline__ T xor_shfl(T v, int m);
 template <> __device__ __forceinline__ double xor_shfl<double>(double v, int m)
 {
@@ -244,6 +272,9 @@ template <typename T, int N, bool H2>
 __device__ __forceinline__ void basis_table(T x, T *tab, int slot, bool write)
 {
     constexpr gll::Table<N> G = gll::Nodes<N>::t;
+    // The jets of the first one or two factors are written out (1, 0, 0),
+    // (t, 1, 0), (., ., 2): products with the constants 0 and 1 would
+    // otherwise be issued, since they cannot be folded for a general x.
     T pv[N], pd[N], pdd[N];
     pv[0] = T(1);
     pd[0] = T(0);
@@ -251,24 +282,30 @@ __device__ __forceinline__ void basis_table(T x, T *tab, int slot, bool write)
 #pragma unroll
     for (int i = 1; i < N; ++i) {
         const T t = x - T(G.z[i - 1]);
-        if (H2) pdd[i] = pdd[i - 1] * t + T(2) * pd[i - 1];
-        pd[i] = pd[i - 1] * t + pv[i - 1];
-        pv[i] = pv[i - 1] * t;
+        if (H2) pdd[i] = i == 1 ? T(0) : i == 2 ? T(2) * pd[1] : pdd[i - 1] * t + T(2) * pd[i - 1];
+        pd[i] = i == 1 ? T(1) : pd[i - 1] * t + pv[i - 1];
+        pv[i] = i == 1 ? t : pv[i - 1] * t;
     }
     T sv = T(1), sd = T(0), sdd = T(0);
 #pragma unroll
     for (int i = N - 1; i >= 0; --i) {
+        const int ns = N - 1 - i;   // factors in the suffix
         if (write) {
-            tab[(0 * N + i) * 16 + slot] = T(G.w[i]) * (pv[i] * sv);
-            tab[(1 * N + i) * 16 + slot] = T(G.w[i]) * (pd[i] * sv + pv[i] * sd);
-            if (H2)
-                tab[(2 * N + i) * 16 + slot] =
-                    T(G.w[i]) * (pdd[i] * sv + T(2) * pd[i] * sd + pv[i] * sdd);
+            const T v = ns == 0 ? pv[i] : pv[i] * sv;
+            const T d = ns == 0 ? pd[i] : ns == 1 ? pd[i] * sv + pv[i] : pd[i] * sv + pv[i] * sd;
+            tab[(0 * N + i) * 16 + slot] = T(G.w[i]) * v;
+            tab[(1 * N + i) * 16 + slot] = T(G.w[i]) * d;
+            if (H2) {
+                const T dd = ns == 0   ? pdd[i]
+                             : ns == 1 ? pdd[i] * sv + T(2) * pd[i]
+                                       : pdd[i] * sv + T(2) * pd[i] * sd + pv[i] * sdd;
+                tab[(2 * N + i) * 16 + slot] = T(G.w[i]) * dd;
+            }
         }
         const T t = x - T(G.z[i]);
-        if (H2) sdd = sdd * t + T(2) * sd;
-        sd = sd * t + sv;
-        sv = sv * t;
+        if (H2) sdd = ns == 0 ? T(0) : ns == 1 ? T(2) * sd : sdd * t + T(2) * sd;
+        sd = ns == 0 ? T(1) : sd * t + sv;
+        sv = ns == 0 ? t : sv * t;
     }
 }
 
@@ -388,8 +425,9 @@ __device__ __forceinline__ void sweep1(const T *xl, T *tab, int lane, const T (&
         }
     }
     constexpr bool kFullA = (N % 4 == 0) && (S::ROWS % 16 == 0);
-#pragma unroll 1
-    for (int m = 0; m < S::MT; ++m) {
+    // one row tile; the first is issued on its own, where the partial sums
+    // are still the constant 0 (no registers to clear for the loop)
+    auto tile = [&](int m) __attribute__((always_inline)) {
         v4 acc0[D], acc1[D];
 #pragma unroll
         for (int c = 0; c < D; ++c) {
@@ -447,7 +485,10 @@ __device__ __forceinline__ void sweep1(const T *xl, T *tab, int lane, const T (&
                 }
             }
         }
-    }
+    };
+    tile(0);
+#pragma unroll 1
+    for (int m = 1; m < S::MT; ++m) tile(m);
     if constexpr (F::ON) {
 #pragma unroll
         for (int js = 0; js < F::NJ; ++js) {
@@ -517,8 +558,7 @@ __device__ __forceinline__ void sweep2(const T *xl, T *tab, int lane, const T (&
     for (int js = 0; js < F::NJ; ++js)
 #pragma unroll
         for (int a = 0; a < 6; ++a) Z[js][a] = T(0);
-#pragma unroll 1
-    for (int m = 0; m < S::MT; ++m) {
+    auto tile = [&](int m) __attribute__((always_inline)) {
         // the slot's residual enters the B operand, so one accumulator per
         // basis kind collects sum_c dx_c C_c[row][slot] over the coordinates
         v4 acc0 = v4{0, 0, 0, 0}, acc1 = v4{0, 0, 0, 0}, acc2 = v4{0, 0, 0, 0};
@@ -571,7 +611,10 @@ __device__ __forceinline__ void sweep2(const T *xl, T *tab, int lane, const T (&
                 Sa[2] = fma(C1, sd, Sa[2]);         // rs
             }
         }
-    }
+    };
+    tile(0);
+#pragma unroll 1
+    for (int m = 1; m < S::MT; ++m) tile(m);
     if constexpr (F::ON) {
 #pragma unroll
         for (int js = 0; js < F::NJ; ++js) {
@@ -646,7 +689,7 @@ __device__ __forceinline__ bool solve_free(const T (&H)[kSym<R>], const T (&g)[R
         for (int k = 0; k < a; ++k) s -= L[a][k] * L[a][k] * d[k];
         d[a] = s;
         ok = ok && (s > T(0));
-        inv[a] = T(1) / s;   // one division per pivot
+        inv[a] = rcp_pos(s);   // one reciprocal per pivot (unused when s <= 0)
 #pragma unroll
         for (int c = a + 1; c < R; ++c) {
             T t = A[c][a];
@@ -859,7 +902,7 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                     T xn = T(0);
 #pragma unroll
                     for (int c = 0; c < D; ++c) xn = fma(xs[c], xs[c], xn);
-                    xnorm = sqrt(xn);
+                    xnorm = sqrt_scale(xn);
                     state = S_INIT;
                     pass = 0;
                     alpha = T(1);
@@ -987,11 +1030,12 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                 T H[kSym<R>];
 #pragma unroll
                 for (int k = 0; k < kSym<R>; ++k) H[k] = beta ? cur.Hgn[k] - Hs[k] : cur.Hgn[k];
+                // held: at a bound of the box with the gradient pointing
+                // out of it (r = +-1 exactly, so r g has the sign test)
                 bool held[R];
 #pragma unroll
                 for (int k = 0; k < R; ++k)
-                    held[k] = (r[k] == T(1) && cur.g[k] > T(0)) ||
-                              (r[k] == T(-1) && cur.g[k] < T(0));
+                    held[k] = (fabs(r[k]) == T(1)) & (r[k] * cur.g[k] > T(0));
                 T x[R];
                 bool ok = solve_free<T, R>(H, cur.g, held, x);
                 if (!ok && beta) {
@@ -1014,8 +1058,10 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
 #pragma unroll
                 for (int k = 0; k < R; ++k) {
                     gd = fma(cur.g[k], dr[k], gd);
+                    T w = T(0);   // (H dr)_k
 #pragma unroll
-                    for (int b = 0; b < R; ++b) dHd = fma(dr[k] * H[sym<R>(k, b)], dr[b], dHd);
+                    for (int b = 0; b < R; ++b) w = fma(H[sym<R>(k, b)], dr[b], w);
+                    dHd = fma(dr[k], w, dHd);
                 }
                 pred = T(2) * gd - dHd;
                 if (dmax < tol) {
@@ -1170,7 +1216,7 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
             // trust-region test (the step is at least the tolerance here)
             bool accept;
             const T decr = cur.f - nw.f;
-            const T sf = sqrt(cur.f);
+            const T sf = sqrt_scale(cur.f);
             const T noise = T(64) * eps_of<T>() * sf * (xnorm + sf);
             if (pred > T(0) && pred <= noise) {
                 accept = true;
