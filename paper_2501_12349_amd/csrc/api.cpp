@@ -148,7 +148,12 @@ FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
     // exact bound (their kernel has no overflow path).
     const int64_t cmax = n * (int64_t)std::max(m->max_cell - 1, 1);
     w.cap2 = std::max<int64_t>(1, m->R == 1 ? cmax : std::min<int64_t>(cmax, n));
-    w.scan_blocks = scan_tmp_blocks(std::max<int64_t>(std::max<int64_t>(n, m->nel), ncell));
+    w.bin_shift = bin_shift(ncell);
+    w.bin_hist_n = w.bin_shift < 0 ? 0
+                                    : ((ncell + (1ll << w.bin_shift) - 1) >> w.bin_shift) *
+                                          bin_tiles(n);
+    w.scan_blocks = scan_tmp_blocks(
+        std::max<int64_t>(std::max<int64_t>(std::max<int64_t>(n, m->nel), ncell), w.bin_hist_n));
     const size_t I = sizeof(int);
     w.cell_cnt = c.take(I * ncell);
     w.cell_poff = c.take(I * (ncell + 1));
@@ -199,6 +204,8 @@ FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
     w.ov_grid = (int64_t)m->cus * 4;
     w.ov_int = c.take(I * 3 * w.ov_grid);
     w.ov_dbl = c.take(sizeof(double) * (m->R + 1) * w.ov_grid);
+    w.bin_hist = c.take(I * (w.bin_hist_n + 1));
+    w.bin_pairs = c.take(w.bin_shift < 0 ? 1 : sizeof(int2) * n);
     w.counters = c.take(I * kCounters);
     w.stats = c.take(sizeof(unsigned long long) * 3 * kStats);
     w.total = c.at;
@@ -297,13 +304,28 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         chk(launch_fill_i32(park_cnt, nel, 0, s));
         chk(launch_fill_i32(counters, kCounters, 0, s));
         chk(launch_fill_i32(reinterpret_cast<int *>(stats), 6 * kStats, 0, s));
-        chk(launch_cell_bin(m, 0, n, d_pts, pts4, keep, cellpt, cell_cnt, nullptr, rank, nullptr,
-                            ncand, primary, d_code, d_elem, d_r, d_dist, s));
-        chk(launch_exclusive_scan(cell_cnt, cell_poff, ncell, 1, tmp, tb, s));
-        chk(launch_exclusive_scan(cell_cnt, cell_choff, ncell, kChunk, tmp, tb, s));
-        chk(launch_task_map(cell_choff, ncell, task_cell, s));
-        chk(launch_cell_bin(m, 1, n, d_pts, nullptr, keep, cellpt, nullptr, cell_poff, rank, pbin,
-                            nullptr, nullptr, d_code, d_elem, d_r, d_dist, s));
+        if (w.bin_shift >= 0) {
+            int *bh = at<int>(d_ws, w.bin_hist);
+            int2 *pairs = at<int2>(d_ws, w.bin_pairs);
+            const int *npairs = bh + w.bin_hist_n;   // the scan's total
+            chk(launch_bin_tiles(m, n, d_pts, pts4, keep, cellpt, ncand, primary, d_code, d_elem,
+                                 d_r, d_dist, w.bin_shift, bh, s));
+            chk(launch_exclusive_scan(bh, bh, w.bin_hist_n, 1, tmp, tb, s));
+            chk(launch_bin_coarse(m, n, cellpt, w.bin_shift, bh, pairs, s));
+            chk(launch_bin_rank(n, npairs, w.bin_shift, pairs, cell_cnt, rank, s));
+            chk(launch_exclusive_scan(cell_cnt, cell_poff, ncell, 1, tmp, tb, s));
+            chk(launch_exclusive_scan(cell_cnt, cell_choff, ncell, kChunk, tmp, tb, s));
+            chk(launch_task_map(cell_choff, ncell, task_cell, s));
+            chk(launch_bin_scatter(n, npairs, pairs, rank, cell_poff, pbin, m->cus, s));
+        } else {
+            chk(launch_cell_bin(m, 0, n, d_pts, pts4, keep, cellpt, cell_cnt, nullptr, rank,
+                                nullptr, ncand, primary, d_code, d_elem, d_r, d_dist, s));
+            chk(launch_exclusive_scan(cell_cnt, cell_poff, ncell, 1, tmp, tb, s));
+            chk(launch_exclusive_scan(cell_cnt, cell_choff, ncell, kChunk, tmp, tb, s));
+            chk(launch_task_map(cell_choff, ncell, task_cell, s));
+            chk(launch_cell_bin(m, 1, n, d_pts, nullptr, keep, cellpt, nullptr, cell_poff, rank,
+                                pbin, nullptr, nullptr, d_code, d_elem, d_r, d_dist, s));
+        }
         chk(launch_locate_cells(m, n, d_pts, pts4, pbin, cell_poff, cell_choff, ncell, task_cell,
                                 w.tb_cell, ncand, primary, elem_cnt, rank, bin_prim, d_code,
                                 d_elem, d_r, d_dist, s));

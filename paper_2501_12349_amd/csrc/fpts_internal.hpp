@@ -165,12 +165,14 @@ struct FindWs {
         elem_off2, chunk_off2, slot_pt, slot_elem, sorted2, res_r, res_dist, res_code,
         task_cell, task_elem, task_elem2, scan_tmp, counters, stats, pts4, start, park_meta,
         park_r, park_cnt, park_off, park_choff, park_rank, park_sorted, park_task, olist, ov_int,
-        ov_dbl, total;
+        ov_dbl, bin_hist, bin_pairs, total;
     int64_t cap2;           // capacity for second-pass (point, candidate) pairs
     int64_t scan_blocks;
     int64_t ncell;
     int64_t tb_cell, tb_elem, tb_elem2, tb_park;   // task bounds
     int64_t ov_grid;        // blocks of the overflow search (its scratch)
+    int bin_shift;          // phase A without per-point atomics: bucket shift, or -1
+    int64_t bin_hist_n;     // entries of its bucket histograms (nb * ntile)
 };
 
 struct EvalWs {
@@ -342,6 +344,35 @@ hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double
                            double *pts4, const int *keep, int *cellpt, int *cell_cnt,
                            const int *cell_poff, int *rank, int *pbin, int *ncand, int *primary,
                            int32_t *code, int32_t *elem, double *r, double *dist, hipStream_t s);
+// Phase A without per-point atomics (meshes with at most kBinMaxCells
+// cells; bin_shift returns -1 beyond): cells grouped into buckets of
+// 2^shift cells, at most kBinMaxBuckets of them.  tiles: as pass 0 of
+// launch_cell_bin, and each tile's bucket histogram into bh[bucket * ntile
+// + tile] (ntile = bin_tiles(n); bh is then scanned in place, its total at
+// bh[nb * ntile]); coarse: (cell, id) pairs sorted by bucket from the
+// scanned bh; rank: each pair's rank in its cell (cell_cnt zeroed before,
+// complete after), *total pairs; scatter: pbin[cell_poff[c] + rank[i]] =
+// id of pair i.
+constexpr int64_t kBinMaxCells = (int64_t)1 << 24;
+constexpr int kBinMaxBuckets = 4096;
+int bin_shift(int64_t ncell);
+int64_t bin_tiles(int64_t n);
+inline int64_t bin_cells(const fpts_mesh *m)
+{
+    int64_t c = 1;
+    for (int d = 0; d < m->D; ++d) c *= m->NL;
+    return c;
+}
+hipError_t launch_bin_tiles(const fpts_mesh *m, int64_t n, const double *pts, double *pts4,
+                            const int *keep, int *cellpt, int *ncand, int *primary,
+                            int32_t *code, int32_t *elem, double *r, double *dist, int shift,
+                            int *bh, hipStream_t s);
+hipError_t launch_bin_coarse(const fpts_mesh *m, int64_t n, const int *cellpt, int shift,
+                             const int *boff, int2 *pairs, hipStream_t s);
+hipError_t launch_bin_rank(int64_t n, const int *total, int shift, const int2 *pairs,
+                           int *cell_cnt, int *rank, hipStream_t s);
+hipError_t launch_bin_scatter(int64_t n, const int *total, const int2 *pairs, const int *rank,
+                              const int *cell_poff, int *pbin, int cus, hipStream_t s);
 // search hints: pass 0 makes the previous element of each previously
 // INTERIOR point its primary (counted per element); pass 1 sets keep[p] for
 // points the hinted search settled

@@ -132,9 +132,42 @@ __device__ inline void write_not_found(int p, int n, int R, int32_t *code, int32
     for (int a = 0; a < R; ++a) r[(size_t)a * n + p] = 0.0;
 }
 
-// Phase A.  pass 0: cell of each point, count per cell, NOT_FOUND for points
-// outside the map, and (pts4 not null) the coordinates packed per point;
-// pass 1: scatter point ids into their cell's bucket.
+// Phase A for one point: its cell (-1 for a kept point, whose result is
+// already final, and for a point outside the map), the packed copy of its
+// coordinates (pts4 not null), defined candidate data, and NOT_FOUND for a
+// point outside the map.
+template <int D>
+__device__ inline int bin_point(const HashView &h, int p, int n, int R, const double *pts,
+                                double *pts4, const int *keep, int *cellpt, int *ncand,
+                                int *primary, int32_t *code, int32_t *elem, double *r,
+                                double *dist)
+{
+    int c = -1;
+    const bool kept = keep && keep[p];
+    if (!kept) {
+        double x[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = pts[(size_t)d * n + p];
+        c = cell_of<D>(h, x);
+        if (pts4) {
+            // the packed copy (one cache line per point for the kernels that
+            // visit points in bucket order)
+            typedef double v2 __attribute__((ext_vector_type(2)));
+            v2 *o = reinterpret_cast<v2 *>(pts4 + (size_t)p * pt_stride(D));
+            o[0] = v2{x[0], x[1]};
+            if (D == 3) o[1] = v2{x[D - 1], 0.0};
+        }
+    }
+    cellpt[p] = c;
+    ncand[p] = 0;
+    primary[p] = -1;
+    if (c < 0 && !kept) write_not_found(p, n, R, code, elem, r, dist);
+    return c;
+}
+
+// Phase A with one atomic per point (meshes with more than kBinMaxCells
+// cells).  pass 0: bin_point and the count per cell; pass 1: scatter point
+// ids into their cell's bucket.
 template <int D>
 __global__ __launch_bounds__(256) void k_cell_bin(HashView h, int pass, int n, int R,
                                                  const double *pts, double *pts4, const int *keep,
@@ -148,35 +181,135 @@ __global__ __launch_bounds__(256) void k_cell_bin(HashView h, int pass, int n, i
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = p < n;
     if (pass == 0) {
-        int c = -1;
-        if (in) {
-            // a kept point (its result is already final) is not searched
-            const bool kept = keep && keep[p];
-            if (!kept) {
-                double x[D];
-#pragma unroll
-                for (int d = 0; d < D; ++d) x[d] = pts[(size_t)d * n + p];
-                c = cell_of<D>(h, x);
-                if (pts4) {
-                    // the packed copy (one cache line per point for the
-                    // kernels that visit points in bucket order)
-                    typedef double v2 __attribute__((ext_vector_type(2)));
-                    v2 *o = reinterpret_cast<v2 *>(pts4 + (size_t)p * pt_stride(D));
-                    o[0] = v2{x[0], x[1]};
-                    if (D == 3) o[1] = v2{x[D - 1], 0.0};
-                }
-            }
-            cellpt[p] = c;
-            // every point gets defined candidate data, also those no cell holds
-            ncand[p] = 0;
-            primary[p] = -1;
-            if (c < 0 && !kept) write_not_found(p, n, R, code, elem, r, dist);
-        }
+        const int c = in ? bin_point<D>(h, p, n, R, pts, pts4, keep, cellpt, ncand, primary, code,
+                                        elem, r, dist)
+                         : -1;
         const int k = wave_inc(cell_cnt, c, c >= 0);
         if (c >= 0) rank[p] = k;
     } else {
         const int c = in ? cellpt[p] : -1;
         if (c >= 0) pbin[cell_poff[c] + rank[p]] = p;
+    }
+}
+
+// Phase A without per-point atomics.  Points arrive in any order (uniformly
+// random in the benchmarks), so a count per cell by atomics costs one
+// device atomic per point (about 26 G/s on this GPU) and the scatter into
+// cell buckets one write at a random place per point.  Instead the cells
+// are grouped into coarse buckets of 2^shift consecutive cells (at most
+// kBinMaxBuckets buckets):
+//  tiles:   per tile of kBinTile points, bin_point and the tile's histogram
+//           over the buckets (LDS atomics), stored bucket-major in bh; an
+//           exclusive scan of bh gives each (bucket, tile) its range;
+//  coarse:  each tile writes its points as (cell, id) pairs into those
+//           ranges: pairs sorted by bucket, one short run per (tile, bucket);
+//  rank:    windows of kBinTile consecutive pairs (cells of at most two
+//           buckets, unless the buckets are sparse) count their cells in LDS
+//           and take one atomic per cell on cell_cnt for a block of ranks;
+//  scatter: after the scan of cell_cnt, pbin[cell_poff[c] + rank] = id in
+//           pair order, so a window's writes fall in the cells of one or two
+//           buckets.
+constexpr int kBinThreads = 256;
+constexpr int kBinItems = 16;
+constexpr int kBinTile = kBinThreads * kBinItems;
+
+template <int D>
+__global__ __launch_bounds__(kBinThreads) void k_bin_tiles(HashView h, int n, int R,
+                                                          const double *pts, double *pts4,
+                                                          const int *keep, int *cellpt,
+                                                          int *ncand, int *primary,
+                                                          int32_t *code, int32_t *elem, double *r,
+                                                          double *dist, int shift, int nb,
+                                                          int ntile, int *bh)
+{
+    extern __shared__ int hist[];   // [nb]
+    for (int i = threadIdx.x; i < nb; i += kBinThreads) hist[i] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kBinTile;
+    for (int k = 0; k < kBinItems; ++k) {
+        const int64_t q = base + (int64_t)k * kBinThreads + threadIdx.x;
+        if (q < n) {
+            const int c = bin_point<D>(h, (int)q, n, R, pts, pts4, keep, cellpt, ncand, primary,
+                                       code, elem, r, dist);
+            if (c >= 0) atomicAdd(&hist[c >> shift], 1);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += kBinThreads)
+        bh[(int64_t)i * ntile + blockIdx.x] = hist[i];
+}
+
+__global__ __launch_bounds__(kBinThreads) void k_bin_coarse(int n, const int *cellpt, int shift,
+                                                           int nb, int ntile, const int *boff,
+                                                           int2 *pairs)
+{
+    extern __shared__ int off[];   // [nb] next free place of each bucket's range
+    for (int i = threadIdx.x; i < nb; i += kBinThreads)
+        off[i] = boff[(int64_t)i * ntile + blockIdx.x];
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kBinTile;
+    for (int k = 0; k < kBinItems; ++k) {
+        const int64_t q = base + (int64_t)k * kBinThreads + threadIdx.x;
+        if (q < n) {
+            const int c = cellpt[q];
+            if (c >= 0) pairs[atomicAdd(&off[c >> shift], 1)] = make_int2(c, (int)q);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBinThreads) void k_bin_rank(const int *total_p, int shift,
+                                                         const int2 *pairs, int *cell_cnt,
+                                                         int *rank)
+{
+    extern __shared__ int cnt[];   // [2 << shift] cells of buckets hA, hA + 1
+    const int total = *total_p;
+    const int64_t w0 = (int64_t)blockIdx.x * kBinTile;
+    if (w0 >= total) return;   // the whole block
+    const int w1 = (int)(w0 + kBinTile < total ? w0 + kBinTile : total);
+    const int hA = pairs[w0].x >> shift, hB = pairs[w1 - 1].x >> shift;
+    if (hB - hA > 1) {
+        // sparse buckets: few pairs per cell, one atomic each
+        for (int64_t i = w0 + threadIdx.x; i < w1; i += kBinThreads)
+            rank[i] = atomicAdd(&cell_cnt[pairs[i].x], 1);
+        return;
+    }
+    const int c0 = hA << shift, nbin = 2 << shift;
+    for (int i = threadIdx.x; i < nbin; i += kBinThreads) cnt[i] = 0;
+    __syncthreads();
+    int bin[kBinItems], lr[kBinItems];
+#pragma unroll
+    for (int k = 0; k < kBinItems; ++k) {
+        const int64_t i = w0 + (int64_t)k * kBinThreads + threadIdx.x;
+        bin[k] = 0;
+        lr[k] = 0;
+        if (i < w1) {
+            bin[k] = pairs[i].x - c0;
+            lr[k] = atomicAdd(&cnt[bin[k]], 1);
+        }
+    }
+    __syncthreads();
+    // the window's block of ranks in each of its cells
+    for (int j = threadIdx.x; j < nbin; j += kBinThreads) {
+        const int v = cnt[j];
+        if (v > 0) cnt[j] = atomicAdd(&cell_cnt[c0 + j], v);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kBinItems; ++k) {
+        const int64_t i = w0 + (int64_t)k * kBinThreads + threadIdx.x;
+        if (i < w1) rank[i] = cnt[bin[k]] + lr[k];
+    }
+}
+
+__global__ __launch_bounds__(kBinThreads) void k_bin_scatter(const int *total_p, const int2 *pairs,
+                                                            const int *rank,
+                                                            const int *cell_poff, int *pbin)
+{
+    const int total = *total_p;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int2 cp = pairs[i];
+        pbin[cell_poff[cp.x] + rank[i]] = cp.y;
     }
 }
 
@@ -669,6 +802,62 @@ hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double
     hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, h, pass, (int)n, m->R, pts, pts4, keep,
                        cellpt, cell_cnt, cell_poff, rank, pbin, ncand, primary, code, elem, r,
                        dist);
+    return hipGetLastError();
+}
+
+int bin_shift(int64_t ncell)
+{
+    if (ncell > kBinMaxCells) return -1;
+    int shift = 8;
+    while ((ncell + (1ll << shift) - 1) >> shift > kBinMaxBuckets) ++shift;
+    return shift;
+}
+
+int64_t bin_tiles(int64_t n) { return (n + kBinTile - 1) / kBinTile; }
+
+hipError_t launch_bin_tiles(const fpts_mesh *m, int64_t n, const double *pts, double *pts4,
+                            const int *keep, int *cellpt, int *ncand, int *primary,
+                            int32_t *code, int32_t *elem, double *r, double *dist, int shift,
+                            int *bh, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    HashView h = hash_view(m);
+    const int64_t ncell = bin_cells(m);
+    const int nb = (int)((ncell + (1ll << shift) - 1) >> shift), ntile = (int)bin_tiles(n);
+    auto k = m->D == 2 ? k_bin_tiles<2> : k_bin_tiles<3>;
+    hipLaunchKernelGGL(k, dim3(ntile), dim3(kBinThreads), sizeof(int) * nb, s, h, (int)n, m->R,
+                       pts, pts4, keep, cellpt, ncand, primary, code, elem, r, dist, shift, nb,
+                       ntile, bh);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_coarse(const fpts_mesh *m, int64_t n, const int *cellpt, int shift,
+                             const int *boff, int2 *pairs, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t ncell = bin_cells(m);
+    const int nb = (int)((ncell + (1ll << shift) - 1) >> shift), ntile = (int)bin_tiles(n);
+    hipLaunchKernelGGL(k_bin_coarse, dim3(ntile), dim3(kBinThreads), sizeof(int) * nb, s, (int)n,
+                       cellpt, shift, nb, ntile, boff, pairs);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_rank(int64_t n, const int *total, int shift, const int2 *pairs,
+                           int *cell_cnt, int *rank, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bin_rank, dim3((unsigned)bin_tiles(n)), dim3(kBinThreads),
+                       sizeof(int) * (2 << shift), s, total, shift, pairs, cell_cnt, rank);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_scatter(int64_t n, const int *total, const int2 *pairs, const int *rank,
+                              const int *cell_poff, int *pbin, int cus, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>(grid_for(n, kBinThreads), (int64_t)cus * 16);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(grid), dim3(kBinThreads), 0, s, total, pairs, rank,
+                       cell_poff, pbin);
     return hipGetLastError();
 }
 
