@@ -160,8 +160,7 @@ FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
     w.cell_choff = c.take(I * (ncell + 1));
     w.cellpt = c.take(I * n);
     w.pbin = c.take(I * n);
-    w.ncand = c.take(I * n);
-    w.primary = c.take(I * n);
+    w.cand = c.take(sizeof(int2) * n);
     w.rank = c.take(I * n);
     w.bin_prim = c.take(I * n);
     w.elem_cnt = c.take(I * m->nel);
@@ -264,7 +263,7 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     int *bin_prim = at<int>(d_ws, w.bin_prim);
     int *cell_poff = at<int>(d_ws, w.cell_poff), *cell_choff = at<int>(d_ws, w.cell_choff);
     int *cellpt = at<int>(d_ws, w.cellpt), *pbin = at<int>(d_ws, w.pbin);
-    int *ncand = at<int>(d_ws, w.ncand), *primary = at<int>(d_ws, w.primary);
+    int2 *cand = at<int2>(d_ws, w.cand);
     int *elem_cnt = at<int>(d_ws, w.elem_cnt);
     int *elem_off = at<int>(d_ws, w.elem_off), *chunk_off = at<int>(d_ws, w.chunk_off);
     int *sorted = at<int>(d_ws, w.sorted), *ulist = at<int>(d_ws, w.ulist);
@@ -308,8 +307,8 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
             int *bh = at<int>(d_ws, w.bin_hist);
             int2 *pairs = at<int2>(d_ws, w.bin_pairs);
             const int *npairs = bh + w.bin_hist_n;   // the scan's total
-            chk(launch_bin_tiles(m, n, d_pts, pts4, keep, cellpt, ncand, primary, d_code, d_elem,
-                                 d_r, d_dist, w.bin_shift, bh, s));
+            chk(launch_bin_tiles(m, n, d_pts, pts4, keep, cellpt, cand, d_code, d_elem, d_r,
+                                 d_dist, w.bin_shift, bh, s));
             chk(launch_exclusive_scan(bh, bh, w.bin_hist_n, 1, tmp, tb, s));
             chk(launch_bin_coarse(m, n, cellpt, w.bin_shift, bh, pairs, s));
             chk(launch_bin_rank(n, npairs, w.bin_shift, pairs, cell_cnt, rank, s));
@@ -319,15 +318,15 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
             chk(launch_bin_scatter(n, npairs, pairs, rank, cell_poff, pbin, m->cus, s));
         } else {
             chk(launch_cell_bin(m, 0, n, d_pts, pts4, keep, cellpt, cell_cnt, nullptr, rank,
-                                nullptr, ncand, primary, d_code, d_elem, d_r, d_dist, s));
+                                nullptr, cand, d_code, d_elem, d_r, d_dist, s));
             chk(launch_exclusive_scan(cell_cnt, cell_poff, ncell, 1, tmp, tb, s));
             chk(launch_exclusive_scan(cell_cnt, cell_choff, ncell, kChunk, tmp, tb, s));
             chk(launch_task_map(cell_choff, ncell, task_cell, s));
             chk(launch_cell_bin(m, 1, n, d_pts, nullptr, keep, cellpt, nullptr, cell_poff, rank,
-                                pbin, nullptr, nullptr, d_code, d_elem, d_r, d_dist, s));
+                                pbin, nullptr, d_code, d_elem, d_r, d_dist, s));
         }
         chk(launch_locate_cells(m, n, d_pts, pts4, pbin, cell_poff, cell_choff, ncell, task_cell,
-                                w.tb_cell, ncand, primary, elem_cnt, rank, bin_prim, d_code,
+                                w.tb_cell, cand, elem_cnt, rank, bin_prim, d_code,
                                 d_elem, d_r, d_dist, s));
         chk(launch_exclusive_scan(elem_cnt, elem_off, nel, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt, chunk_off, nel, kChunk, tmp, tb, s));
@@ -380,16 +379,16 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     {   // phase D: other candidates of unsettled points, then the selection rule
         Span sp(m, 3, s);
         // counters[0]: listed points, counters[1]: slots handed out
-        chk(launch_unsettled(m, n, cellpt, ncand, primary, d_code, d_r, ulist, counters, s));
+        chk(launch_unsettled(m, n, cellpt, cand, d_code, d_r, ulist, counters, s));
         unsigned long long *slot_total =
             reinterpret_cast<unsigned long long *>(counters + kSlotTotal);
-        chk(launch_resolve(m, 0, n, d_pts, cellpt, primary, ulist, counters, uoff, ucnt,
+        chk(launch_resolve(m, 0, n, d_pts, cellpt, cand, ulist, counters, uoff, ucnt,
                            slot_total, elem_cnt2, nullptr, nullptr, nullptr, nullptr, nullptr,
                            w.cap2, olist, counters + kOverflowCount, s));
         chk(launch_exclusive_scan(elem_cnt2, elem_off2, nel, 1, tmp, tb, s));
         chk(launch_exclusive_scan(elem_cnt2, chunk_off2, nel, kChunk, tmp, tb, s));
         chk(launch_task_map(chunk_off2, nel, task_elem2, s));
-        chk(launch_resolve(m, 1, n, d_pts, cellpt, primary, ulist, counters, uoff, ucnt,
+        chk(launch_resolve(m, 1, n, d_pts, cellpt, cand, ulist, counters, uoff, ucnt,
                            nullptr, nullptr, elem_off2, elem_fill2, slot_pt, slot_elem, sorted2,
                            w.cap2, nullptr, nullptr, s));
         NewtonIO io{sorted2, elem_off2, chunk_off2, slot_pt, res_code, nullptr, res_r, w.cap2,
@@ -399,7 +398,7 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         // the other candidates are few and near element faces: plain FP64
         // in both modes (an FP32 phase would not pay for its launches)
         chk(launch_newton(m, FPTS_FP64, n, d_pts, io, 3, s));
-        chk(launch_select2(m, n, ulist, counters, uoff, ucnt, primary, slot_elem, w.cap2, res_r,
+        chk(launch_select2(m, n, ulist, counters, uoff, ucnt, cand, slot_elem, w.cap2, res_r,
                            res_dist, res_code, d_code, d_elem, d_r, d_dist, s));
         if (m->R >= 2) {
             // points whose other candidates did not fit the slots (none in
@@ -409,7 +408,7 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
             oio.pts4 = pts4;
             oio.ocount = counters + kOverflowCount;
             oio.cellpt = cellpt;
-            oio.primary = primary;
+            oio.cand = cand;
             oio.ov_int = ov_int;
             oio.ov_dbl = ov_dbl;
             chk(launch_newton(m, FPTS_FP64, n, d_pts, oio, 8, s));
@@ -827,7 +826,8 @@ int fpts_lpt_step(fpts_mesh *m, const fpts_lpt_params *p, int64_t n, int first, 
     // in its previous element from its previous r; the full search then
     // skips the particles that this settled.
     const FindWs w = find_ws_layout(m, n);
-    int *primary = at<int>(sub, w.primary), *elem_cnt = at<int>(sub, w.elem_cnt);
+    int2 *cand = at<int2>(sub, w.cand);
+    int *elem_cnt = at<int>(sub, w.elem_cnt);
     int *rank = at<int>(sub, w.rank), *elem_off = at<int>(sub, w.elem_off);
     int *chunk_off = at<int>(sub, w.chunk_off), *sorted = at<int>(sub, w.sorted);
     int *task_elem = at<int>(sub, w.task_elem), *tmp = at<int>(sub, w.scan_tmp);
@@ -841,11 +841,11 @@ int fpts_lpt_step(fpts_mesh *m, const fpts_lpt_params *p, int64_t n, int first, 
         chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
         chk(launch_fill_i32(counters, kCounters, 0, s));
         chk(launch_fill_i32(reinterpret_cast<int *>(stats), 6 * kStats, 0, s));
-        chk(launch_hint(m, 0, n, d_code, d_elem, d_r, primary, elem_cnt, rank, nullptr, s));
+        chk(launch_hint(m, 0, n, d_code, d_elem, d_r, cand, elem_cnt, rank, nullptr, s));
         chk(launch_exclusive_scan(elem_cnt, elem_off, m->nel, 1, tmp, w.scan_blocks, s));
         chk(launch_exclusive_scan(elem_cnt, chunk_off, m->nel, kChunk, tmp, w.scan_blocks, s));
         chk(launch_task_map(chunk_off, m->nel, task_elem, s));
-        chk(launch_primary_scatter(n, m->nel, primary, elem_off, rank, sorted, s));
+        chk(launch_primary_scatter(n, m->nel, cand, elem_off, rank, sorted, s));
     }
     {
         Span sp(m, 2, s);
@@ -856,7 +856,7 @@ int fpts_lpt_step(fpts_mesh *m, const fpts_lpt_params *p, int64_t n, int first, 
                     counters + kNewtonCounters, stats, task_elem, w.tb_elem, nullptr, 0,
                     keep, kHintPasses};
         chk(launch_newton(m, precision, n, d_x, io, 2, s));
-        chk(launch_hint(m, 1, n, d_code, d_elem, d_r, primary, nullptr, nullptr, keep, s));
+        chk(launch_hint(m, 1, n, d_code, d_elem, d_r, cand, nullptr, nullptr, keep, s));
     }
     if (e != hipSuccess) return FPTS_EDEVICE;
     return find_impl(m, n, d_x, d_code, d_elem, d_r, d_dist, precision, sub, sub_bytes, stream,
@@ -896,7 +896,8 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
                        stream, nullptr, rs);
     if (st != FPTS_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    const int *primary = at<int>(d_ws, w.primary), *sorted = at<int>(d_ws, w.sorted);
+    const int2 *cand = at<int2>(d_ws, w.cand);
+    const int *sorted = at<int>(d_ws, w.sorted);
     const int *elem_off = at<int>(d_ws, w.elem_off), *chunk_off = at<int>(d_ws, w.chunk_off);
     const int *task_elem = at<int>(d_ws, w.task_elem);
     int *elem_cnt = at<int>(ews, v.elem_cnt), *erank = at<int>(ews, v.rank);
@@ -928,7 +929,7 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
         Span sp(m, 4, s);
         chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
         chk(launch_fill_i32(scount, 1, 0, s));
-        chk(launch_eval_bin(m, 0, n, d_code, d_elem, d_r, primary, n_fields, d_out, elem_cnt,
+        chk(launch_eval_bin(m, 0, n, d_code, d_elem, d_r, cand, n_fields, d_out, elem_cnt,
                             nullptr, erank, nullptr, s));
         if (split)
             chk(launch_eval_split(m, n, d_elem, erank, elem_cnt, nullptr, nullptr, nullptr,
@@ -940,7 +941,7 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
             chk(launch_eval_split(m, n, d_elem, erank, elem_cnt, eoff, esorted, slist, scount, 1,
                                   s));
         else
-            chk(launch_eval_bin(m, 1, n, d_code, d_elem, d_r, primary, n_fields, d_out, nullptr,
+            chk(launch_eval_bin(m, 1, n, d_code, d_elem, d_r, cand, n_fields, d_out, nullptr,
                                 eoff, erank, esorted, s));
     }
     {

@@ -159,8 +159,10 @@ __device__ inline bool box_pass(P rec, const double *x, double &depth)
     return in && (mx <= 1.0);
 }
 
+// cand[p] (find workspace): (number of candidates that pass the box tests,
+// primary element or -1) of point p
 struct FindWs {
-    size_t cell_cnt, cell_poff, cell_choff, cellpt, pbin, ncand, primary, rank, bin_prim,
+    size_t cell_cnt, cell_poff, cell_choff, cellpt, pbin, cand, rank, bin_prim,
         elem_cnt, elem_off, chunk_off, sorted, ulist, uoff, ucnt, elem_cnt2, elem_fill2,
         elem_off2, chunk_off2, slot_pt, slot_elem, sorted2, res_r, res_dist, res_code,
         task_cell, task_elem, task_elem2, scan_tmp, counters, stats, pts4, start, park_meta,
@@ -235,7 +237,7 @@ struct NewtonIO {
     // and ov_dbl [R + 1][grid]; code/elem/r/dist are the final outputs
     const int *ocount;
     const int *cellpt;
-    const int *primary;
+    const int2 *cand;
     int *ov_int;
     double *ov_dbl;
 };
@@ -342,7 +344,7 @@ int64_t scan_tmp_blocks(int64_t n);
 // writes the coordinates packed per point to pts4 unless it is null
 hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double *pts,
                            double *pts4, const int *keep, int *cellpt, int *cell_cnt,
-                           const int *cell_poff, int *rank, int *pbin, int *ncand, int *primary,
+                           const int *cell_poff, int *rank, int *pbin, int2 *cand,
                            int32_t *code, int32_t *elem, double *r, double *dist, hipStream_t s);
 // Phase A without per-point atomics (meshes with at most kBinMaxCells
 // cells; bin_shift returns -1 beyond): cells grouped into buckets of
@@ -364,7 +366,7 @@ inline int64_t bin_cells(const fpts_mesh *m)
     return c;
 }
 hipError_t launch_bin_tiles(const fpts_mesh *m, int64_t n, const double *pts, double *pts4,
-                            const int *keep, int *cellpt, int *ncand, int *primary,
+                            const int *keep, int *cellpt, int2 *cand,
                             int32_t *code, int32_t *elem, double *r, double *dist, int shift,
                             int *bh, hipStream_t s);
 hipError_t launch_bin_coarse(const fpts_mesh *m, int64_t n, const int *cellpt, int shift,
@@ -377,7 +379,7 @@ hipError_t launch_bin_scatter(int64_t n, const int *total, const int2 *pairs, co
 // INTERIOR point its primary (counted per element); pass 1 sets keep[p] for
 // points the hinted search settled
 hipError_t launch_hint(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
-                       const int32_t *elem, const double *r, int *primary, int *elem_cnt,
+                       const int32_t *elem, const double *r, int2 *cand, int *elem_cnt,
                        int *rank, int *keep, hipStream_t s);
 // phase B: candidates of each point from its cell's list (one wave per 64
 // points of one cell), primary = deepest inside its OBB
@@ -395,15 +397,15 @@ hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
                                const double *pts4,
                                const int *pbin, const int *cell_poff, const int *cell_choff,
                                int64_t ncell, const int *task_cell, int64_t task_bound,
-                               int *ncand, int *primary, int *elem_cnt, int *rank,
+                               int2 *cand, int *elem_cnt, int *rank,
                                int *bin_prim, int32_t *code, int32_t *elem, double *r,
                                double *dist, hipStream_t s);
 // sorted[elem_off[bin_prim[i]] + rank[i]] = pbin[i] for i < *nbinned
 hipError_t launch_primary_scatter_bins(int64_t n, const int *nbinned, const int *pbin,
                                        const int *bin_prim, const int *rank,
                                        const int *elem_off, int *sorted, hipStream_t s);
-// sorted[elem_off[primary[p]] + rank[p]] = p
-hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int *primary,
+// sorted[elem_off[cand[p].y] + rank[p]] = p
+hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int2 *cand,
                                   const int *elem_off, const int *rank, int *sorted,
                                   hipStream_t s);
 // phase D: list the points whose primary result does not settle them
@@ -411,17 +413,17 @@ hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int *primary,
 // each point a block of slots (uoff, ucnt, running total *slot_total), pass
 // 1 writes the (point, element) slots into element buckets; select2 applies
 // the selection rule to every listed point
-hipError_t launch_unsettled(const fpts_mesh *m, int64_t n, const int *cellpt, const int *ncand,
-                            const int *primary, const int32_t *code, const double *r, int *ulist,
+hipError_t launch_unsettled(const fpts_mesh *m, int64_t n, const int *cellpt, const int2 *cand,
+                            const int32_t *code, const double *r, int *ulist,
                             int *ucount, hipStream_t s);
 hipError_t launch_resolve(const fpts_mesh *m, int pass, int64_t n, const double *pts,
-                          const int *cellpt, const int *primary, const int *ulist,
+                          const int *cellpt, const int2 *cand, const int *ulist,
                           const int *ucount, int *uoff, int *ucnt, unsigned long long *slot_total,
                           int *elem_cnt2, const int *elem_off2, int *elem_fill2, int *slot_pt,
                           int *slot_elem, int *sorted2, int64_t cap2, int *olist, int *ocount,
                           hipStream_t s);
 hipError_t launch_select2(const fpts_mesh *m, int64_t n, const int *ulist, const int *ucount,
-                          const int *uoff, const int *ucnt, const int *primary,
+                          const int *uoff, const int *ucnt, const int2 *cand,
                           const int *slot_elem, int64_t cap2, const double *res_r,
                           const double *res_dist, const int *res_code, int32_t *code,
                           int32_t *elem, double *r, double *dist, hipStream_t s);
@@ -439,11 +441,11 @@ hipError_t launch_eval_sparse(const fpts_mesh *m, int64_t n, const double *r, in
                               int field_n, const double *field, double *out,
                               const int32_t *elem, const int *list, const int *count,
                               hipStream_t s);
-// interpolation binning; with `primary` (fused find + interpolate) the
+// interpolation binning; with `cand` (fused find + interpolate) the
 // points their primary result settled are left out (r is read for that)
 // (pass 0 keeps each point's rank in its element's bucket, pass 1 uses it)
 hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
-                           const int32_t *elem, const double *r, const int *primary,
+                           const int32_t *elem, const double *r, const int2 *cand,
                            int n_fields, double *out, int *elem_cnt, const int *elem_off,
                            int *rank, int *sorted, hipStream_t s);
 // field_n: GLL nodes per direction of the field (its own order, 2..kMaxN)

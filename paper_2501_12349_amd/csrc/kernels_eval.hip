@@ -24,12 +24,12 @@ constexpr int kSparseMax = 4;
 
 // pass 0: count points per element, keep each point's rank in its bucket
 // (-1 for points not binned) and write NaN for NOT_FOUND points; pass 1:
-// place point ids at their ranks in their element's bucket.  With `primary`
+// place point ids at their ranks in their element's bucket.  With `cand`
 // (fused find + interpolate) the points that their primary result settled
 // are left out: the fused pass over Find's primary list has them.
 __global__ __launch_bounds__(256) void k_eval_bin(int pass, int n, int nel, int R,
                                                  const int32_t *code, const int32_t *elem,
-                                                 const double *r, const int *primary,
+                                                 const double *r, const int2 *cand,
                                                  int n_fields, double *out, int *elem_cnt,
                                                  const int *elem_off, int *rank,
                                                  int *sorted)
@@ -51,8 +51,8 @@ __global__ __launch_bounds__(256) void k_eval_bin(int pass, int n, int nel, int 
     if (in) {
         e = elem[p];
         cd = code[p];
-        if (primary) {
-            pr = primary[p];
+        if (cand) {
+            pr = cand[p].y;
 #pragma unroll
             for (int k = 0; k < 3; ++k)
                 if (k < R) rr[k] = r[(size_t)k * n + p];
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void k_eval_bin(int pass, int n, int nel, int 
     }
     const bool found = in && cd != FPTS_NOT_FOUND && e >= 0 && e < nel;
     bool done = false;
-    if (primary && found && cd == FPTS_INTERIOR && pr == e) {
+    if (cand && found && cd == FPTS_INTERIOR && pr == e) {
         double mg = 1.0;
         for (int k = 0; k < R; ++k) mg = fmin(mg, 1.0 - fabs(rr[k]));
         done = mg > kSettleGuard;
@@ -562,13 +562,13 @@ EvalFn pick_eval_r(int R, int N)
 }  // namespace
 
 hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
-                           const int32_t *elem, const double *r, const int *primary,
+                           const int32_t *elem, const double *r, const int2 *cand,
                            int n_fields, double *out, int *elem_cnt, const int *elem_off,
                            int *rank, int *sorted, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_eval_bin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pass,
-                       (int)n, (int)m->nel, m->R, code, elem, r, primary, n_fields, out,
+                       (int)n, (int)m->nel, m->R, code, elem, r, cand, n_fields, out,
                        elem_cnt, elem_off, rank, sorted);
     return hipGetLastError();
 }

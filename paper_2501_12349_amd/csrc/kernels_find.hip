@@ -138,9 +138,8 @@ __device__ inline void write_not_found(int p, int n, int R, int32_t *code, int32
 // point outside the map.
 template <int D>
 __device__ inline int bin_point(const HashView &h, int p, int n, int R, const double *pts,
-                                double *pts4, const int *keep, int *cellpt, int *ncand,
-                                int *primary, int32_t *code, int32_t *elem, double *r,
-                                double *dist)
+                                double *pts4, const int *keep, int *cellpt, int2 *cand,
+                                int32_t *code, int32_t *elem, double *r, double *dist)
 {
     int c = -1;
     const bool kept = keep && keep[p];
@@ -159,8 +158,7 @@ __device__ inline int bin_point(const HashView &h, int p, int n, int R, const do
         }
     }
     cellpt[p] = c;
-    ncand[p] = 0;
-    primary[p] = -1;
+    cand[p] = make_int2(0, -1);
     if (c < 0 && !kept) write_not_found(p, n, R, code, elem, r, dist);
     return c;
 }
@@ -173,17 +171,15 @@ __global__ __launch_bounds__(256) void k_cell_bin(HashView h, int pass, int n, i
                                                  const double *pts, double *pts4, const int *keep,
                                                  int *cellpt, int *cell_cnt,
                                                  const int *cell_poff, int *rank,
-                                                 int *pbin, int *ncand, int *primary,
-                                                 int32_t *code, int32_t *elem, double *r,
-                                                 double *dist)
+                                                 int *pbin, int2 *cand, int32_t *code,
+                                                 int32_t *elem, double *r, double *dist)
 {
     // no early exit: wave_inc needs every lane
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = p < n;
     if (pass == 0) {
-        const int c = in ? bin_point<D>(h, p, n, R, pts, pts4, keep, cellpt, ncand, primary, code,
-                                        elem, r, dist)
-                         : -1;
+        const int c =
+            in ? bin_point<D>(h, p, n, R, pts, pts4, keep, cellpt, cand, code, elem, r, dist) : -1;
         const int k = wave_inc(cell_cnt, c, c >= 0);
         if (c >= 0) rank[p] = k;
     } else {
@@ -210,14 +206,14 @@ __global__ __launch_bounds__(256) void k_cell_bin(HashView h, int pass, int n, i
 //           pair order, so a window's writes fall in the cells of one or two
 //           buckets.
 constexpr int kBinThreads = 256;
-constexpr int kBinItems = 16;
+constexpr int kBinItems = 32;
 constexpr int kBinTile = kBinThreads * kBinItems;
 
 template <int D>
 __global__ __launch_bounds__(kBinThreads) void k_bin_tiles(HashView h, int n, int R,
                                                           const double *pts, double *pts4,
                                                           const int *keep, int *cellpt,
-                                                          int *ncand, int *primary,
+                                                          int2 *cand,
                                                           int32_t *code, int32_t *elem, double *r,
                                                           double *dist, int shift, int nb,
                                                           int ntile, int *bh)
@@ -229,8 +225,8 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_tiles(HashView h, int n, in
     for (int k = 0; k < kBinItems; ++k) {
         const int64_t q = base + (int64_t)k * kBinThreads + threadIdx.x;
         if (q < n) {
-            const int c = bin_point<D>(h, (int)q, n, R, pts, pts4, keep, cellpt, ncand, primary,
-                                       code, elem, r, dist);
+            const int c = bin_point<D>(h, (int)q, n, R, pts, pts4, keep, cellpt, cand, code,
+                                       elem, r, dist);
             if (c >= 0) atomicAdd(&hist[c >> shift], 1);
         }
     }
@@ -346,8 +342,8 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
                                                     const double *pts4,
                                                     const int *pbin, const int *cell_poff,
                                                     const int *cell_choff, int ncell,
-                                                    const int *task_cell, int *ncand,
-                                                    int *primary, int *elem_cnt, int *rank,
+                                                    const int *task_cell, int2 *cand,
+                                                    int *elem_cnt, int *rank,
                                                     int *bin_prim, int32_t *code, int32_t *elem,
                                                     double *r, double *dist)
 {
@@ -444,8 +440,7 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
         if (!l2) ids_of(nxt, nxt.q0, pn, minen);   // a cell without candidates
         if (!l3) data_of(nxt, nxt.q0, pn, minen, xn, rvn);
         if (has) {
-            ncand[p] = cnt;
-            primary[p] = prim;
+            cand[p] = make_int2(cnt, prim);   // one scattered write per point
             if (prim < 0) write_not_found(p, n, R, code, elem, r, dist);
         }
         const int k = wave_inc(elem_cnt, prim, has && prim >= 0);
@@ -466,12 +461,12 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
     }
 }
 
-__global__ __launch_bounds__(256) void k_primary_scatter(int n, int nel, const int *primary,
+__global__ __launch_bounds__(256) void k_primary_scatter(int n, int nel, const int2 *cand,
                                                         const int *elem_off, const int *rank,
                                                         int *sorted)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    const int e = p < n ? primary[p] : -1;
+    const int e = p < n ? cand[p].y : -1;
     if (e >= 0 && e < nel) sorted[elem_off[e] + rank[p]] = p;
 }
 
@@ -516,7 +511,7 @@ __device__ inline bool settled(int nc, int32_t cd, const double (&rr)[3], int R)
 constexpr int kMarkChunk = 4096;
 
 __global__ __launch_bounds__(256) void k_unsettled(int n, int R, const int *cellpt,
-                                                  const int *ncand, const int *primary,
+                                                  const int2 *cand,
                                                   const int32_t *code, const double *r,
                                                   int *ulist, int *ucount)
 {
@@ -531,7 +526,9 @@ __global__ __launch_bounds__(256) void k_unsettled(int n, int R, const int *cell
         const int p = (int)q;
         bool todo = false;
         if (q < n) {
-            const int c = cellpt[p], prim = primary[p], nc = ncand[p];
+            const int c = cellpt[p];
+            const int2 cd2 = cand[p];
+            const int prim = cd2.y, nc = cd2.x;
             const int32_t cd = code[p];
             double rr[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -579,7 +576,7 @@ __device__ __forceinline__ int wave_excl_sum(int v, int &total)
 // by element.
 template <int D>
 __global__ __launch_bounds__(256) void k_resolve(HashView h, int pass, int n, const double *pts,
-                                                const int *cellpt, const int *primary,
+                                                const int *cellpt, const int2 *cand,
                                                 const int *ulist, const int *ucount,
                                                 int *uoff, int *ucnt,
                                                 unsigned long long *slot_total,
@@ -600,7 +597,7 @@ __global__ __launch_bounds__(256) void k_resolve(HashView h, int pass, int n, co
         for (int d = 0; d < D; ++d) x[d] = 0.0;
         if (act) {
             p = ulist[i];
-            prim = primary[p];
+            prim = cand[p].y;
             c = cellpt[p];
 #pragma unroll
             for (int d = 0; d < D; ++d) x[d] = pts[(size_t)d * n + p];
@@ -659,7 +656,7 @@ __global__ __launch_bounds__(256) void k_resolve(HashView h, int pass, int n, co
 // distance (lowest id on ties).
 __global__ __launch_bounds__(256) void k_select2(int n, int R, const int *ulist,
                                                 const int *ucount, const int *uoff,
-                                                const int *ucnt, const int *primary,
+                                                const int *ucnt, const int2 *cand,
                                                 const int *slot_elem, int64_t cap2,
                                                 const double *res_r, const double *res_dist,
                                                 const int *res_code, int32_t *code,
@@ -672,7 +669,7 @@ __global__ __launch_bounds__(256) void k_select2(int n, int R, const int *ulist,
         if (s0 == s1) continue;
         // best so far: the primary (slot -1)
         int best = -1;
-        int bcode = code[p], belem = primary[p];
+        int bcode = code[p], belem = cand[p].y;
         double bdist = dist[p];
         for (int s = s0; s < s1; ++s) {
             const int e = slot_elem[s], cd = res_code[s];
@@ -708,7 +705,7 @@ inline int grid_for(int64_t n, int block) { return (int)((n + block - 1) / block
 // the full search gives, and they are kept.
 __global__ __launch_bounds__(256) void k_hint(int pass, int n, int nel, int R,
                                              const int32_t *code, const int32_t *elem,
-                                             const double *r, int *primary, int *elem_cnt,
+                                             const double *r, int2 *cand, int *elem_cnt,
                                              int *rank, int *keep)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -716,11 +713,11 @@ __global__ __launch_bounds__(256) void k_hint(int pass, int n, int nel, int R,
     if (pass == 0) {
         const int e = in && code[p] == FPTS_INTERIOR ? elem[p] : -1;
         const bool ok = e >= 0 && e < nel;
-        if (in) primary[p] = ok ? e : -1;
+        if (in) cand[p] = make_int2(ok ? 1 : 0, ok ? e : -1);
         const int k = wave_inc(elem_cnt, e, ok);
         if (ok) rank[p] = k;
     } else if (in) {
-        bool k = primary[p] >= 0 && code[p] == FPTS_INTERIOR && keep[p] == 1;
+        bool k = cand[p].y >= 0 && code[p] == FPTS_INTERIOR && keep[p] == 1;
         double mg = 1.0;
         for (int a = 0; a < R; ++a) mg = fmin(mg, 1.0 - fabs(r[(size_t)a * n + p]));
         keep[p] = k && mg > kSettleGuard;
@@ -792,7 +789,7 @@ hipError_t launch_park_bin(int pass, const int4 *meta, const int *count, int64_t
 
 hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double *pts,
                            double *pts4, const int *keep, int *cellpt, int *cell_cnt,
-                           const int *cell_poff, int *rank, int *pbin, int *ncand, int *primary,
+                           const int *cell_poff, int *rank, int *pbin, int2 *cand,
                            int32_t *code, int32_t *elem, double *r, double *dist, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
@@ -800,15 +797,16 @@ hipError_t launch_cell_bin(const fpts_mesh *m, int pass, int64_t n, const double
     const int grid = grid_for(n, 256);
     auto k = m->D == 2 ? k_cell_bin<2> : k_cell_bin<3>;
     hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, h, pass, (int)n, m->R, pts, pts4, keep,
-                       cellpt, cell_cnt, cell_poff, rank, pbin, ncand, primary, code, elem, r,
-                       dist);
+                       cellpt, cell_cnt, cell_poff, rank, pbin, cand, code, elem, r, dist);
     return hipGetLastError();
 }
 
 int bin_shift(int64_t ncell)
 {
     if (ncell > kBinMaxCells) return -1;
-    int shift = 8;
+    // buckets of at least 512 cells: a tile's run per bucket is then tens
+    // of pairs long (whole cache lines) at a few points per cell
+    int shift = 9;
     while ((ncell + (1ll << shift) - 1) >> shift > kBinMaxBuckets) ++shift;
     return shift;
 }
@@ -816,7 +814,7 @@ int bin_shift(int64_t ncell)
 int64_t bin_tiles(int64_t n) { return (n + kBinTile - 1) / kBinTile; }
 
 hipError_t launch_bin_tiles(const fpts_mesh *m, int64_t n, const double *pts, double *pts4,
-                            const int *keep, int *cellpt, int *ncand, int *primary,
+                            const int *keep, int *cellpt, int2 *cand,
                             int32_t *code, int32_t *elem, double *r, double *dist, int shift,
                             int *bh, hipStream_t s)
 {
@@ -826,7 +824,7 @@ hipError_t launch_bin_tiles(const fpts_mesh *m, int64_t n, const double *pts, do
     const int nb = (int)((ncell + (1ll << shift) - 1) >> shift), ntile = (int)bin_tiles(n);
     auto k = m->D == 2 ? k_bin_tiles<2> : k_bin_tiles<3>;
     hipLaunchKernelGGL(k, dim3(ntile), dim3(kBinThreads), sizeof(int) * nb, s, h, (int)n, m->R,
-                       pts, pts4, keep, cellpt, ncand, primary, code, elem, r, dist, shift, nb,
+                       pts, pts4, keep, cellpt, cand, code, elem, r, dist, shift, nb,
                        ntile, bh);
     return hipGetLastError();
 }
@@ -873,7 +871,7 @@ hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
                                const double *pts4,
                                const int *pbin, const int *cell_poff, const int *cell_choff,
                                int64_t ncell, const int *task_cell, int64_t task_bound,
-                               int *ncand, int *primary, int *elem_cnt, int *rank,
+                               int2 *cand, int *elem_cnt, int *rank,
                                int *bin_prim, int32_t *code, int32_t *elem, double *r,
                                double *dist, hipStream_t s)
 {
@@ -882,8 +880,7 @@ hipError_t launch_locate_cells(const fpts_mesh *m, int64_t n, const double *pts,
     auto k = m->D == 2 ? (pts4 ? k_locate_cells<2, true> : k_locate_cells<2, false>)
                        : (pts4 ? k_locate_cells<3, true> : k_locate_cells<3, false>);
     hipLaunchKernelGGL(k, dim3(task_grid(task_bound, m->cus)), dim3(64), 0, s, h, (int)n, m->R,
-                       pts, pts4, pbin, cell_poff, cell_choff, (int)ncell, task_cell, ncand,
-                       primary,
+                       pts, pts4, pbin, cell_poff, cell_choff, (int)ncell, task_cell, cand,
                        elem_cnt, rank, bin_prim, code, elem, r, dist);
     return hipGetLastError();
 }
@@ -898,23 +895,23 @@ hipError_t launch_primary_scatter_bins(int64_t n, const int *nbinned, const int 
     return hipGetLastError();
 }
 
-hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int *primary,
+hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int2 *cand,
                                   const int *elem_off, const int *rank, int *sorted,
                                   hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_primary_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, (int)n,
-                       (int)nel, primary, elem_off, rank, sorted);
+                       (int)nel, cand, elem_off, rank, sorted);
     return hipGetLastError();
 }
 
-hipError_t launch_unsettled(const fpts_mesh *m, int64_t n, const int *cellpt, const int *ncand,
-                            const int *primary, const int32_t *code, const double *r, int *ulist,
+hipError_t launch_unsettled(const fpts_mesh *m, int64_t n, const int *cellpt, const int2 *cand,
+                            const int32_t *code, const double *r, int *ulist,
                             int *ucount, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_unsettled, dim3(grid_for(n, kMarkChunk)), dim3(256), 0, s, (int)n, m->R,
-                       cellpt, ncand, primary, code, r, ulist, ucount);
+                       cellpt, cand, code, r, ulist, ucount);
     return hipGetLastError();
 }
 
@@ -926,7 +923,7 @@ static int list_grid(const fpts_mesh *m, int64_t n)
 }
 
 hipError_t launch_resolve(const fpts_mesh *m, int pass, int64_t n, const double *pts,
-                          const int *cellpt, const int *primary, const int *ulist,
+                          const int *cellpt, const int2 *cand, const int *ulist,
                           const int *ucount, int *uoff, int *ucnt, unsigned long long *slot_total,
                           int *elem_cnt2, const int *elem_off2, int *elem_fill2, int *slot_pt,
                           int *slot_elem, int *sorted2, int64_t cap2, int *olist, int *ocount,
@@ -936,20 +933,20 @@ hipError_t launch_resolve(const fpts_mesh *m, int pass, int64_t n, const double 
     HashView h = hash_view(m);
     auto k = m->D == 2 ? k_resolve<2> : k_resolve<3>;
     hipLaunchKernelGGL(k, dim3(list_grid(m, n)), dim3(256), 0, s, h, pass, (int)n, pts, cellpt,
-                       primary, ulist, ucount, uoff, ucnt, slot_total, elem_cnt2, elem_off2,
+                       cand, ulist, ucount, uoff, ucnt, slot_total, elem_cnt2, elem_off2,
                        elem_fill2, slot_pt, slot_elem, sorted2, cap2, olist, ocount);
     return hipGetLastError();
 }
 
 hipError_t launch_select2(const fpts_mesh *m, int64_t n, const int *ulist, const int *ucount,
-                          const int *uoff, const int *ucnt, const int *primary,
+                          const int *uoff, const int *ucnt, const int2 *cand,
                           const int *slot_elem, int64_t cap2, const double *res_r,
                           const double *res_dist, const int *res_code, int32_t *code,
                           int32_t *elem, double *r, double *dist, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_select2, dim3(list_grid(m, n)), dim3(256), 0, s, (int)n, m->R, ulist,
-                       ucount, uoff, ucnt, primary, slot_elem, cap2, res_r, res_dist, res_code,
+                       ucount, uoff, ucnt, cand, slot_elem, cap2, res_r, res_dist, res_code,
                        code, elem, r, dist);
     return hipGetLastError();
 }
@@ -959,12 +956,12 @@ hipError_t launch_select2(const fpts_mesh *m, int64_t n, const int *ulist, const
 namespace fpts {
 
 hipError_t launch_hint(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
-                       const int32_t *elem, const double *r, int *primary, int *elem_cnt,
+                       const int32_t *elem, const double *r, int2 *cand, int *elem_cnt,
                        int *rank, int *keep, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_hint, dim3(grid_for(n, 256)), dim3(256), 0, s, pass, (int)n,
-                       (int)m->nel, m->R, code, elem, r, primary, elem_cnt, rank, keep);
+                       (int)m->nel, m->R, code, elem, r, cand, elem_cnt, rank, keep);
     return hipGetLastError();
 }
 

@@ -1723,7 +1723,7 @@ k_resolve_overflow(NewtonArgs a, HashView h)
     Counters cn;
     for (int i = b; i < cnt; i += G) {
         const int p = io.list[i];
-        const int prim = io.primary[p], c = io.cellpt[p];
+        const int prim = io.cand[p].y, c = io.cellpt[p];
         double x[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) x[d] = point_coord<D>(a, p, d);
