@@ -1134,7 +1134,7 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
         // whose pairs that ends take new pairs at once, and those starting
         // at a node get their first trial point too (a second round), so no
         // slot idles in this trip's sweep.  One copy of each step.
-        bool done = false, h2 = false;
+        bool done = false;
         for (int round = 0;; round = 1) {
             refill();
             fresh = false;
@@ -1150,7 +1150,8 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                 // a slot that waits for second derivatives gets them at
                 // once: holding it back to batch more waiting slots (4 or
                 // 8) costs more in idle slots than the batching saves
-                // (measured on hex48)
+                // (measured on hex48); it is then planned with the others
+                // and takes part in this trip's sweep 1
                 if (KIND != kPrimary && KIND != kPolish && waitm != 0) {
                     T Sn[kSym<R>];
                     sweep2<T, D, R, N>(xl, tab, lane, r, dx, Sn);
@@ -1166,8 +1167,6 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                         if (leader && FINAL) cn.evals_h2++;
                     }
                     if (leader && FINAL && state != S_FREE) cn.evals_h2_exec++;
-                    h2 = true;
-                    break;
                 }
             } else if (!any) {
                 break;
@@ -1176,7 +1175,6 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
             if (round == 1 || !__ballot(leader && ended)) break;
         }
         if (done) break;
-        if (h2) continue;
         if (state != S_INIT && state != S_STEP) {
 #pragma unroll
             for (int k = 0; k < R; ++k) q[k] = r[k];
