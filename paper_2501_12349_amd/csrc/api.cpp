@@ -248,7 +248,7 @@ namespace fpts {
 // writes its settling results in list order (NewtonIO::rs).
 int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int32_t *d_elem,
               double *d_r, double *d_dist, int precision, void *d_ws, size_t ws_bytes,
-              void *stream, const int *keep, double *rs)
+              void *stream, const int *keep, double *rs, const EvalRest *rest)
 {
     if (!m || n < 0 || n > INT32_MAX - 1) return FPTS_EINVAL;
     if (precision != FPTS_FP64 && precision != FPTS_MIXED) return FPTS_EINVAL;
@@ -302,6 +302,7 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
         chk(launch_fill_i32(elem_fill2, nel, 0, s));
         chk(launch_fill_i32(park_cnt, nel, 0, s));
         chk(launch_fill_i32(counters, kCounters, 0, s));
+        if (rest) chk(launch_fill_i32(rest->count, 1, 0, s));
         chk(launch_fill_i32(reinterpret_cast<int *>(stats), 6 * kStats, 0, s));
         if (w.bin_shift >= 0) {
             int *bh = at<int>(d_ws, w.bin_hist);
@@ -379,7 +380,9 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     {   // phase D: other candidates of unsettled points, then the selection rule
         Span sp(m, 3, s);
         // counters[0]: listed points, counters[1]: slots handed out
-        chk(launch_unsettled(m, n, cellpt, cand, d_code, d_r, ulist, counters, s));
+        const EvalRest none{nullptr, nullptr, nullptr, 0};
+        chk(launch_unsettled(m, n, cellpt, cand, d_code, d_r, ulist, counters,
+                             rest ? *rest : none, s));
         unsigned long long *slot_total =
             reinterpret_cast<unsigned long long *>(counters + kSlotTotal);
         chk(launch_resolve(m, 0, n, d_pts, cellpt, cand, ulist, counters, uoff, ucnt,
@@ -892,8 +895,13 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
     const EvalWs v = eval_ws_layout(m, n);
     void *ews = static_cast<char *>(d_ws) + w.total;
     double *rs = at<double>(d_ws, w.total + align_up(v.total));
+    // volume and surface meshes: the points left for the second
+    // interpolation pass are listed by the find's marking pass (in slist,
+    // which only the line-mesh path uses otherwise)
+    const bool listed = m->R >= 2;
+    const EvalRest rest{at<int>(ews, v.slist), at<int>(ews, v.scount), d_out, n_fields};
     int st = find_impl(m, n, d_pts, d_code, d_elem, d_r, d_dist, precision, d_ws, w.total,
-                       stream, nullptr, rs);
+                       stream, nullptr, rs, listed ? &rest : nullptr);
     if (st != FPTS_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     const int2 *cand = at<int2>(d_ws, w.cand);
@@ -928,9 +936,14 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
         const bool split = m->R == 1;
         Span sp(m, 4, s);
         chk(launch_fill_i32(elem_cnt, m->nel, 0, s));
-        chk(launch_fill_i32(scount, 1, 0, s));
-        chk(launch_eval_bin(m, 0, n, d_code, d_elem, d_r, cand, n_fields, d_out, elem_cnt,
-                            nullptr, erank, nullptr, s));
+        if (listed) {
+            chk(launch_eval_bin_list(m, 0, slist, scount, n, d_elem, elem_cnt, nullptr, erank,
+                                     nullptr, s));
+        } else {
+            chk(launch_fill_i32(scount, 1, 0, s));
+            chk(launch_eval_bin(m, 0, n, d_code, d_elem, d_r, cand, n_fields, d_out, elem_cnt,
+                                nullptr, erank, nullptr, s));
+        }
         if (split)
             chk(launch_eval_split(m, n, d_elem, erank, elem_cnt, nullptr, nullptr, nullptr,
                                   nullptr, 0, s));
@@ -940,6 +953,9 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
         if (split)
             chk(launch_eval_split(m, n, d_elem, erank, elem_cnt, eoff, esorted, slist, scount, 1,
                                   s));
+        else if (listed)
+            chk(launch_eval_bin_list(m, 1, slist, scount, n, d_elem, nullptr, eoff, erank,
+                                     esorted, s));
         else
             chk(launch_eval_bin(m, 1, n, d_code, d_elem, d_r, cand, n_fields, d_out, nullptr,
                                 eoff, erank, esorted, s));

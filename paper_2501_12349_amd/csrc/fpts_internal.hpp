@@ -159,6 +159,16 @@ __device__ inline bool box_pass(P rec, const double *x, double &depth)
     return in && (mx <= 1.0);
 }
 
+// fused find + interpolate (list null otherwise): the points the pass over
+// the primary list does not interpolate (list, *count of them; count zeroed
+// by the find), and NaN values for NOT_FOUND points
+struct EvalRest {
+    int *list;
+    int *count;
+    double *out;
+    int n_fields;
+};
+
 // cand[p] (find workspace): (number of candidates that pass the box tests,
 // primary element or -1) of point p
 struct FindWs {
@@ -326,7 +336,7 @@ int device_setup(fpts_mesh *m, hipStream_t s);
 // and are not searched (api.cpp)
 int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int32_t *d_elem,
               double *d_r, double *d_dist, int precision, void *d_ws, size_t ws_bytes,
-              void *stream, const int *keep, double *rs);
+              void *stream, const int *keep, double *rs, const EvalRest *rest = nullptr);
 
 // workspace layouts (api.cpp)
 FindWs find_ws_layout(const fpts_mesh *m, int64_t n);
@@ -415,7 +425,7 @@ hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int2 *cand,
 // the selection rule to every listed point
 hipError_t launch_unsettled(const fpts_mesh *m, int64_t n, const int *cellpt, const int2 *cand,
                             const int32_t *code, const double *r, int *ulist,
-                            int *ucount, hipStream_t s);
+                            int *ucount, const EvalRest &rest, hipStream_t s);
 hipError_t launch_resolve(const fpts_mesh *m, int pass, int64_t n, const double *pts,
                           const int *cellpt, const int2 *cand, const int *ulist,
                           const int *ucount, int *uoff, int *ucnt, unsigned long long *slot_total,
@@ -444,6 +454,12 @@ hipError_t launch_eval_sparse(const fpts_mesh *m, int64_t n, const double *r, in
 // interpolation binning; with `cand` (fused find + interpolate) the
 // points their primary result settled are left out (r is read for that)
 // (pass 0 keeps each point's rank in its element's bucket, pass 1 uses it)
+// the same over a list of points (*count of them) whose results are final
+// and found (no NaN writes): pass 0 counts per element and keeps each entry's
+// rank, pass 1 places the points
+hipError_t launch_eval_bin_list(const fpts_mesh *m, int pass, const int *list, const int *count,
+                                int64_t cap, const int32_t *elem, int *elem_cnt,
+                                const int *elem_off, int *rank, int *sorted, hipStream_t s);
 hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
                            const int32_t *elem, const double *r, const int2 *cand,
                            int n_fields, double *out, int *elem_cnt, const int *elem_off,

@@ -72,6 +72,31 @@ __global__ __launch_bounds__(256) void k_eval_bin(int pass, int n, int nel, int 
         for (int f = 0; f < n_fields; ++f) out[(size_t)f * n + p] = __builtin_nan("");
 }
 
+// k_eval_bin over a list of found points (grid-stride; the loop bound is
+// uniform per wavefront, as wave_inc needs)
+__global__ __launch_bounds__(256) void k_eval_bin_list(int pass, const int *list,
+                                                      const int *count, int nel,
+                                                      const int32_t *elem, int *elem_cnt,
+                                                      const int *elem_off, int *rank,
+                                                      int *sorted)
+{
+    const int cnt = *count;
+    const int lane = threadIdx.x & 63;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i - lane < cnt;
+         i += gridDim.x * blockDim.x) {
+        const bool act = i < cnt;
+        const int p = act ? list[i] : 0;
+        const int e = act ? elem[p] : -1;
+        const bool ok = act && e >= 0 && e < nel;
+        if (pass == 0) {
+            const int k = wave_inc(elem_cnt, e, ok);
+            if (act) rank[i] = ok ? k : -1;
+        } else if (ok && rank[i] >= 0) {
+            sorted[elem_off[e] + rank[i]] = p;
+        }
+    }
+}
+
 template <int N>
 __device__ __forceinline__ void basis_v(double r, const double *z, const double *w, double (&v)[N])
 {
@@ -560,6 +585,18 @@ EvalFn pick_eval_r(int R, int N)
 }
 
 }  // namespace
+
+hipError_t launch_eval_bin_list(const fpts_mesh *m, int pass, const int *list, const int *count,
+                                int64_t cap, const int32_t *elem, int *elem_cnt,
+                                const int *elem_off, int *rank, int *sorted, hipStream_t s)
+{
+    if (cap <= 0) return hipSuccess;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((cap + 255) / 256,
+                                                                 (int64_t)m->cus * 16));
+    hipLaunchKernelGGL(k_eval_bin_list, dim3(grid), dim3(256), 0, s, pass, list, count,
+                       (int)m->nel, elem, elem_cnt, elem_off, rank, sorted);
+    return hipGetLastError();
+}
 
 hipError_t launch_eval_bin(const fpts_mesh *m, int pass, int64_t n, const int32_t *code,
                            const int32_t *elem, const double *r, const int2 *cand,

@@ -495,13 +495,17 @@ __global__ __launch_bounds__(256) void k_primary_scatter_bins(int n, const int *
 // interior (it would overlap the primary), so the paper's rule -- first
 // INTERIOR candidate in ascending id order -- picks the same element.
 
-__device__ inline bool settled(int nc, int32_t cd, const double (&rr)[3], int R)
+__device__ inline bool deep_interior(int32_t cd, const double (&rr)[3], int R)
 {
-    if (nc <= 1) return true;
     if (cd != FPTS_INTERIOR) return false;
     double m = 1.0;
     for (int a = 0; a < R; ++a) m = fmin(m, 1.0 - fabs(rr[a]));
     return m > kSettleGuard;
+}
+
+__device__ inline bool settled(int nc, int32_t cd, const double (&rr)[3], int R)
+{
+    return nc <= 1 || deep_interior(cd, rr, R);
 }
 
 // Phase D, marking: every point whose primary result leaves the search open
@@ -516,21 +520,41 @@ __device__ inline bool settled(int nc, int32_t cd, const double (&rr)[3], int R)
 // issued at once.
 constexpr int kMarkChunk = 4096;
 
+// With rest.list (fused find + interpolate, volume and surface meshes) the
+// same pass also lists the points the interpolation over the primary list
+// leaves out -- found, but not INTERIOR at least kSettleGuard inside by the
+// primary result (the listed points among them) -- and writes NaN to the
+// interpolated values of NOT_FOUND points, so that the interpolation needs
+// no pass over all points of its own.
+__device__ inline void list_append(bool take, int p, int lane, int *lst, int &lcnt)
+{
+    const unsigned long long m = __ballot(take);
+    if (m) {
+        int at = 0;
+        if (lane == 0) at = atomicAdd(&lcnt, __popcll(m));
+        at = __shfl(at, 0, 64);
+        if (take) lst[at + __popcll(m & ((1ull << lane) - 1))] = p;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_unsettled(int n, int R, const int *cellpt,
                                                   const int2 *cand,
                                                   const int32_t *code, const double *r,
-                                                  int *ulist, int *ucount)
+                                                  int *ulist, int *ucount, EvalRest rest)
 {
-    __shared__ int lst[kMarkChunk];
-    __shared__ int lcnt, gbase;
+    __shared__ int lst[kMarkChunk], elst[kMarkChunk];
+    __shared__ int lcnt, ecnt, gbase, ebase;
     const int lane = threadIdx.x & 63;
-    if (threadIdx.x == 0) lcnt = 0;
+    if (threadIdx.x == 0) {
+        lcnt = 0;
+        ecnt = 0;
+    }
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kMarkChunk;
     for (int it = 0; it < kMarkChunk / 256; ++it) {
         const int64_t q = base + it * 256 + threadIdx.x;
         const int p = (int)q;
-        bool todo = false;
+        bool todo = false, other = false;
         if (q < n) {
             const int c = cellpt[p];
             const int2 cd2 = cand[p];
@@ -541,21 +565,26 @@ __global__ __launch_bounds__(256) void k_unsettled(int n, int R, const int *cell
             for (int a = 0; a < 3; ++a)
                 if (a < R) rr[a] = r[(size_t)a * n + p];
             todo = c >= 0 && prim >= 0 && !settled(nc, cd, rr, R);
+            if (rest.list) {
+                const bool found = cd != FPTS_NOT_FOUND;
+                other = found && !deep_interior(cd, rr, R);
+                if (!found)
+                    for (int f = 0; f < rest.n_fields; ++f)
+                        rest.out[(size_t)f * n + p] = __builtin_nan("");
+            }
         }
-        const unsigned long long m = __ballot(todo);
-        if (m) {
-            int at = 0;
-            if (lane == 0) at = atomicAdd(&lcnt, __popcll(m));
-            at = __shfl(at, 0, 64);
-            if (todo) lst[at + __popcll(m & ((1ull << lane) - 1))] = p;
-        }
+        list_append(todo, p, lane, lst, lcnt);
+        if (rest.list) list_append(other, p, lane, elst, ecnt);
     }
     __syncthreads();
-    const int cnt = lcnt;
-    if (cnt == 0) return;
-    if (threadIdx.x == 0) gbase = atomicAdd(ucount, cnt);
+    const int cnt = lcnt, ec = ecnt;
+    if (threadIdx.x == 0) {
+        if (cnt) gbase = atomicAdd(ucount, cnt);
+        if (ec) ebase = atomicAdd(rest.count, ec);
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < cnt; i += 256) ulist[gbase + i] = lst[i];
+    for (int i = threadIdx.x; i < ec; i += 256) rest.list[ebase + i] = elst[i];
 }
 
 // Exclusive prefix sum of v over the lanes of a wavefront; total = the sum.
@@ -919,11 +948,11 @@ hipError_t launch_primary_scatter(int64_t n, int64_t nel, const int2 *cand,
 
 hipError_t launch_unsettled(const fpts_mesh *m, int64_t n, const int *cellpt, const int2 *cand,
                             const int32_t *code, const double *r, int *ulist,
-                            int *ucount, hipStream_t s)
+                            int *ucount, const EvalRest &rest, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_unsettled, dim3(grid_for(n, kMarkChunk)), dim3(256), 0, s, (int)n, m->R,
-                       cellpt, cand, code, r, ulist, ucount);
+                       cellpt, cand, code, r, ulist, ucount, rest);
     return hipGetLastError();
 }
 
