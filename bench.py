@@ -503,6 +503,8 @@ def main():
         # counters of the last find (the iteration counts are deterministic)
         stats = gm.find_stats(newton_pass=1)
         stats_all = gm.find_stats()
+        stats_other = gm.find_stats(newton_pass=2)
+        stats_face = gm.find_stats(newton_pass=3)
         codes = torch.bincount(out["code"].long(), minlength=3).cpu().tolist()
         # the sample the oracle checks: the first points of the batch
         ns = min(args.cpu_sample, n)
@@ -512,8 +514,10 @@ def main():
         newton_ms = kt["newton_ms"] / max(kt["find_calls"], 1)
         fl = newton_flops(stats, D, R, N)
         results[mode] = dict(ms_per_step=ms, mpts=n / (dt / args.steps) / 1e6, kt=kt,
-                             newton_ms=newton_ms, stats=stats, stats_all=stats_all, flops=fl,
+                             newton_ms=newton_ms, stats=stats, stats_all=stats_all,
+                             stats_other=stats_other, stats_face=stats_face, flops=fl,
                              codes=codes, snap=snap, snap_u=snap_u)
+        log("%s: other candidates %s  face %s" % (mode, stats_other, stats_face))
         log("%s: %.3f ms/step  %.1f Mpts/s  k_newton %.3f ms (%.1f TFLOP/s)  face %.3f  "
             "nearest %.3f locate %.3f select %.3f eval_bin %.3f eval %.3f ms/call  codes %s  "
             "slots %s  stats %s" % (
@@ -587,7 +591,8 @@ def main():
                          ("locate", "nearest", "newton", "face", "select") else "eval_calls"], 1), 4)
                          for k in ("locate", "nearest", "newton", "face", "select", "eval_bin",
                                    "eval")}
-    line["newton_stats"] = {"primary": r0["stats"], "all": r0["stats_all"]}
+    line["newton_stats"] = {"primary": r0["stats"], "other_candidates": r0["stats_other"],
+                            "face": r0["stats_face"], "all": r0["stats_all"]}
     line["separate_calls"] = {"value": round(n / dt_sep / 1e6, 3), "unit": "Mpts/s",
                               "ms_per_step": round(dt_sep * 1e3, 4),
                               "calls": "fpts_find then fpts_eval"}

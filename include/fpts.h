@@ -249,6 +249,12 @@ typedef struct fpts_find_stats {
                                  is a GLL node, taken from the element's
                                  nodes and differentiation matrix rows
                                  without a sweep */
+    int64_t parked_pairs;   /* primary pairs that reached a face in the FP64
+                               primary kernel and went on in the face kernel
+                               (any pass) */
+    int64_t listed_points;  /* points left open by their primary result
+                               whose other candidates were searched (any
+                               pass) */
 } fpts_find_stats;
 
 int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws,

@@ -642,6 +642,8 @@ int fpts_find_stats_get(const fpts_mesh *m, int64_t n, const void *d_ws, int pas
         for (int q = 0; q < 3; ++q)
             if (pass == 0 || pass == q + 1) v[k] += all[q * kStats + k];
     out->overflow_points = ctr[kOverflowCount];
+    out->parked_pairs = ctr[kParkCount];
+    out->listed_points = ctr[0];
     out->pairs = (int64_t)v[0];
     out->passes = (int64_t)v[1];
     out->evals = (int64_t)v[2];

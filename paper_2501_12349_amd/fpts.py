@@ -50,7 +50,8 @@ class FindStats(ctypes.Structure):
                 ("passes_fp32", ctypes.c_int64), ("evals_fp32", ctypes.c_int64),
                 ("evals_h2_exec", ctypes.c_int64), ("sweeps", ctypes.c_int64),
                 ("sweeps_h2", ctypes.c_int64), ("sweeps_fp32", ctypes.c_int64),
-                ("overflow_points", ctypes.c_int64), ("evals_fp32_node", ctypes.c_int64)]
+                ("overflow_points", ctypes.c_int64), ("evals_fp32_node", ctypes.c_int64),
+                ("parked_pairs", ctypes.c_int64), ("listed_points", ctypes.c_int64)]
 
 
 class KernelTimes(ctypes.Structure):

@@ -95,7 +95,7 @@ def traffic(fetch_csv, write_csv):
     return out, fr, fw
 
 
-def sq_counters(paths, match=("k_newton", "k_nearest")):
+def sq_counters(paths, match=("k_newton", "k_nearest", "k_locate", "k_bin_", "k_eval")):
     """kernel -> {counter: value per dispatch} over the --pmc runs."""
     agg = OrderedDict()
     for path in paths:
