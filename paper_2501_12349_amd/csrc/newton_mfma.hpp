@@ -1565,6 +1565,54 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
     }
 }
 
+// Nearest node of x among the element's nodes staged in LDS (FP64, NodeLds
+// layout): the squared distance summed over the coordinates in order, the
+// lowest node index among equal distances (Section 3.2.1 starts Newton
+// there).  Wave-cooperative: each lane scans every 64th node, then the
+// lanes are reduced; every lane returns the index.
+template <int D, int R, int N>
+__device__ __forceinline__ int nearest_staged(const double *xl, const double (&x)[D], int lane)
+{
+    double bd = __builtin_huge_val();
+    int bi = 0;
+    for (int j = lane; j < Shape<D, R, N>::NP; j += kWave) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            const double t = x[d] - xl[NodeLds<double, D, R, N>::at(d, j / N, j % N)];
+            d2 = fma(t, t, d2);
+        }
+        if (d2 < bd) {
+            bd = d2;
+            bi = j;
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const double od = __shfl_xor(bd, o);
+        const int oi = __shfl_xor(bi, o);
+        if (od < bd || (od == bd && oi < bi)) {
+            bd = od;
+            bi = oi;
+        }
+    }
+    return bi;
+}
+
+// Reference coordinate k of node `node` (packed index i + N j + N^2 l): the
+// GLL point of its k-th index.
+template <int N>
+__device__ __forceinline__ double node_coord(int node, int k)
+{
+    constexpr gll::Table<N> GT = gll::Nodes<N>::t;
+    const int ik = k == 0 ? node % N : k == 1 ? (node / N) % N : node / (N * N);
+    double v = GT.z[0];
+#pragma unroll
+    for (int m = 1; m < N; ++m)
+        if (ik == m) v = GT.z[m];
+    return v;
+}
+
 // Newton over the element queue in precision T: one wave per element (task
 // counter io.counter[8] for the FP64 kernel, [9] for the FP32 phase of mixed
 // mode), over the elements that have pairs.  The start of every pair is
@@ -1575,6 +1623,10 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
 // scattered over many elements; a counter would be stepped once per element
 // of the mesh, mostly past empty queues, one same-address atomic after the
 // other.  The parked pairs of the face kernel are likewise spread thinly.
+// kResolve finds the starts of its pairs itself, from the nodes it stages
+// anyway: a separate nearest-node pass would read every such element's
+// node data once more for about one pair each, and score that pair on
+// matrix tiles of 16.
 template <typename T, int D, int R, int N, bool TASKS, int KIND>
 __device__ __forceinline__ void newton_body(const NewtonArgs &a)
 {
@@ -1611,7 +1663,37 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &a)
         }
         __syncthreads();
         if constexpr (FINAL) {
+            // kResolve: lane l < q1 - q0 (at most kChunk = 64) loads pair
+            // q0 + l (slot id, point) before the nodes are staged
+            int it = 0;
+            double px[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) px[d] = 0.0;
+            if constexpr (KIND == kResolve) {
+                static_assert(kChunk <= kWave, "one lane per pair of a task");
+                if (lane < q1 - q0) {
+                    it = io.list[q0 + lane];
+                    const int p = io.slot_pt[it];
+#pragma unroll
+                    for (int d = 0; d < D; ++d) px[d] = point_coord<D>(a, p, d);
+                }
+            }
             stage_nodes<double, D, R, N>(xl, a.nodes + (size_t)e * D * S::NP, lane);
+            if constexpr (KIND == kResolve) {
+                for (int j = 0; j < q1 - q0; ++j) {
+                    double x[D];
+#pragma unroll
+                    for (int d = 0; d < D; ++d) x[d] = __shfl(px[d], j);
+                    const int bi = nearest_staged<D, R, N>(xl, x, lane);
+                    const int itj = __shfl(it, j);
+                    if (lane < R) io.r[(size_t)lane * io.ostride + itj] = node_coord<N>(bi, lane);
+                }
+                // the refill reads the starts back with loads that bypass
+                // L1; this wave's stores only have to be complete (a
+                // device-scope fence would also write back and invalidate
+                // the L2, once per task)
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            }
             run_element<double, D, R, N, true, KIND>(a, e, q0, q1, xl, tab, cache, citem, lane,
                                                      a.max_iter, a.tol, nullptr, cn);
         } else {
@@ -1634,20 +1716,14 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &a)
 }
 
 // The primary pass and the pass over the other candidates of unsettled
-// points run the same code under two kernel names, so that a kernel trace
-// reports them apart.
+// points run the same Newton code under two kernel names, so that a kernel
+// trace reports them apart (the latter finds its starts itself).
 // (at least three waves per SIMD: the register budget then stays within the
 // 256 VGPRs, and the compiler gives the MFMA results VGPRs, not AGPRs that
 // the selection would first have to copy out)
 template <int D, int R, int N, bool MIXED>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void
 k_nearest(NewtonArgs a)
-{
-    nearest_body<D, R, N, MIXED>(a);
-}
-template <int D, int R, int N, bool MIXED>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void
-k_nearest_resolve(NewtonArgs a)
 {
     nearest_body<D, R, N, MIXED>(a);
 }
@@ -1693,7 +1769,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 k_resolve_overflow(NewtonArgs a, HashView h)
 {
     typedef Shape<D, R, N> S;
-    constexpr gll::Table<N> GT = gll::Nodes<N>::t;
     extern __shared__ double lds_raw[];
     int *citem = Lds<double, D, R, N>::citem(lds_raw);
     double *xl = lds_raw;
@@ -1739,40 +1814,10 @@ k_resolve_overflow(NewtonArgs a, HashView h)
                 continue;
             __syncthreads();
             stage_nodes<double, D, R, N>(xl, a.nodes + (size_t)e * D * S::NP, lane);
-            // nearest node: squared distance, lowest index among equals
-            double bd = __builtin_huge_val();
-            int bi = 0;
-            for (int j = lane; j < S::NP; j += kWave) {
-                double d2 = 0.0;
-#pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const double t = x[d] - xl[NodeLds<double, D, R, N>::at(d, j / N, j % N)];
-                    d2 = fma(t, t, d2);
-                }
-                if (d2 < bd) {
-                    bd = d2;
-                    bi = j;
-                }
-            }
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const double od = __shfl_xor(bd, o);
-                const int oi = __shfl_xor(bi, o);
-                if (od < bd || (od == bd && oi < bi)) {
-                    bd = od;
-                    bi = oi;
-                }
-            }
+            const int bi = nearest_staged<D, R, N>(xl, x, lane);
             if (lane == 0) {
-                const int ii[3] = {bi % N, (bi / N) % N, bi / (N * N)};
 #pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    double v = GT.z[0];
-#pragma unroll
-                    for (int m = 1; m < N; ++m)
-                        if (ii[k] == m) v = GT.z[m];
-                    la.io.r[(size_t)k * G + b] = v;
-                }
+                for (int k = 0; k < R; ++k) la.io.r[(size_t)k * G + b] = node_coord<N>(bi, k);
             }
             // lane 0 wrote the queue entry and the start and reads them back
             // in the refill (same lane, program order)
@@ -1842,7 +1887,7 @@ Kernels pick_kernels(int N, bool resolve)
     Kernels k;
 #define FPTS_CASE(NN)                                                                       \
     case NN:                                                                                \
-        k.nearest = resolve ? k_nearest_resolve<D, R, NN, MIXED> : k_nearest<D, R, NN, MIXED>; \
+        k.nearest = resolve ? nullptr : k_nearest<D, R, NN, MIXED>;                          \
         k.newton = resolve ? k_newton_resolve<D, R, NN> : k_newton<D, R, NN>;               \
         k.face = k_newton_face<D, R, NN>;                                                   \
         k.overflow = k_resolve_overflow<D, R, NN>;                                          \
@@ -1872,7 +1917,8 @@ Kernels pick_kernels(int N, bool resolve)
 }
 
 // Launches on the caller's stream: nearest nodes (which & 1; task grid of
-// 64-pair tasks over io.chunk_off, io.task_elem), then Newton (which & 2; element
+// 64-pair tasks over io.chunk_off, io.task_elem; not for the *_resolve
+// kernels, which find them from the nodes they stage), then Newton (which & 2; element
 // tasks: in mixed mode the FP32 phase, counter io.counter[9], then the FP64
 // kernel, counter io.counter[8]); which & 4 runs the face kernel over the
 // parked pairs (io.list = park indices binned by element, io.elem_off /
@@ -1887,7 +1933,7 @@ hipError_t launch_newton_kind(const fpts_mesh *m, bool mixed, int64_t n, const d
     const bool resolve = io.slot_pt != nullptr;
     const Kernels k = mixed ? pick_kernels<D, R, true>(m->N, resolve)
                             : pick_kernels<D, R, false>(m->N, resolve);
-    if (!k.nearest || !k.newton) return hipErrorInvalidValue;
+    if ((!k.nearest && !resolve) || !k.newton) return hipErrorInvalidValue;
     NewtonArgs a;
     a.nodes = m->d_nodes;
     a.nodes32 = m->d_nodes32;
@@ -1903,7 +1949,8 @@ hipError_t launch_newton_kind(const fpts_mesh *m, bool mixed, int64_t n, const d
     a.eps_d = m->p.surf_eps_d;
     a.max_iter32 = m->p.mixed_max_iter;
     a.tol32 = (float)m->p.mixed_tol;
-    if (which & 1) {
+    // the other candidates' Newton kernel finds their starts itself
+    if ((which & 1) && !resolve) {
         hipLaunchKernelGGL(k.nearest, dim3(task_grid(io.task_bound, m->cus)), dim3(64),
                            k.lds_nearest, s, a);
         const hipError_t e = hipGetLastError();
