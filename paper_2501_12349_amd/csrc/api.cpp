@@ -192,6 +192,10 @@ FindWs find_ws_layout(const fpts_mesh *m, int64_t n)
     // parked pairs of the primary pass (at most one per point)
     w.park_meta = c.take(sizeof(int4) * n);
     w.park_r = c.take(sizeof(double) * (m->R + 1) * n);
+    // saved iteration states: a few per cent of the pairs park on volume
+    // meshes; those beyond the capacity are re-evaluated by the face kernel
+    w.park_state_cap = std::min<int64_t>(n, n / 8 + 1024);
+    w.park_state = c.take(sizeof(double) * kParkState * w.park_state_cap);
     w.park_cnt = c.take(I * m->nel);
     w.park_off = c.take(I * (m->nel + 1));
     w.park_choff = c.take(I * (m->nel + 1));
@@ -283,6 +287,7 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
     double *start = at<double>(d_ws, w.start);
     int4 *park_meta = at<int4>(d_ws, w.park_meta);
     double *park_r = at<double>(d_ws, w.park_r);
+    double *park_state = at<double>(d_ws, w.park_state);
     int *park_cnt = at<int>(d_ws, w.park_cnt), *park_off = at<int>(d_ws, w.park_off);
     int *park_choff = at<int>(d_ws, w.park_choff), *park_rank = at<int>(d_ws, w.park_rank);
     int *park_sorted = at<int>(d_ws, w.park_sorted), *park_task = at<int>(d_ws, w.park_task);
@@ -348,6 +353,8 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
             io.park_r = park_r;
             io.park_cap = n;
             io.park_count = counters + kParkCount;
+            io.park_state = park_state;
+            io.park_state_cap = w.park_state_cap;
             io.polish = precision == FPTS_MIXED && m->R == m->D;
         }
         {
@@ -374,6 +381,8 @@ int find_impl(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code, int
             fio.park_meta = park_meta;
             fio.park_r = park_r;
             fio.park_cap = n;
+            fio.park_state = park_state;
+            fio.park_state_cap = w.park_state_cap;
             chk(launch_newton(m, FPTS_FP64, n, d_pts, fio, 4, s));
         }
     }

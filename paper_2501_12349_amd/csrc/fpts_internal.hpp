@@ -176,12 +176,13 @@ struct FindWs {
         elem_cnt, elem_off, chunk_off, sorted, ulist, uoff, ucnt, elem_cnt2, elem_fill2,
         elem_off2, chunk_off2, slot_pt, slot_elem, sorted2, res_r, res_dist, res_code,
         task_cell, task_elem, task_elem2, scan_tmp, counters, stats, pts4, start, park_meta,
-        park_r, park_cnt, park_off, park_choff, park_rank, park_sorted, park_task, olist, ov_int,
-        ov_dbl, bin_hist, bin_pairs, total;
+        park_r, park_state, park_cnt, park_off, park_choff, park_rank, park_sorted, park_task,
+        olist, ov_int, ov_dbl, bin_hist, bin_pairs, total;
     int64_t cap2;           // capacity for second-pass (point, candidate) pairs
     int64_t scan_blocks;
     int64_t ncell;
     int64_t tb_cell, tb_elem, tb_elem2, tb_park;   // task bounds
+    int64_t park_state_cap;  // parked pairs whose iteration state is saved
     int64_t ov_grid;        // blocks of the overflow search (its scratch)
     int bin_shift;          // phase A without per-point atomics: bucket shift, or -1
     int64_t bin_hist_n;     // entries of its bucket histograms (nb * ntile)
@@ -238,6 +239,12 @@ struct NewtonIO {
     double *park_r;
     int64_t park_cap;
     int *park_count;
+    // optional: the iteration state at r of parked pair k < park_state_cap,
+    // park_state[k * kParkState + j] (j: f, g[R], the Gauss-Newton Hessian
+    // [kSym<R>], dx[D]), so that the face kernel resumes without evaluating
+    // the map at r again; pairs parked beyond the capacity are re-evaluated
+    double *park_state;
+    int64_t park_state_cap;
     // mixed mode, FP64 phase of a volume mesh: when the first FP64 Newton
     // step from the FP32 result is below kPolishTol and off the faces, that
     // step ends the iteration (one FP64 evaluation per pair)
@@ -257,6 +264,10 @@ struct NewtonIO {
 // the solution one step leaves an error of order kappa * 1e-12, kappa the
 // element map's relative curvature (<< 1 for elements of a valid mesh).
 constexpr double kPolishTol = 1e-6;
+
+// Doubles per saved park state (at most 1 + 3 + 6 + 3 used), one 128-byte
+// record per parked pair.
+constexpr int kParkState = 16;
 
 }  // namespace fpts
 

@@ -913,6 +913,19 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                         const int4 mt = io.park_meta[item];
                         pass = mt.w;
                         alpha = T(io.park_r[(size_t)R * io.park_cap + item]);
+                        if (item < io.park_state_cap) {
+                            // with the state the evaluation at r left: the
+                            // pair waits for its second derivatives at once
+                            const double *ps = io.park_state + (size_t)item * kParkState;
+                            cur.f = T(ps[0]);
+#pragma unroll
+                            for (int j = 0; j < R; ++j) cur.g[j] = T(ps[1 + j]);
+#pragma unroll
+                            for (int j = 0; j < kSym<R>; ++j) cur.Hgn[j] = T(ps[1 + R + j]);
+#pragma unroll
+                            for (int c = 0; c < D; ++c) dx[c] = T(ps[1 + R + kSym<R> + c]);
+                            state = S_WAIT;
+                        }
                         item = mt.x;
                         pos = mt.y;
                     } else if (leader && FINAL) {
@@ -1121,6 +1134,20 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                             for (int j = 0; j < R; ++j)
                                 io.park_r[(size_t)j * io.park_cap + k] = (double)r[j];
                             io.park_r[(size_t)R * io.park_cap + k] = (double)alpha;
+                            static_assert(1 + R + kSym<R> + D <= kParkState, "park state");
+                            if (k < io.park_state_cap) {
+                                // the state at r, as the evaluation there left it
+                                double *ps = io.park_state + (size_t)k * kParkState;
+                                ps[0] = (double)cur.f;
+#pragma unroll
+                                for (int j = 0; j < R; ++j) ps[1 + j] = (double)cur.g[j];
+#pragma unroll
+                                for (int j = 0; j < kSym<R>; ++j)
+                                    ps[1 + R + j] = (double)cur.Hgn[j];
+#pragma unroll
+                                for (int c = 0; c < D; ++c)
+                                    ps[1 + R + kSym<R> + c] = (double)dx[c];
+                            }
                         }
                         state = S_FREE;
                     }
