@@ -1494,20 +1494,42 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
                     best[pt][qq] = __builtin_huge_val();
                 }
             }
-#pragma unroll 2
-            for (int nt = 0; nt < NT; ++nt) {
-                if (nt == NT / 2 && more) coords_of(cntn, itemn, pxn);   // next task, level 3
-                const double bv = a.near[((size_t)e * 4 + g) * L::NPAD + 16 * nt + col];
-                const int node = 16 * nt + col;
+            // One loop per pair-tile count, free of branches, so that the
+            // tiles' MFMAs issue back to back and each result is taken up
+            // after the others are issued; each lane's B values are loaded
+            // two node tiles ahead (NT >= 2 and even).
+            const double *brow = a.near + ((size_t)e * 4 + g) * L::NPAD + col;
+            auto scan = [&](auto tiles) __attribute__((always_inline)) {
+                constexpr int NTL = decltype(tiles)::value;
+                auto tile = [&](int nt, double bv) __attribute__((always_inline)) {
+                    if (nt == NT / 2 && more) coords_of(cntn, itemn, pxn);   // next task, level 3
+                    const int node = 16 * nt + col;
+                    v4 d[NTL];
 #pragma unroll
-                for (int pt = 0; pt < 4; ++pt) {
-                    if (pt < ntile) {
-                        const v4 d = mfma16(av[pt], bv, seed[pt]);
+                    for (int pt = 0; pt < NTL; ++pt) d[pt] = mfma16(av[pt], bv, seed[pt]);
+#pragma unroll
+                    for (int pt = 0; pt < NTL; ++pt)
 #pragma unroll
                         for (int qq = 0; qq < 4; ++qq)
-                            best[pt][qq] = key_min(best[pt][qq], with_node(d[qq], node));
+                            best[pt][qq] = key_min(best[pt][qq], with_node(d[pt][qq], node));
+                };
+                double b0 = brow[0], b1 = brow[16];
+#pragma unroll 1
+                for (int nt = 0; nt < NT; nt += 2) {
+                    const double c0 = b0, c1 = b1;
+                    if (nt + 2 < NT) {
+                        b0 = brow[16 * (nt + 2)];
+                        b1 = brow[16 * (nt + 3)];
                     }
+                    tile(nt, c0);
+                    tile(nt + 1, c1);
                 }
+            };
+            switch (ntile) {
+            case 1: scan(std::integral_constant<int, 1>()); break;
+            case 2: scan(std::integral_constant<int, 2>()); break;
+            case 3: scan(std::integral_constant<int, 3>()); break;
+            default: scan(std::integral_constant<int, 4>()); break;
             }
 #pragma unroll
             for (int pt = 0; pt < 4; ++pt) {
@@ -1539,24 +1561,33 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
                 }
             }
             // node tiles outside, pair tiles inside: each B value is read once
-            // per task and scores every pair tile
+            // per task and scores every pair tile; one branch-free loop per
+            // pair-tile count, the tiles' MFMAs issued back to back
+            auto scan = [&](auto tiles) __attribute__((always_inline)) {
+                constexpr int NTL = decltype(tiles)::value;
 #pragma unroll 2
-            for (int nt = 0; nt < NT; ++nt) {
-                if (nt == NT / 2 && more) coords_of(cntn, itemn, pxn);   // next task, level 3
-                const T bv = Bt[g * L::NPAD + 16 * nt + col];
-                const int node = 16 * nt + col;
+                for (int nt = 0; nt < NT; ++nt) {
+                    if (nt == NT / 2 && more) coords_of(cntn, itemn, pxn);   // next task, level 3
+                    const T bv = Bt[g * L::NPAD + 16 * nt + col];
+                    const int node = 16 * nt + col;
+                    v4 d[NTL];
 #pragma unroll
-                for (int pt = 0; pt < 4; ++pt) {
-                    if (pt < ntile) {
-                        const v4 d = mfma16(av[pt], bv, v4{0, 0, 0, 0});
+                    for (int pt = 0; pt < NTL; ++pt) d[pt] = mfma16(av[pt], bv, v4{0, 0, 0, 0});
+#pragma unroll
+                    for (int pt = 0; pt < NTL; ++pt)
 #pragma unroll
                         for (int qq = 0; qq < 4; ++qq) {
-                            const bool lt = d[qq] < best[pt][qq];
+                            const bool lt = d[pt][qq] < best[pt][qq];
                             bix[pt][qq] = lt ? node : bix[pt][qq];
-                            best[pt][qq] = lt ? d[qq] : best[pt][qq];
+                            best[pt][qq] = lt ? d[pt][qq] : best[pt][qq];
                         }
-                    }
                 }
+            };
+            switch (ntile) {
+            case 1: scan(std::integral_constant<int, 1>()); break;
+            case 2: scan(std::integral_constant<int, 2>()); break;
+            case 3: scan(std::integral_constant<int, 3>()); break;
+            default: scan(std::integral_constant<int, 4>()); break;
             }
 #pragma unroll
             for (int pt = 0; pt < 4; ++pt) {
