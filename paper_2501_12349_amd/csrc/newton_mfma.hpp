@@ -1406,10 +1406,10 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
         cnt = min(io.elem_off[e + 1] - beg, kChunk);
     };
     auto pair_of = [&](int beg, int cnt) __attribute__((always_inline)) { return lane < cnt ? io.list[beg + lane] : 0; };
+    // (the primary pass only: its items are the points themselves)
     auto coords_of = [&](int cnt, int item, double (&x)[D]) __attribute__((always_inline)) {
-        const int p = io.slot_pt ? io.slot_pt[item] : item;
 #pragma unroll
-        for (int c = 0; c < D; ++c) x[c] = lane < cnt ? point_coord<D>(a, p, c) : 0.0;
+        for (int c = 0; c < D; ++c) x[c] = lane < cnt ? point_coord<D>(a, item, c) : 0.0;
     };
     int t = task_of_block();
     if (t >= total) return;
@@ -1496,8 +1496,10 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
             }
             // One loop per pair-tile count, free of branches, so that the
             // tiles' MFMAs issue back to back and each result is taken up
-            // after the others are issued; each lane's B values are loaded
-            // two node tiles ahead (NT >= 2 and even).
+            // after the others are issued.  Each lane's B values are loaded
+            // four node tiles ahead into four registers, each reloaded right
+            // after its tile's MFMAs have read it (no copy at the loop's back
+            // edge, which would wait for the load); NT is even, NT >= 2.
             const double *brow = a.near + ((size_t)e * 4 + g) * L::NPAD + col;
             auto scan = [&](auto tiles) __attribute__((always_inline)) {
                 constexpr int NTL = decltype(tiles)::value;
@@ -1513,16 +1515,38 @@ __device__ __forceinline__ void nearest_body(const NewtonArgs &a)
                         for (int qq = 0; qq < 4; ++qq)
                             best[pt][qq] = key_min(best[pt][qq], with_node(d[pt][qq], node));
                 };
-                double b0 = brow[0], b1 = brow[16];
+                constexpr int NT4 = NT & ~3;
+                double b0 = brow[0], b1 = brow[16], b2 = 0.0, b3 = 0.0;
+                if constexpr (NT > 2) {
+                    b2 = brow[32];
+                    b3 = brow[48];
+                }
+                // The reloads are unconditional (past the row's end they read
+                // its last tile again), so that the wait before each tile
+                // counts on the three loads issued after its own.  Their
+                // offsets pass through an empty asm statement: otherwise the
+                // compiler proves each reload equal to the next iteration's
+                // tile and loads it there, just before its use.
+                auto ahead = [&](int t) __attribute__((always_inline)) {
+                    int off = 16 * min(t, NT - 1);
+                    asm volatile("" : "+s"(off));
+                    return brow[off];
+                };
 #pragma unroll 1
-                for (int nt = 0; nt < NT; nt += 2) {
-                    const double c0 = b0, c1 = b1;
-                    if (nt + 2 < NT) {
-                        b0 = brow[16 * (nt + 2)];
-                        b1 = brow[16 * (nt + 3)];
-                    }
-                    tile(nt, c0);
-                    tile(nt + 1, c1);
+                for (int nt = 0; nt < NT4; nt += 4) {
+                    tile(nt, b0);
+                    b0 = ahead(nt + 4);
+                    tile(nt + 1, b1);
+                    b1 = ahead(nt + 5);
+                    tile(nt + 2, b2);
+                    b2 = ahead(nt + 6);
+                    tile(nt + 3, b3);
+                    b3 = ahead(nt + 7);
+                }
+                if constexpr (NT4 < NT) {
+                    // the last two tiles (NT = 2 mod 4), in b0 and b1
+                    tile(NT4, b0);
+                    tile(NT4 + 1, b1);
                 }
             };
             switch (ntile) {
