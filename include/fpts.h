@@ -70,7 +70,11 @@ typedef struct fpts_params {
                            quads) or 1 with dim 2 or 3 (line elements,
                            Section 2 eq. eq_x_tensor_surf; OBB frame by
                            Rodrigues' rotation, Section 4.2) */
-    int nodes_1d;       /* N = p + 1 GLL nodes per direction, 2..10 */
+    int nodes_1d;       /* N = p + 1 GLL nodes per direction, 2..10 (p <= 9,
+                           which covers every case of the paper; the Newton
+                           kernels hold an element's nodes in LDS, and a hex
+                           of N = 16 would need 96 KiB per wavefront);
+                           FPTS_EINVAL beyond */
     int hash_n;         /* N_L cells per direction of the local map; 0 picks
                            the smallest n with n^D >= n_elem (Section 3.1.3) */
     int64_t n_elem;     /* number of elements, >= 1 */
