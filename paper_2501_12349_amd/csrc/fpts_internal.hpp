@@ -135,15 +135,20 @@ __device__ __forceinline__ int wave_inc(int *ctr, int key, bool active)
     return out;
 }
 
-// Box filter of one element record (eq. eq_AABB_test, then eq. eq_OBB_test);
-// `depth` receives ||A(x - c)||_inf, the point's OBB depth (smaller =
-// deeper).  Inclusive tests.
+// Box filter of one element record: the AABB test (eq. eq_AABB_test,
+// inclusive) and the point's OBB depth ||A(x - c)||_inf (eq. eq_OBB_test:
+// inside when <= 1; smaller = deeper).
 template <int D, typename P>
-__device__ inline bool box_pass(P rec, const double *x, double &depth)
+__device__ inline bool aabb_in(P rec, const double *x)
 {
     bool in = true;
 #pragma unroll
     for (int d = 0; d < D; ++d) in = in && ((x[d] - rec[d]) * (rec[D + d] - x[d]) >= 0.0);
+    return in;
+}
+template <int D, typename P>
+__device__ inline double obb_depth(P rec, const double *x)
+{
     double y[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) y[d] = x[d] - rec[2 * D + d];
@@ -155,8 +160,15 @@ __device__ inline bool box_pass(P rec, const double *x, double &depth)
         for (int b = 0; b < D; ++b) t += rec[3 * D + a * D + b] * y[b];
         mx = fmax(mx, fabs(t));
     }
-    depth = mx;
-    return in && (mx <= 1.0);
+    return mx;
+}
+// Both tests; `depth` receives the OBB depth.
+template <int D, typename P>
+__device__ inline bool box_pass(P rec, const double *x, double &depth)
+{
+    const bool in = aabb_in<D>(rec, x);
+    depth = obb_depth<D>(rec, x);
+    return in && (depth <= 1.0);
 }
 
 // fused find + interpolate (list null otherwise): the points the pass over

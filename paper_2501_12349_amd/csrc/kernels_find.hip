@@ -428,13 +428,20 @@ __global__ __launch_bounds__(64) void k_locate_cells(HashView h, int n, int R, c
                     data_of(nxt, nxt.q0, pn, minen, xn, rvn);   // next task, level 3
                     l3 = true;
                 }
-                // candidate j's record, broadcast to scalar registers
+                // candidate j's record, broadcast to scalar registers: the
+                // AABB first; when no point of the wave lies inside it (a
+                // box that only grazes the cell) the OBB part is neither
+                // read nor tested
                 double rec[RS];
 #pragma unroll
-                for (int f = 0; f < RS; ++f) rec[f] = read_lane(rv[f % HR], j + 32 * (f / HR));
+                for (int f = 0; f < 2 * D; ++f) rec[f] = read_lane(rv[f % HR], j + 32 * (f / HR));
+                const bool in = has && aabb_in<D>(rec, x);
+                if (!__ballot(in)) continue;
+#pragma unroll
+                for (int f = 2 * D; f < RS; ++f) rec[f] = read_lane(rv[f % HR], j + 32 * (f / HR));
                 const int e = __builtin_amdgcn_readlane(mine, j);
-                double depth;
-                if (box_pass<D>(rec, x, depth)) {
+                const double depth = obb_depth<D>(rec, x);
+                if (in && depth <= 1.0) {
                     ++cnt;
                     if (depth < best) {
                         best = depth;
