@@ -837,30 +837,47 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                 cend = min(q1, head + kCache);
                 const int idx = cstart + lane;
                 if (lane < kCache && idx < cend) {
-                    // kFace: the list holds park indices; the point, the saved
-                    // iterate and the rest of the pair's state come from the
-                    // park record
+                    // The starts are read at the pair's list position
+                    // (io.start: issued at once, beside the chain list ->
+                    // point) or with its item (io.r; kFace: the list holds
+                    // park indices, and the point, the saved iterate and the
+                    // rest of the pair's state come from the park record).
+                    // Plain loads, as an earlier kernel wrote them -- except
+                    // in kResolve, whose wave wrote its starts moments ago
+                    // (agent-scope loads, which bypass L1).
+                    auto load_start = [&](const double *src) __attribute__((always_inline)) {
+                        if constexpr (KIND == kResolve)
+                            return __hip_atomic_load(src, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                        else
+                            return *src;
+                    };
+                    const bool by_pos = KIND != kFace && io.start != nullptr;
+                    double sv[R];
+#pragma unroll
+                    for (int k = 0; k < R; ++k)
+                        sv[k] = by_pos ? load_start(io.start + (size_t)k * io.start_stride + idx)
+                                       : 0.0;
                     const int it = io.list[idx];
                     int p;
                     if constexpr (KIND == kFace) p = io.park_meta[it].x;
                     else p = io.slot_pt ? io.slot_pt[it] : it;
+                    double pc[D];
+#pragma unroll
+                    for (int c = 0; c < D; ++c) pc[c] = point_coord<D>(a, p, c);
+                    if (!by_pos) {
+#pragma unroll
+                        for (int k = 0; k < R; ++k)
+                            sv[k] = load_start(KIND == kFace
+                                                   ? io.park_r + (size_t)k * io.park_cap + it
+                                                   : io.r + (size_t)k * io.ostride + it);
+                    }
                     citem[lane] = it;
 #pragma unroll
                     for (int c = 0; c < D; ++c)
-                        cache[c * kCache + lane] =
-                            T(point_coord<D>(a, p, c) - (shift ? shift[c] : 0.0));
-                    // agent-scope loads: in mixed mode the FP32 phase of this
-                    // wave stored these values moments ago
+                        cache[c * kCache + lane] = T(pc[c] - (shift ? shift[c] : 0.0));
 #pragma unroll
-                    for (int k = 0; k < R; ++k) {
-                        const double *src;
-                        if constexpr (KIND == kFace) src = io.park_r + (size_t)k * io.park_cap + it;
-                        else
-                            src = io.start ? io.start + (size_t)k * io.start_stride + idx
-                                           : io.r + (size_t)k * io.ostride + it;
-                        cache[(D + k) * kCache + lane] =
-                            T(__hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                    }
+                    for (int k = 0; k < R; ++k) cache[(D + k) * kCache + lane] = T(sv[k]);
                     // a start that is a GLL node (every nearest-node start): its
                     // packed index, so that the start is evaluated from the node
                     // block directly (kFace resumes from parked iterates)
