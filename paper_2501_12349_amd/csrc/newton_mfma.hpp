@@ -825,6 +825,54 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
     // slot waits for the next trip instead (the loop cost more there than
     // the idle slots, measured on hex48).
     constexpr int batches = (!FINAL || KIND == kPolish) ? 2 : 1;
+    // The pair ids, points and starts of a batch of the queue (lane l: list
+    // position b0 + l) are loaded into registers by fetch and written to the
+    // cache when the batch is staged.  The batches follow each other in
+    // list order, so where an element's queue spans many batches (the
+    // primary and polish passes) the next batch is fetched as soon as the
+    // current one is staged, and its loads complete behind the sweeps.
+    // The starts are read at the pair's list position (io.start: issued at
+    // once, beside the chain list -> point) or with its item (io.r; kFace:
+    // the list holds park indices, and the point, the saved iterate and the
+    // rest of the pair's state come from the park record).  Plain loads, as
+    // an earlier kernel wrote them -- except in kResolve, whose wave wrote
+    // its starts moments ago (agent-scope loads, which bypass L1).
+    constexpr bool kAhead = KIND == kPrimary || KIND == kPolish;
+    int nb_it = 0;
+    double nb_pc[D], nb_sv[R];
+    auto fetch = [&](int b0) __attribute__((always_inline)) {
+        auto load_start = [&](const double *src) __attribute__((always_inline)) {
+            if constexpr (KIND == kResolve)
+                return __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                return *src;
+        };
+        const int idx = b0 + lane;
+        nb_it = 0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) nb_pc[c] = 0.0;
+#pragma unroll
+        for (int k = 0; k < R; ++k) nb_sv[k] = 0.0;
+        if (lane < kCache && idx < q1) {
+            const bool by_pos = KIND != kFace && io.start != nullptr;
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+                if (by_pos) nb_sv[k] = load_start(io.start + (size_t)k * io.start_stride + idx);
+            nb_it = io.list[idx];
+            int p;
+            if constexpr (KIND == kFace) p = io.park_meta[nb_it].x;
+            else p = io.slot_pt ? io.slot_pt[nb_it] : nb_it;
+#pragma unroll
+            for (int c = 0; c < D; ++c) nb_pc[c] = point_coord<D>(a, p, c);
+            if (!by_pos) {
+#pragma unroll
+                for (int k = 0; k < R; ++k)
+                    nb_sv[k] = load_start(KIND == kFace ? io.park_r + (size_t)k * io.park_cap + nb_it
+                                                        : io.r + (size_t)k * io.ostride + nb_it);
+            }
+        }
+    };
+    if constexpr (kAhead) fetch(q0);
     auto refill = [&]() {
 #pragma unroll 1
         for (int round = 0; round < batches; ++round) {
@@ -832,52 +880,19 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
             const int nfree = __popcll(freem);
             if (!nfree || head >= q1) return;
             if (head >= cend) {
+                // the next batch starts where the staged one ended
                 wave_lds_sync();   // earlier reads of the cache come first
                 cstart = head;
                 cend = min(q1, head + kCache);
+                if constexpr (!kAhead) fetch(cstart);
                 const int idx = cstart + lane;
                 if (lane < kCache && idx < cend) {
-                    // The starts are read at the pair's list position
-                    // (io.start: issued at once, beside the chain list ->
-                    // point) or with its item (io.r; kFace: the list holds
-                    // park indices, and the point, the saved iterate and the
-                    // rest of the pair's state come from the park record).
-                    // Plain loads, as an earlier kernel wrote them -- except
-                    // in kResolve, whose wave wrote its starts moments ago
-                    // (agent-scope loads, which bypass L1).
-                    auto load_start = [&](const double *src) __attribute__((always_inline)) {
-                        if constexpr (KIND == kResolve)
-                            return __hip_atomic_load(src, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-                        else
-                            return *src;
-                    };
-                    const bool by_pos = KIND != kFace && io.start != nullptr;
-                    double sv[R];
-#pragma unroll
-                    for (int k = 0; k < R; ++k)
-                        sv[k] = by_pos ? load_start(io.start + (size_t)k * io.start_stride + idx)
-                                       : 0.0;
-                    const int it = io.list[idx];
-                    int p;
-                    if constexpr (KIND == kFace) p = io.park_meta[it].x;
-                    else p = io.slot_pt ? io.slot_pt[it] : it;
-                    double pc[D];
-#pragma unroll
-                    for (int c = 0; c < D; ++c) pc[c] = point_coord<D>(a, p, c);
-                    if (!by_pos) {
-#pragma unroll
-                        for (int k = 0; k < R; ++k)
-                            sv[k] = load_start(KIND == kFace
-                                                   ? io.park_r + (size_t)k * io.park_cap + it
-                                                   : io.r + (size_t)k * io.ostride + it);
-                    }
-                    citem[lane] = it;
+                    citem[lane] = nb_it;
 #pragma unroll
                     for (int c = 0; c < D; ++c)
-                        cache[c * kCache + lane] = T(pc[c] - (shift ? shift[c] : 0.0));
+                        cache[c * kCache + lane] = T(nb_pc[c] - (shift ? shift[c] : 0.0));
 #pragma unroll
-                    for (int k = 0; k < R; ++k) cache[(D + k) * kCache + lane] = T(sv[k]);
+                    for (int k = 0; k < R; ++k) cache[(D + k) * kCache + lane] = T(nb_sv[k]);
                     // a start that is a GLL node (every nearest-node start): its
                     // packed index, so that the start is evaluated from the node
                     // block directly (kFace resumes from parked iterates)
@@ -899,6 +914,8 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                     }
                     cnode[lane] = node;
                 }
+                if constexpr (kAhead)
+                    if (cend < q1) fetch(cend);
                 wave_lds_sync();
             }
             if (state == S_FREE) {
