@@ -774,11 +774,13 @@ struct Counters {
 // mode).  Each trip evaluates either sweep 1 at the slots' query points
 // (start points of new pairs, trial points of the others) or, when enough
 // slots wait for it, sweep 2 at the waiting slots' current points.
-template <typename T, int D, int R, int N, bool FINAL, int KIND>
+// stage(): stages the element's nodes in LDS (a no-op where the caller
+// staged them: kResolve, before it wrote the starts, and kFace).
+template <typename T, int D, int R, int N, bool FINAL, int KIND, typename Stage>
 __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, int q1,
                                             const T *xl, T *tab, T *cache, int *citem, int lane,
                                             int max_iter, T tol, const double *shift,
-                                            Counters &cn)
+                                            Counters &cn, Stage &&stage)
 {
     const int slot = lane & 15;
     const bool leader = lane < 16;
@@ -872,7 +874,12 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
             }
         }
     };
-    if constexpr (kAhead) fetch(q0);
+    // the primary and polish passes fetch the first batch before the nodes
+    // are staged, so that the two wait together (the face kernel would spill
+    // registers for it; kResolve writes its starts after staging)
+    constexpr bool kEarly = kAhead;
+    if constexpr (kEarly) fetch(q0);
+    stage();
     auto refill = [&]() {
 #pragma unroll 1
         for (int round = 0; round < batches; ++round) {
@@ -884,7 +891,9 @@ __device__ __forceinline__ void run_element(const NewtonArgs &a, int e, int q0, 
                 wave_lds_sync();   // earlier reads of the cache come first
                 cstart = head;
                 cend = min(q1, head + kCache);
-                if constexpr (!kAhead) fetch(cstart);
+                if constexpr (!kAhead) {
+                    if (!kEarly || cstart != q0) fetch(cstart);
+                }
                 const int idx = cstart + lane;
                 if (lane < kCache && idx < cend) {
                     citem[lane] = nb_it;
@@ -1757,6 +1766,7 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &a)
     T *cache = tab + 2 * Lds<T, D, R, N>::TAB;
     Counters cn;
     const int total = TASKS ? io.chunk_off[a.nel] : 0;
+    int ticket = -1;   // (lane 0) the element counter's value for the next element
     for (int t = TASKS ? task_of_block() : 0;; t += gridDim.x) {
         int e = 0, q0, q1;
         if constexpr (TASKS) {
@@ -1766,11 +1776,15 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &a)
             q1 = min(io.elem_off[e + 1], q0 + kChunk);
         } else {
             if (lane == 0) {
-                // next element with a non-empty queue
-                for (;;) {
-                    e = atomicAdd(io.counter + (FINAL ? 8 : 9), 1);
-                    if (e >= a.nel || io.elem_off[e + 1] > io.elem_off[e]) break;
-                }
+                // the element of the ticket taken before, or the next one with
+                // a non-empty queue; then the ticket for the wave's next
+                // element, taken now so that its atomic completes while this
+                // element is staged (every ticket below nel is processed by
+                // the wave that took it)
+                int *ctr = io.counter + (FINAL ? 8 : 9);
+                e = ticket < 0 ? atomicAdd(ctr, 1) : ticket;
+                while (e < a.nel && io.elem_off[e + 1] <= io.elem_off[e]) e = atomicAdd(ctr, 1);
+                ticket = e < a.nel ? atomicAdd(ctr, 1) : a.nel;
             }
             e = __builtin_amdgcn_readfirstlane(__shfl(e, 0));
             if (e >= a.nel) break;
@@ -1794,8 +1808,9 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &a)
                     for (int d = 0; d < D; ++d) px[d] = point_coord<D>(a, p, d);
                 }
             }
-            stage_nodes<double, D, R, N>(xl, a.nodes + (size_t)e * D * S::NP, lane);
+            const double *src = a.nodes + (size_t)e * D * S::NP;
             if constexpr (KIND == kResolve) {
+                stage_nodes<double, D, R, N>(xl, src, lane);
                 for (int j = 0; j < q1 - q0; ++j) {
                     double x[D];
 #pragma unroll
@@ -1809,14 +1824,26 @@ __device__ __forceinline__ void newton_body(const NewtonArgs &a)
                 // device-scope fence would also write back and invalidate
                 // the L2, once per task)
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                run_element<double, D, R, N, true, KIND>(a, e, q0, q1, xl, tab, cache, citem,
+                                                         lane, a.max_iter, a.tol, nullptr, cn,
+                                                         [] {});
+            } else if constexpr (KIND == kFace) {
+                stage_nodes<double, D, R, N>(xl, src, lane);
+                run_element<double, D, R, N, true, KIND>(a, e, q0, q1, xl, tab, cache, citem,
+                                                         lane, a.max_iter, a.tol, nullptr, cn,
+                                                         [] {});
+            } else {
+                // the primary and polish passes stage the nodes after their
+                // first batch of pairs has been fetched
+                run_element<double, D, R, N, true, KIND>(
+                    a, e, q0, q1, xl, tab, cache, citem, lane, a.max_iter, a.tol, nullptr, cn,
+                    [&] { stage_nodes<double, D, R, N>(xl, src, lane); });
             }
-            run_element<double, D, R, N, true, KIND>(a, e, q0, q1, xl, tab, cache, citem, lane,
-                                                     a.max_iter, a.tol, nullptr, cn);
         } else {
-            stage_nodes<float, D, R, N>(xl, a.nodes32 + (size_t)e * D * S::NP, lane);
-            run_element<float, D, R, N, false, KIND>(a, e, q0, q1, xl, tab, cache, citem, lane,
-                                                     a.max_iter32, a.tol32,
-                                                     a.xc + (size_t)e * D, cn);
+            const float *src = a.nodes32 + (size_t)e * D * S::NP;
+            run_element<float, D, R, N, false, KIND>(
+                a, e, q0, q1, xl, tab, cache, citem, lane, a.max_iter32, a.tol32,
+                a.xc + (size_t)e * D, cn, [&] { stage_nodes<float, D, R, N>(xl, src, lane); });
         }
     }
     unsigned long long v[11] = {cn.pairs,  cn.passes,        cn.evals,  cn.evals_h2,
@@ -1938,7 +1965,8 @@ k_resolve_overflow(NewtonArgs a, HashView h)
             // lane 0 wrote the queue entry and the start and reads them back
             // in the refill (same lane, program order)
             run_element<double, D, R, N, true, kResolve>(la, e, b, b + 1, xl, tab, cache, citem,
-                                                        lane, a.max_iter, a.tol, nullptr, cn);
+                                                        lane, a.max_iter, a.tol, nullptr, cn,
+                                                        [] {});
             // slot 0's leader (lane 0) wrote the result
             int cd = 0;
             double dd = 0.0, rr[R];
