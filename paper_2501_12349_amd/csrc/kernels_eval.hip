@@ -128,6 +128,9 @@ struct EvalArgs {
     // r comes from rs[k * n + list position]; NaN there skips the point
     const double *rs;
     int f0;                 // first field of this launch (k_eval_mfma)
+    // k_eval_mfma: walk the elements (every wave at most a few of them)
+    // instead of the task grid
+    int by_elem;
 };
 
 typedef const __attribute__((address_space(4))) double cdouble;
@@ -249,11 +252,15 @@ __global__ __launch_bounds__(64) void k_eval(EvalArgs a)
 // (hexes with N = 4, 8: summed over k first, then weighted per j), and the
 // four lanes of a slot are summed.  A point's value depends on its own
 // coordinates and element only, not on the group it lands in.
-// (four waves per SIMD: the register budget of 128 VGPRs holds the kernel
-// with one spilled lane id, and the MFMA results land in VGPRs, not in
-// AGPRs to copy out)
+// The wave walks the elements e, e + G, ... (G = grid size; each XCD a
+// contiguous range per round) and skips those without points; the fields
+// of its next element are loaded into registers while the current one is
+// contracted, and the bucket offsets of the one after are loaded then too,
+// so that an element's staging does not wait on memory.  (Two waves per
+// SIMD: the prefetched fields take 48 VGPRs; the LDS footprint, 15 KiB per
+// wave for three fields of N = 8, allowed at most ten waves per CU anyway.)
 template <int R, int N, int FC>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void
 k_eval_mfma(EvalArgs a)
 {
     typedef newton::Shape<3, R, N> S;
@@ -267,36 +274,34 @@ k_eval_mfma(EvalArgs a)
     double *xl = lds_eval;        // the FC fields, NodeLds layout
     double *tab = xl + L::SIZE;   // [R][N][16] bases of the group's points
     const int lane = threadIdx.x, slot = lane & 15, g = lane >> 4;
-    const int total = a.chunk_off[a.nel];
-    for (int t = task_of_block(); t < total; t += gridDim.x) {
-        const int e = __builtin_amdgcn_readfirstlane(a.task_elem[t]);
-        // the element's first task takes all its points, so that its fields
-        // are staged once (the other tasks of the element have nothing to do)
-        if (t != a.chunk_off[e]) continue;
-        // stage the element's FC fields (every load issued before the stores)
-        {
-            double v[FC][PER];
+    const int G = gridDim.x, nel = a.nel;
+    double v[FC][PER];
+    auto load_fields = [&](int en) __attribute__((always_inline)) {
 #pragma unroll
-            for (int f = 0; f < FC; ++f) {
-                const double *src = a.field + ((size_t)(a.f0 + f) * a.nel + e) * NP;
+        for (int f = 0; f < FC; ++f) {
+            const double *src = a.field + ((size_t)(a.f0 + f) * nel + en) * NP;
 #pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int j = lane + 64 * k;
-                    v[f][k] = (NP % 64 == 0 || j < NP) ? src[j] : 0.0;
-                }
+            for (int k = 0; k < PER; ++k) {
+                const int j = lane + 64 * k;
+                v[f][k] = (NP % 64 == 0 || j < NP) ? src[j] : 0.0;
             }
-            __syncthreads();   // the previous task's reads come first
-#pragma unroll
-            for (int f = 0; f < FC; ++f)
-#pragma unroll
-                for (int k = 0; k < PER; ++k) {
-                    const int j = lane + 64 * k;
-                    if (NP % 64 == 0 || j < NP) xl[L::at(f, j / N, j % N)] = v[f][k];
-                }
-            __syncthreads();
         }
-        const int eend = a.elem_off[e + 1];
-        for (int beg = a.elem_off[e]; beg < eend; beg += kChunk) {
+    };
+    // the element's FC fields, from v into LDS
+    auto stage_fields = [&]() __attribute__((always_inline)) {
+        __syncthreads();   // the previous element's reads come first
+#pragma unroll
+        for (int f = 0; f < FC; ++f)
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int j = lane + 64 * k;
+                if (NP % 64 == 0 || j < NP) xl[L::at(f, j / N, j % N)] = v[f][k];
+            }
+        __syncthreads();
+    };
+    // the points of the staged element: list positions [ebeg, eend)
+    auto points = [&](int ebeg, int eend) __attribute__((always_inline)) {
+        for (int beg = ebeg; beg < eend; beg += kChunk) {
         const int end = min(eend, beg + kChunk);
         const int idx = beg + lane;
         bool has = idx < end;
@@ -391,6 +396,59 @@ k_eval_mfma(EvalArgs a)
                 if (hp && g == f) a.out[(size_t)(a.f0 + f) * a.n + pp] = X[f];
         }
         }
+    };
+    if (!a.by_elem) {
+        // task grid: the element's first task takes all its points, so that
+        // its fields are staged once (its other tasks have nothing to do)
+        const int total = a.chunk_off[nel];
+        for (int t = task_of_block(); t < total; t += G) {
+            const int e = __builtin_amdgcn_readfirstlane(a.task_elem[t]);
+            if (t != a.chunk_off[e]) continue;
+            load_fields(e);
+            stage_fields();
+            points(a.elem_off[e], a.elem_off[e + 1]);
+        }
+        return;
+    }
+    // element walk: the wave's first element with points from e0 on, in
+    // steps of G (nel when none), its bucket range in o0, o1
+    auto busy_from = [&](int e0, int &o0, int &o1) __attribute__((always_inline)) {
+        int en = e0;
+        for (; en < nel; en += G) {
+            o0 = a.elem_off[en];
+            o1 = a.elem_off[en + 1];
+            if (o1 > o0) break;
+        }
+        return en;
+    };
+    int ebeg = 0, eend = 0;
+    int e = busy_from(task_of_block(), ebeg, eend);
+    if (e < nel) load_fields(e);
+    // offsets of the element after the next, loaded one element ahead
+    int nb = 0, nnb = 0;
+    int en = e + G;
+    if (en < nel) {
+        nb = a.elem_off[en];
+        nnb = a.elem_off[en + 1];
+    }
+    while (e < nel) {
+        stage_fields();   // fields loaded during the previous element
+        // the next element with points: en, whose offsets arrived meanwhile
+        // (past an empty one the search goes on from there)
+        if (en < nel && !(nnb > nb)) en = busy_from(en + G, nb, nnb);
+        const int n0 = nb, n1 = nnb;
+        if (en < nel) {
+            load_fields(en);
+            if (en + G < nel) {
+                nb = a.elem_off[en + G];
+                nnb = a.elem_off[en + G + 1];
+            }
+        }
+        points(ebeg, eend);
+        e = en;
+        ebeg = n0;
+        eend = n1;
+        en = e + G;
     }
 }
 
@@ -631,6 +689,9 @@ hipError_t launch_eval(const fpts_mesh *m, int64_t n, const double *r, int n_fie
     if (field_n == m->N) a.basis = m->basis;
     else gll::fill(field_n, a.basis.z, a.basis.w);
     const dim3 grid(task_grid(task_bound, m->cus));
+    // the matrix-core kernel walks the elements when every wave has at most
+    // eight of them to visit (many points); else it follows the task grid
+    a.by_elem = (int64_t)grid.x * 8 >= m->nel;
     if (m->R >= 2) {
         // matrix cores, up to three fields per launch
         for (int f0 = 0; f0 < n_fields; f0 += 3) {
