@@ -163,3 +163,28 @@ def test_second_search_overflow(precision):
     print(precision, rep, "overflow points", st["overflow_points"])
     assert st["overflow_points"] > 100
     assert (orc["code"] == oracle.BORDER).sum() > 1000
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_face_pairs_beyond_the_saved_states(precision):
+    """Points just outside the cube (offsets up to 2e-3, inside the boxes of
+    the boundary elements, whose map is the identity on the cube's faces):
+    the primary pair of nearly every point iterates to the boundary face,
+    needs second derivatives there and leaves the primary kernel's slots.
+    The park records keep the iteration state of the first n/8 + 1024 such
+    pairs only, so the face kernel resumes some pairs from their state and
+    re-evaluates the others, within the same waves.  Results as the
+    oracle's (BORDER at the offset's distance)."""
+    wl = W.hex16(n_in=0, n_out=0)
+    rng = np.random.default_rng(2024)
+    n = 60000
+    pts = rng.uniform(0.0, 1.0, size=(3, n))
+    axis = rng.integers(0, 3, size=n)
+    side = rng.integers(0, 2, size=n)
+    off = rng.uniform(1e-5, 2e-3, size=n)
+    pts[axis, np.arange(n)] = np.where(side == 1, 1.0 + off, -off)
+    rep, gm = _check(wl, pts, precision)
+    st = gm.find_stats()
+    cap = min(n, n // 8 + 1024)
+    print("parked", st["parked_pairs"], "saved states", cap)
+    assert st["parked_pairs"] > cap
