@@ -208,8 +208,9 @@ int fpts_find_eval(fpts_mesh *m, int64_t n, const double *d_pts, int32_t *d_code
  * bytes; its address is looked up when the first mesh is set up on that
  * device).  The call allocates nothing.  It returns FPTS_ENOMEM, without
  * doing anything, when fpts_find_eval_workspace_size(m, n) exceeds
- * FPTS_NOALLOC_SCRATCH_BYTES (about 250 bytes per point plus the
- * mesh-sized arrays: some 2.1 million points on a 48^3 mesh with N = 8).  Every call on one device shares that device's
+ * FPTS_NOALLOC_SCRATCH_BYTES (about 265 bytes per point plus the
+ * mesh-sized arrays: some 2.0 million points on a 48^3 mesh with N = 8).
+ * Every call on one device shares that device's
  * array: calls that overlap on one device -- on different streams, or
  * from different threads -- race and corrupt each other's results; they
  * must be ordered (one stream, or events).  The array keeps the last call's
