@@ -26,9 +26,12 @@
 //
 // Mixed precision: the FP32 phase runs every pair of the element on FP32
 // nodes stored as offsets from the element centre (points shifted the same
-// way in FP64 before rounding) to ||dr|| < 1e-6 or 10 passes; the FP64 phase
-// then restarts each pair from that r with alpha = 1.  Codes, distances and
-// the final residual come from the FP64 phase.
+// way in FP64 before rounding) until ||dr|| < mixed_tol (default 1e-3) or
+// mixed_max_iter passes; the FP64 phase then evaluates the map at that r
+// and takes one Newton step, which ends the iteration when it is at most
+// kPolishTol and off the faces (the polish step), else the iteration goes
+// on in FP64 from there with alpha = 1.  Codes, distances and the final
+// residual come from the FP64 phase.
 #pragma once
 #include <cfloat>
 #include <type_traits>
