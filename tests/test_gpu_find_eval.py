@@ -62,8 +62,14 @@ def test_field_of_another_order():
     _same(wl, "fp64", field_nodes_1d=4, field=field)
 
 
-def test_hex48_full_size():
-    _same(W.hex48(), "fp64")
+@pytest.fixture(scope="module")
+def hex48():
+    return W.hex48()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_hex48_full_size(hex48, precision):
+    _same(hex48, precision)
 
 
 def test_ragged_sizes_and_arguments():
