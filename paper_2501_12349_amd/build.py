@@ -23,7 +23,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-Wno-unused-command-line-argument",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
-SOURCES = ["kernels_newton_hex.hip", "kernels_newton_surf.hip", "kernels_newton_quad.hip",
+SOURCES = ["kernels_newton.hip",
            "kernels_newton_line.hip",
            "kernels_find.hip", "kernels_eval.hip", "setup_device.hip", "lpt.hip", "api.cpp", "setup.cpp",
            "serve.cpp"]

@@ -498,7 +498,8 @@ hipError_t launch_nodes32(const fpts_mesh *m, hipStream_t s);
 // padding columns j >= N^R score 1e300
 hipError_t launch_near_rows(const fpts_mesh *m, hipStream_t s);
 
-// Newton launchers per element kind (kernels_newton_*.hip)
+// Newton launchers per element kind (kernels_newton.hip; lines:
+// kernels_newton_line.hip)
 hipError_t launch_newton_hex(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,
                              const NewtonIO &io, int which, hipStream_t s);
 hipError_t launch_newton_quad(const fpts_mesh *m, bool mixed, int64_t n, const double *pts,

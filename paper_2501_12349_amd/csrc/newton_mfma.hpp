@@ -1,6 +1,7 @@
 // Trust-region Newton inversion of the element map (Section 3.2.1) for
 // (point, candidate element) pairs grouped by element, with the element-map
-// contraction on the matrix cores.  Shared by kernels_newton_*.hip.
+// contraction on the matrix cores.  Instantiated in kernels_newton.hip
+// (hex, quad and surface kinds); kernels_eval.hip shares its LDS layout.
 //
 // Task = one element and the queue of its pairs.  The wave stages the
 // element's nodal coordinates in LDS and serves 16 pairs at a time, one per

@@ -22,7 +22,7 @@ import sys
 from collections import OrderedDict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-NEWTON_SOURCES = ("csrc/newton_mfma.hpp", "csrc/kernels_newton_hex.hip")
+NEWTON_SOURCES = ("csrc/newton_mfma.hpp", "csrc/kernels_newton.hip")
 CALIB_BYTES = 1 << 30      # the --calib-copy copy
 TRAFFIC_TAG = "k_newton_traffic"
 
