@@ -1409,10 +1409,14 @@ struct NearLds {
 // kNodeBits mantissa bits; one minimum per score then keeps the nearest node
 // with ties (equal to 2^-42 relative) to the lowest index.
 constexpr int kNodeBits = 10;   // node indices below 1024 (N <= 10)
+// one bit-field insert (mask from a scalar register: no literal operands
+// here), in place in the low word; written out because the compiler would
+// fold the node index's own arithmetic into an AND and an OR per score
 __device__ __forceinline__ double with_node(double d, int node)
 {
-    constexpr unsigned m = (1u << kNodeBits) - 1;
-    const unsigned lo = ((unsigned)__double2loint(d) & ~m) | ((unsigned)node & m);   // v_bfi
+    const unsigned m = (1u << kNodeBits) - 1;
+    unsigned lo = (unsigned)__double2loint(d);
+    asm("v_bfi_b32 %0, %1, %2, %0" : "+v"(lo) : "s"(m), "v"(node));
     return __hiloint2double(__double2hiint(d), (int)lo);
 }
 // min of two keys: the keys are finite or +inf (never NaN), so the plain
